@@ -1,0 +1,26 @@
+"""Build the CPU oracle shared library (test infrastructure only).
+
+Plain gcc, -O2, no fast-math: the oracle's arithmetic is IEEE FP64 as written.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["rng.c", "sampler.c", "driver.c", "closed_form.c", "cv.c"]
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-pthread",
+           "-Wall", "-Wextra", "-Wno-unused-parameter", "-fno-fast-math",
+           "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))
