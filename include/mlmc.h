@@ -1,0 +1,195 @@
+/*
+ * mlmc.h -- C ABI of the MI355X (gfx950) multilevel Monte Carlo library.
+ *
+ * What it computes (D. J. Higham, "An Introduction to Multilevel Monte Carlo
+ * for Option Valuation"):
+ *   E[h(X(T))] for an Ito SDE dX = f(X) dt + g(X) dW (Sec. 2, eq. (eq:sde)),
+ *   discretised by Euler--Maruyama (eq. (eq:em)) on levels with step
+ *   dt_l = M^-l T (Sec. 5, eq. (eq:mlmc:Dtl)), estimated through the
+ *   telescoping sum E[P_L] = E[P_0] + sum_l E[P_l - P_{l-1}]
+ *   (eq. (eq:mlmc:ident)) with independent level estimators Yhat_l
+ *   (eqs. (eq:mlmc:Yzero), (eq:Yldef)) whose fine and coarse paths share one
+ *   Brownian path, the coarse increments being sums of M fine ones.
+ *
+ * Conventions for every entry point:
+ *   - returns an mlmc_status; 0 = success.  Nothing aborts or throws across
+ *     the ABI.  On failure a message is available from mlmc_last_error().
+ *   - structs and host arrays belong to the caller and are only read or
+ *     written during the call.  The context owns every device buffer it
+ *     allocates.  Arguments named d_* are caller-owned DEVICE pointers on the
+ *     context's device; all others are host pointers.
+ *   - a context is not thread-safe: use one per host thread.  Calls are
+ *     enqueued on the context's stream (mlmc_set_stream) and synchronise it
+ *     before returning results to host memory.
+ *   - random numbers: Philox4x32-10 keyed by the 64-bit seed; sample s of
+ *     level l is a pure function of (seed, l, s), so results do not depend on
+ *     the launch configuration except for the order of FP64 atomic additions
+ *     (relative differences of order 1e-16).
+ */
+#ifndef MLMC_H
+#define MLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MLMC_OK = 0,
+    MLMC_ENOTCONV = 1,    /* warning: L_max reached before the bias test
+                             passed; the estimate is still returned          */
+    MLMC_EINVAL = -1,     /* invalid argument                                */
+    MLMC_ENOMEM = -2,     /* device or host allocation failed                */
+    MLMC_EDEVICE = -3,    /* HIP runtime error                               */
+    MLMC_ENONFINITE = -4  /* some samples were not finite; they are counted
+                             in n_nonfinite and left out of the sums          */
+} mlmc_status;
+
+/* Models (eq. (eq:sde)); GBM is the model of Sec. 6. */
+typedef enum { MLMC_GBM = 0, MLMC_HESTON = 1 } mlmc_model_kind;
+/* Payoffs: European call (Sec. 5), arithmetic Asian and floating-strike
+ * lookback (named in Sec. 7.1), digital with the tie rule of Sec. 6. */
+typedef enum { MLMC_CALL = 0, MLMC_ASIAN = 1, MLMC_LOOKBACK = 2, MLMC_DIGITAL = 3 } mlmc_payoff_kind;
+
+typedef struct {
+    int kind;                       /* mlmc_model_kind */
+    double S0, r, sigma, T;         /* GBM: dS = r S dt + sigma S dW */
+    double kappa, theta, xi, rho, v0;
+    /* Heston: dS = r S dt + sqrt(v) S dW1, dv = kappa (theta - v) dt +
+     * xi sqrt(v) dW2, corr(dW1, dW2) = rho, v(0) = v0; stepped by
+     * full-truncation Euler (sigma unused).                               */
+} mlmc_model;
+
+typedef struct {
+    int kind;                       /* mlmc_payoff_kind */
+    double K;                       /* strike (unused by the lookback) */
+    double payout;                  /* digital cash amount (1 or 100) */
+    /* All payoffs are discounted by exp(-rT):
+     *   call     max(S_N - K, 0)
+     *   Asian    max(A - K, 0), A the trapezoid average over the path's grid
+     *   lookback S_N - min S with a Brownian-bridge minimum on every step
+     *   digital  payout if S_N > K, payout/2 if S_N == K, else 0          */
+} mlmc_payoff;
+
+/* Sums of one level's samples, eq. (eq:Yldef): Y = P_l - P_{l-1}
+ * (P_{-1} = 0), Pf = P_l (fine), Pc = P_{l-1} (coarse).
+ * cost = N * (M^l + M^(l-1)) path steps (N at l = 0), the paper's cost
+ * measure of Sec. 3.                                                        */
+typedef struct {
+    double sum_y, sum_y2, sum_pf, sum_pf2, sum_pc, sum_pc2;
+    double cost;
+    uint64_t n, n_nonfinite;
+} mlmc_level_result;
+
+typedef struct mlmc_ctx mlmc_ctx;
+typedef struct mlmc_cv mlmc_cv;
+
+/* Create a context on HIP device `device` (its own non-blocking stream).
+ * MLMC_EDEVICE if the device is absent or not gfx950.                      */
+mlmc_status mlmc_ctx_create(int device, mlmc_ctx** out);
+/* Frees every device buffer of the context; NULL is accepted. */
+mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx);
+/* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream()
+ * .cuda_stream) for all later work; NULL restores the context's own. */
+mlmc_status mlmc_set_stream(mlmc_ctx* ctx, void* hip_stream);
+/* Last error message of this context ("" if none); valid until the next call. */
+const char* mlmc_last_error(const mlmc_ctx* ctx);
+/* Fix the level kernel's launch shape: block in {64,128,256,512,1024},
+ * paths per thread ppt in {1,2,4}.  block = 0 returns to the tuned/default
+ * choice.  Results do not depend on it (see determinism above).            */
+mlmc_status mlmc_set_launch(mlmc_ctx* ctx, int block, int ppt);
+
+/* Level estimator sums (eqs. (eq:mlmc:Yzero), (eq:Yldef)).
+ *   l >= 0, M in {2, 4}, M^l <= 4^8 * 4 (262144 steps), N >= 0 paths
+ *   seed: Philox key; path_offset: index of the first sample, so further
+ *   calls extend the same sequence of independent samples;
+ *   precision: 32 (fp32 paths, fp64 sums) or 64 (fp64 throughout);
+ *   cv: learned control variate (NULL for plain MLMC; requires precision 32).
+ * Returns MLMC_ENONFINITE (sums still valid) if any Y was not finite.     */
+mlmc_status mlmc_level(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                       int l, int M, uint64_t N, uint64_t seed, uint64_t path_offset,
+                       int precision, const mlmc_cv* cv, mlmc_level_result* out);
+
+/* Same samples as mlmc_level, per path: d_pf[i] = P_l and d_pc[i] = P_{l-1}
+ * of sample path_offset + i, i < N (fp64 device arrays of N entries).
+ * For testing; out may be NULL.                                             */
+mlmc_status mlmc_level_paths(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                             int l, int M, uint64_t N, uint64_t seed, uint64_t path_offset,
+                             int precision, const mlmc_cv* cv, double* d_pf, double* d_pc,
+                             mlmc_level_result* out);
+
+/* Raw generator words as the sampler draws them: for paths s = s0 .. s0+npaths-1
+ * and blocks j < nblocks, d_out[(s - s0) * nblocks * 4 + 4 j + w] is word w of
+ * Philox4x32-10 at counter (j, s mod 2^32, level + 256 (s >> 32), stream) with
+ * key (seed mod 2^32, seed >> 32).  d_out: uint32 device array.            */
+mlmc_status mlmc_philox_words(mlmc_ctx* ctx, uint64_t seed, int level, uint64_t s0,
+                              uint32_t stream, uint32_t nblocks, uint64_t npaths,
+                              uint32_t* d_out);
+
+/* Standard normals as the sampler draws them (Box--Muller on word pairs),
+ * dim 1: d_out[(s - s0) * nsteps + n] = z_n; dim 2: two factors per step,
+ * d_out[(s - s0) * 2 nsteps + 2 n + f].  precision 32 or 64; fp64 output. */
+mlmc_status mlmc_normals(mlmc_ctx* ctx, uint64_t seed, int level, uint64_t s0, uint32_t stream,
+                         int dim, int nsteps, uint64_t npaths, int precision, double* d_out);
+
+/* Standard Monte Carlo comparator: sums of P_L alone (no coupling) over
+ * N samples from an independent stream (Sec. 3's estimator a_M).          */
+mlmc_status mlmc_stdmc(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                       int L, int M, uint64_t N, uint64_t seed, uint64_t path_offset,
+                       int precision, mlmc_level_result* out);
+
+/* ---------------------------------------------------------------- driver
+ * Sample counts N_l = ceil(2 eps^-2 sqrt(V_l/C_l) sum_k sqrt(V_k C_k)) for
+ * l = 0..L (the optimisation of Sec. 5's "Constructive Upper Bound" remark,
+ * with eps a root-mean-square error split evenly between bias^2 and
+ * variance), computed on the device in FP64.  V, C, N: host arrays of L+1. */
+mlmc_status mlmc_optimal_n(mlmc_ctx* ctx, int L, const double* V, const double* C, double eps,
+                           double* N);
+
+typedef struct {
+    double eps;          /* target root-mean-square error (absolute units)   */
+    int M;               /* refinement factor, 2 or 4                       */
+    int L_min, L_max;    /* 1 <= L_min <= L_max <= 12                       */
+    uint64_t n_pilot;    /* initial samples on each of levels 0..L_min      */
+    uint64_t seed;
+    int precision;       /* 32 or 64                                         */
+    int persistent;      /* 1: every iteration is one graph launch of the
+                            persistent all-levels kernel; 0: one launch per
+                            level                                             */
+    double alpha, beta;  /* assumed weak and variance rates (<= 0: 1 and 1) */
+    const mlmc_cv* cv;   /* NULL: plain MLMC                                 */
+} mlmc_run_opts;
+
+#define MLMC_MAX_LEVELS 16
+
+typedef struct {
+    double estimate;     /* sum_l Yhat_l */
+    double rmse_est;     /* sqrt(sum_l V_l/N_l + bias estimate^2)           */
+    double wall_s;       /* wall-clock seconds of the call                   */
+    int L, converged, iterations;
+    uint64_t N[MLMC_MAX_LEVELS];
+    double E[MLMC_MAX_LEVELS], V[MLMC_MAX_LEVELS], C[MLMC_MAX_LEVELS];
+    double sum_y[MLMC_MAX_LEVELS], sum_y2[MLMC_MAX_LEVELS];
+    double alpha, beta, gamma;   /* fitted rates of |E_l|, V_l, C_l (l >= 1) */
+    double cost;                 /* total path steps                         */
+    uint64_t n_nonfinite;
+} mlmc_run_result;
+
+/* Adaptive MLMC (Sec. 5 and its complexity theorem): starts with n_pilot
+ * samples on levels 0..L_min, then repeatedly (i) samples the outstanding
+ * dN_l, (ii) on the device, estimates E_l and V_l (for l >= 2 floored by
+ * E_{l-1} M^-alpha and V_{l-1} M^-beta), sets N_l by mlmc_optimal_n and
+ * schedules a level again when its shortfall exceeds 1% of its count,
+ * (iii) when nothing is outstanding, tests the bias
+ * max(|E_L|, |E_{L-1}| M^-alpha) / (M^alpha - 1) <= eps / sqrt(2), adding a
+ * level (V_{L+1} = V_L M^-beta) if it fails.  Returns MLMC_ENOTCONV if L_max
+ * is reached first (result still filled).                                    */
+mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                     const mlmc_run_opts* opts, mlmc_run_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -84,6 +84,8 @@ static double final_payoff(const orc_model *m, const orc_payoff *p, double S,
                            double asian_sum, double mn)
 {
     double disc = exp(-m->r * m->T);
+    /* a path that overflowed stays visible as a non-finite payoff */
+    if (!isfinite(S)) return NAN;
     switch (p->kind) {
     case ORC_CALL:
         return disc * (S > p->K ? S - p->K : 0.0);

@@ -1,0 +1,309 @@
+// C ABI: context management and the per-level entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "context.hpp"
+
+namespace mlmc {
+
+mlmc_status fail(mlmc_ctx* ctx, mlmc_status st, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+mlmc_status hip_fail(mlmc_ctx* ctx, hipError_t e, const char* what)
+{
+    return fail(ctx, MLMC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static int level_steps(int l, int M)
+{
+    int nf = 1;
+    for (int i = 0; i < l; ++i) nf *= M;
+    return nf;
+}
+
+mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payoff* p, int l, int M,
+                             int precision)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (!m || !p) return fail(ctx, MLMC_EINVAL, "model and payoff must not be NULL");
+    if (m->kind != MLMC_GBM && m->kind != MLMC_HESTON)
+        return fail(ctx, MLMC_EINVAL, "unknown model kind");
+    if (p->kind < MLMC_CALL || p->kind > MLMC_DIGITAL)
+        return fail(ctx, MLMC_EINVAL, "unknown payoff kind");
+    if (M != 2 && M != 4) return fail(ctx, MLMC_EINVAL, "M must be 2 or 4");
+    if (l < 0) return fail(ctx, MLMC_EINVAL, "level must be >= 0");
+    if ((M == 2 && l > 18) || (M == 4 && l > 9))
+        return fail(ctx, MLMC_EINVAL, "level too deep: at most 262144 fine steps");
+    if (precision != 32 && precision != 64) return fail(ctx, MLMC_EINVAL, "precision must be 32 or 64");
+    if (!(m->T > 0) || !(m->S0 > 0) || !std::isfinite(m->r))
+        return fail(ctx, MLMC_EINVAL, "model needs T > 0, S0 > 0 and finite r");
+    if (m->kind == MLMC_GBM && !(m->sigma >= 0))
+        return fail(ctx, MLMC_EINVAL, "GBM needs sigma >= 0");
+    if (m->kind == MLMC_HESTON &&
+        (!(m->rho >= -1 && m->rho <= 1) || !(m->xi >= 0) || !(m->theta >= 0) || !(m->v0 >= 0)))
+        return fail(ctx, MLMC_EINVAL, "Heston needs |rho| <= 1 and xi, theta, v0 >= 0");
+    return MLMC_OK;
+}
+
+LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
+                         int M, int precision, uint64_t N)
+{
+    LaunchShape s;
+    s.block = ctx->launch_block ? ctx->launch_block : 256;
+    s.ppt = precision == 64 ? 1 : (ctx->launch_ppt ? ctx->launch_ppt : 2);
+    if (!ctx->launch_block) {
+        // few samples: fewer paths per thread so that more lanes take part
+        const uint64_t lanes = (N + s.ppt - 1) / s.ppt;
+        if (lanes < (uint64_t)ctx->num_cu * 256) s.ppt = 1;
+    }
+    const uint64_t chunk = (uint64_t)s.block * s.ppt;
+    const uint64_t chunks = (N + chunk - 1) / chunk;
+    const uint64_t cap = (uint64_t)ctx->num_cu * (2048 / s.block);
+    s.grid = (int)std::max<uint64_t>(1, std::min(chunks, cap));
+    (void)m; (void)p; (void)l; (void)M;
+    return s;
+}
+
+__global__ void zero_records_kernel(LevelAcc* acc, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        for (int k = 0; k < kNumSums; ++k) acc[i].sum[k] = 0.0;
+        acc[i].n_nonfinite = 0;
+        acc[i].pad = 0;
+    }
+}
+
+hipError_t zero_records(LevelAcc* acc, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_records_kernel, dim3((n + 63) / 64), dim3(64), 0, st, acc, n);
+    return hipGetLastError();
+}
+
+template <typename Real>
+static LevelArgs<Real> make_args(const mlmc_model& m, const mlmc_payoff& p, int l, int M, uint64_t N,
+                                 uint64_t seed, uint64_t offset, uint32_t stream, int coupled,
+                                 LevelAcc* acc, double* d_pf, double* d_pc)
+{
+    LevelArgs<Real> a;
+    a.P = make_step_params<Real>(m, p, l, M);
+    a.seed = seed;
+    a.offset = offset;
+    a.N = N;
+    a.l = l;
+    a.nf = level_steps(l, M);
+    a.ngroups = (uint32_t)((a.nf + 3) / 4);
+    a.stream = stream;
+    a.acc = acc;
+    a.pf_out = d_pf;
+    a.pc_out = d_pc;
+    a.coupled = coupled;
+    return a;
+}
+
+mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
+                          uint64_t N, uint64_t seed, uint64_t offset, int precision, uint32_t stream,
+                          int coupled, LevelAcc* acc, double* d_pf, double* d_pc, const mlmc_cv* cv)
+{
+    if (N == 0) return MLMC_OK;
+    if (cv) return fail(ctx, MLMC_EINVAL, "control variate not available in this build");
+    const LaunchShape shape = choose_shape(ctx, m, p, l, M, precision, N);
+    hipError_t e;
+    if (precision == 64) {
+        auto a = make_args<double>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
+        e = launch_level(m, p, M, 64, &a, shape, ctx->stream);
+    } else {
+        auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
+        e = launch_level(m, p, M, 32, &a, shape, ctx->stream);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "level kernel launch");
+    return MLMC_OK;
+}
+
+static mlmc_status finish_level(mlmc_ctx* ctx, uint64_t N, int l, int M, int coupled,
+                                mlmc_level_result* out)
+{
+    MLMC_HIP(ctx, hipMemcpyAsync(ctx->h_acc, ctx->d_acc, sizeof(LevelAcc), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const LevelAcc& r = ctx->h_acc[0];
+    if (out) {
+        out->sum_y = r.sum[0];
+        out->sum_y2 = r.sum[1];
+        out->sum_pf = r.sum[2];
+        out->sum_pf2 = r.sum[3];
+        out->sum_pc = r.sum[4];
+        out->sum_pc2 = r.sum[5];
+        const double nf = std::pow((double)M, (double)l);
+        out->cost = (double)N * ((coupled && l > 0) ? nf + nf / M : nf);
+        out->n = N;
+        out->n_nonfinite = r.n_nonfinite;
+    }
+    if (r.n_nonfinite)
+        return fail(ctx, MLMC_ENONFINITE,
+                    std::to_string(r.n_nonfinite) + " non-finite samples left out of the sums");
+    return MLMC_OK;
+}
+
+}  // namespace mlmc
+
+using namespace mlmc;
+
+extern "C" {
+
+mlmc_status mlmc_ctx_create(int device, mlmc_ctx** out)
+{
+    if (!out) return MLMC_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return MLMC_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return MLMC_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MLMC_EDEVICE;
+    mlmc_ctx* ctx = new (std::nothrow) mlmc_ctx();
+    if (!ctx) return MLMC_ENOMEM;
+    ctx->device = device;
+    ctx->num_cu = prop.multiProcessorCount;
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_acc, sizeof(LevelAcc) * kAccSlots);
+    if (e == hipSuccess) e = hipHostMalloc(&ctx->h_acc, sizeof(LevelAcc) * kAccSlots);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_tmp, sizeof(double) * 4 * MLMC_MAX_LEVELS);
+    if (e == hipSuccess) e = hipHostMalloc(&ctx->h_tmp, sizeof(double) * 4 * MLMC_MAX_LEVELS);
+    if (e != hipSuccess) {
+        mlmc_ctx_destroy(ctx);
+        return e == hipErrorOutOfMemory ? MLMC_ENOMEM : MLMC_EDEVICE;
+    }
+    ctx->stream = ctx->own_stream;
+    *out = ctx;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_driver_free(mlmc_ctx* ctx);   // driver.hip
+
+mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx)
+{
+    if (!ctx) return MLMC_OK;
+    hipSetDevice(ctx->device);
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    mlmc_driver_free(ctx);
+    if (ctx->d_acc) hipFree(ctx->d_acc);
+    if (ctx->h_acc) hipHostFree(ctx->h_acc);
+    if (ctx->d_tmp) hipFree(ctx->d_tmp);
+    if (ctx->h_tmp) hipHostFree(ctx->h_tmp);
+    if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_set_stream(mlmc_ctx* ctx, void* hip_stream)
+{
+    if (!ctx) return MLMC_EINVAL;
+    ctx->stream = hip_stream ? (hipStream_t)hip_stream : ctx->own_stream;
+    return MLMC_OK;
+}
+
+const char* mlmc_last_error(const mlmc_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+mlmc_status mlmc_set_launch(mlmc_ctx* ctx, int block, int ppt)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (block == 0) {
+        ctx->launch_block = ctx->launch_ppt = 0;
+        return MLMC_OK;
+    }
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+        return fail(ctx, MLMC_EINVAL, "block must be 64, 128, 256, 512 or 1024");
+    if (ppt != 1 && ppt != 2 && ppt != 4) return fail(ctx, MLMC_EINVAL, "ppt must be 1, 2 or 4");
+    ctx->launch_block = block;
+    ctx->launch_ppt = ppt;
+    return MLMC_OK;
+}
+
+static mlmc_status level_common(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                                int l, int M, uint64_t N, uint64_t seed, uint64_t path_offset,
+                                int precision, const mlmc_cv* cv, double* d_pf, double* d_pc,
+                                uint32_t stream, int coupled, mlmc_level_result* out)
+{
+    mlmc_status st = check_level_args(ctx, model, payoff, l, M, precision);
+    if (st) return st;
+    if (cv && precision != 32)
+        return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
+    if (N > (1ull << 40)) return fail(ctx, MLMC_EINVAL, "N too large (max 2^40 per call)");
+    if ((path_offset + N) >> 56) return fail(ctx, MLMC_EINVAL, "path index beyond 2^56");
+    ctx->err.clear();
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    MLMC_HIP(ctx, zero_records(ctx->d_acc, 1, ctx->stream));
+    st = enqueue_level(ctx, *model, *payoff, l, M, N, seed, path_offset, precision, stream, coupled,
+                       ctx->d_acc, d_pf, d_pc, cv);
+    if (st) return st;
+    return finish_level(ctx, N, l, M, coupled, out);
+}
+
+mlmc_status mlmc_level(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff, int l,
+                       int M, uint64_t N, uint64_t seed, uint64_t path_offset, int precision,
+                       const mlmc_cv* cv, mlmc_level_result* out)
+{
+    if (!out) return fail(ctx, MLMC_EINVAL, "out must not be NULL");
+    return level_common(ctx, model, payoff, l, M, N, seed, path_offset, precision, cv, nullptr,
+                        nullptr, kStreamNormal, 1, out);
+}
+
+mlmc_status mlmc_level_paths(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                             int l, int M, uint64_t N, uint64_t seed, uint64_t path_offset,
+                             int precision, const mlmc_cv* cv, double* d_pf, double* d_pc,
+                             mlmc_level_result* out)
+{
+    if (N && (!d_pf || !d_pc)) return fail(ctx, MLMC_EINVAL, "d_pf and d_pc must be device arrays");
+    return level_common(ctx, model, payoff, l, M, N, seed, path_offset, precision, cv, d_pf, d_pc,
+                        kStreamNormal, 1, out);
+}
+
+mlmc_status mlmc_stdmc(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff, int L,
+                       int M, uint64_t N, uint64_t seed, uint64_t path_offset, int precision,
+                       mlmc_level_result* out)
+{
+    if (!out) return fail(ctx, MLMC_EINVAL, "out must not be NULL");
+    return level_common(ctx, model, payoff, L, M, N, seed, path_offset, precision, nullptr, nullptr,
+                        nullptr, kStreamStdMC, 0, out);
+}
+
+mlmc_status mlmc_philox_words(mlmc_ctx* ctx, uint64_t seed, int level, uint64_t s0, uint32_t stream,
+                              uint32_t nblocks, uint64_t npaths, uint32_t* d_out)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (!d_out && npaths && nblocks) return fail(ctx, MLMC_EINVAL, "d_out must not be NULL");
+    if (level < 0 || level > 255) return fail(ctx, MLMC_EINVAL, "level must be in 0..255");
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    MLMC_HIP(ctx, launch_philox_words(seed, level, s0, stream, nblocks, npaths, d_out, ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_normals(mlmc_ctx* ctx, uint64_t seed, int level, uint64_t s0, uint32_t stream,
+                         int dim, int nsteps, uint64_t npaths, int precision, double* d_out)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if ((dim != 1 && dim != 2) || nsteps < 0 || (precision != 32 && precision != 64))
+        return fail(ctx, MLMC_EINVAL, "dim must be 1 or 2, precision 32 or 64");
+    if (!d_out && npaths && nsteps) return fail(ctx, MLMC_EINVAL, "d_out must not be NULL");
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    MLMC_HIP(ctx, launch_normals(seed, level, s0, stream, dim, nsteps, npaths, precision, d_out,
+                                 ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return MLMC_OK;
+}
+
+}  // extern "C"

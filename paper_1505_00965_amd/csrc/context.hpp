@@ -1,0 +1,60 @@
+// Library context: device, stream, device buffers and the last error.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/mlmc.h"
+#include "level.hpp"
+
+struct mlmc_ctx {
+    int device = 0;
+    int num_cu = 256;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int launch_block = 0, launch_ppt = 0;   // 0: tuned/default
+    // Level accumulators: kAccSlots records (payoff x level) + host mirror.
+    mlmc::LevelAcc* d_acc = nullptr;
+    mlmc::LevelAcc* h_acc = nullptr;
+    // Driver state on the device and its pinned host mirror (driver.hip).
+    void* d_drv = nullptr;
+    void* h_drv = nullptr;
+    double* d_tmp = nullptr;                // small fp64 scratch (optimal_n)
+    double* h_tmp = nullptr;
+};
+
+namespace mlmc {
+
+constexpr int kAccSlots = 64;
+
+// Record an error message and return the status.
+mlmc_status fail(mlmc_ctx* ctx, mlmc_status st, const std::string& msg);
+mlmc_status hip_fail(mlmc_ctx* ctx, hipError_t e, const char* what);
+
+#define MLMC_HIP(ctx, expr)                                              \
+    do {                                                                 \
+        hipError_t e__ = (expr);                                         \
+        if (e__ != hipSuccess) return ::mlmc::hip_fail((ctx), e__, #expr); \
+    } while (0)
+
+// Argument validation shared by the level entry points.
+mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payoff* p, int l, int M,
+                             int precision);
+// Launch shape for N samples at level l (honours mlmc_set_launch).
+LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
+                         int M, int precision, uint64_t N);
+// Enqueue one level into record `acc` (no zeroing, no sync).
+mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
+                          uint64_t N, uint64_t seed, uint64_t offset, int precision, uint32_t stream,
+                          int coupled, LevelAcc* acc, double* d_pf, double* d_pc,
+                          const mlmc_cv* cv);
+// Zero `n` records with a fill kernel (safe inside graph capture).
+hipError_t zero_records(LevelAcc* acc, int n, hipStream_t st);
+
+hipError_t launch_philox_words(uint64_t seed, int level, uint64_t s0, uint32_t stream,
+                               uint32_t nblocks, uint64_t npaths, uint32_t* out, hipStream_t st);
+hipError_t launch_normals(uint64_t seed, int level, uint64_t s0, uint32_t stream, int dim,
+                          int nsteps, uint64_t npaths, int precision, double* out, hipStream_t st);
+
+}  // namespace mlmc

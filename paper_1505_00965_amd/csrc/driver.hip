@@ -1,0 +1,287 @@
+// Adaptive MLMC driver: the fp64 update kernel and the host loop.
+//
+// The paper fixes the estimator Y = sum_l Yhat_l (eq. (eq:mlmc:ident)), that
+// level variances add (Sec. 5), the cost measure (Sec. 3), and leaves N_l to
+// an optimisation over estimated variances (Sec. 5, "Constructive Upper
+// Bound"); the complexity theorem sets the target E[(Y - E P)^2] < eps^2.
+// Reading used: eps is an RMSE split evenly into bias^2 and variance;
+// minimising sum N_l C_l under sum V_l/N_l = eps^2/2 gives
+// N_l = ceil(2 eps^-2 sqrt(V_l/C_l) sum_k sqrt(V_k C_k)); costs
+// C_0 = 1, C_l = M^l + M^(l-1); estimates floored by the assumed rates from
+// l = 2; a level is resampled when its shortfall exceeds 1%; the bias is
+// estimated from weak order alpha (eq. (eq:emweak)).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "context.hpp"
+#include "driver.hpp"
+
+namespace mlmc {
+
+__device__ double level_cost_dev(int l, int M)
+{
+    if (l == 0) return 1.0;
+    double a = 1.0;
+    for (int i = 0; i < l - 1; ++i) a *= M;
+    return a * M + a;
+}
+
+__device__ void optimal_n_dev(int L, const double* V, const double* C, double eps, double* N)
+{
+    double total = 0.0;
+    for (int k = 0; k <= L; ++k) total += sqrt(V[k] * C[k]);
+    for (int l = 0; l <= L; ++l) N[l] = ceil(2.0 / (eps * eps) * sqrt(V[l] / C[l]) * total);
+}
+
+__global__ void optimal_n_kernel(int L, const double* V, const double* C, double eps, double* N)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) optimal_n_dev(L, V, C, eps, N);
+}
+
+__device__ double fit_rate_dev(int L, const double* y, int M)
+{
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    int n = 0;
+    for (int l = 1; l <= L; ++l) {
+        if (!(y[l] > 0)) continue;
+        const double x = l, v = log(y[l]) / log((double)M);
+        sx += x; sy += v; sxx += x * x; sxy += x * v; ++n;
+    }
+    if (n < 2) return nan("");
+    return (n * sxy - sx * sy) / (n * sxx - sx * sx);
+}
+
+// Absorb the batch, re-plan.  One thread; a handful of fp64 operations.
+__device__ void driver_update_dev(DriverState* st)
+{
+    const int M = st->M;
+    const double Ma = pow((double)M, st->alpha), Mb = pow((double)M, st->beta);
+    int L = st->L;
+    for (int l = 0; l <= L; ++l) {
+        if (st->dN[l] > 0) {
+            st->sum1[l] += st->batch[l].sum[0];
+            st->sum2[l] += st->batch[l].sum[1];
+            st->n[l] += st->dN[l];
+            st->n_nonfinite += st->batch[l].n_nonfinite;
+        }
+        for (int k = 0; k < kNumSums; ++k) st->batch[l].sum[k] = 0.0;
+        st->batch[l].n_nonfinite = 0;
+        st->dN[l] = 0.0;
+    }
+    st->iterations += 1;
+    for (int l = 0; l <= L; ++l) {
+        st->C[l] = level_cost_dev(l, M);
+        const double m = st->sum1[l] / st->n[l];
+        st->E[l] = fabs(m);
+        st->V[l] = st->sum2[l] / st->n[l] - m * m;
+        if (st->V[l] < 0) st->V[l] = 0;
+    }
+    for (int l = 2; l <= L; ++l) {
+        if (st->E[l] < st->E[l - 1] / Ma) st->E[l] = st->E[l - 1] / Ma;
+        if (st->V[l] < st->V[l - 1] / Mb) st->V[l] = st->V[l - 1] / Mb;
+    }
+    optimal_n_dev(L, st->V, st->C, st->eps, st->Nopt);
+    int more = 0;
+    for (int l = 0; l <= L; ++l) {
+        const double d = st->Nopt[l] - st->n[l];
+        st->dN[l] = (d > 0.01 * st->n[l]) ? d : 0.0;
+        if (st->dN[l] > 0) more = 1;
+    }
+    if (!more) {
+        const double rem = fmax(st->E[L], st->E[L - 1] / Ma) / (Ma - 1.0);
+        st->bias_est = rem;
+        if (rem <= st->eps / sqrt(2.0)) {
+            st->converged = 1;
+            st->done = 1;
+        } else if (L == st->L_max) {
+            st->done = 1;
+        } else {
+            ++L;
+            st->V[L] = st->V[L - 1] / Mb;
+            st->E[L] = st->E[L - 1] / Ma;
+            st->C[L] = level_cost_dev(L, M);
+            st->n[L] = 0;
+            st->sum1[L] = 0;
+            st->sum2[L] = 0;
+            optimal_n_dev(L, st->V, st->C, st->eps, st->Nopt);
+            for (int l = 0; l <= L; ++l) {
+                const double d = st->Nopt[l] - st->n[l];
+                st->dN[l] = (l == L) ? (st->Nopt[l] > 1 ? st->Nopt[l] : 1.0)
+                                     : ((d > 0.01 * st->n[l]) ? d : 0.0);
+            }
+            st->L = L;
+        }
+    }
+    if (st->iterations >= st->max_iterations) st->done = 1;
+    if (st->done) {
+        double est = 0.0, var = 0.0;
+        double absE[kMaxLevels], Vr[kMaxLevels];
+        for (int l = 0; l <= st->L; ++l) {
+            const double m = st->sum1[l] / st->n[l];
+            est += m;
+            const double v = st->sum2[l] / st->n[l] - m * m;
+            var += (v > 0 ? v : 0) / st->n[l];
+            absE[l] = fabs(m);
+            Vr[l] = v;
+        }
+        st->estimate = est;
+        st->var_est = var;
+        st->alpha_fit = -fit_rate_dev(st->L, absE, M);
+        st->beta_fit = -fit_rate_dev(st->L, Vr, M);
+        st->gamma_fit = fit_rate_dev(st->L, st->C, M);
+    }
+}
+
+__global__ void driver_update_kernel(DriverState* st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) driver_update_dev(st);
+}
+
+hipError_t launch_driver_update(DriverState* st, hipStream_t stream)
+{
+    hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(64), 0, stream, st);
+    return hipGetLastError();
+}
+
+static mlmc_status ensure_driver(mlmc_ctx* ctx)
+{
+    if (ctx->d_drv) return MLMC_OK;
+    MLMC_HIP(ctx, hipMalloc(&ctx->d_drv, sizeof(DriverState)));
+    MLMC_HIP(ctx, hipHostMalloc(&ctx->h_drv, sizeof(DriverState)));
+    return MLMC_OK;
+}
+
+// persistent.hip: one iteration as one graph launch
+mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p,
+                           const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st);
+
+}  // namespace mlmc
+
+using namespace mlmc;
+
+extern "C" {
+
+mlmc_status mlmc_driver_free(mlmc_ctx* ctx)
+{
+    if (!ctx) return MLMC_OK;
+    if (ctx->d_drv) hipFree(ctx->d_drv);
+    if (ctx->h_drv) hipHostFree(ctx->h_drv);
+    ctx->d_drv = ctx->h_drv = nullptr;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_optimal_n(mlmc_ctx* ctx, int L, const double* V, const double* C, double eps,
+                           double* N)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (L < 0 || L >= MLMC_MAX_LEVELS || !V || !C || !N || !(eps > 0))
+        return fail(ctx, MLMC_EINVAL, "need 0 <= L < 16, eps > 0 and non-NULL arrays");
+    for (int l = 0; l <= L; ++l)
+        if (!(V[l] >= 0) || !(C[l] > 0)) return fail(ctx, MLMC_EINVAL, "need V >= 0 and C > 0");
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t n = (size_t)(L + 1);
+    double* dV = ctx->d_tmp;
+    double* dC = ctx->d_tmp + MLMC_MAX_LEVELS;
+    double* dN = ctx->d_tmp + 2 * MLMC_MAX_LEVELS;
+    std::memcpy(ctx->h_tmp, V, n * sizeof(double));
+    std::memcpy(ctx->h_tmp + MLMC_MAX_LEVELS, C, n * sizeof(double));
+    MLMC_HIP(ctx, hipMemcpyAsync(ctx->d_tmp, ctx->h_tmp, 2 * MLMC_MAX_LEVELS * sizeof(double),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(optimal_n_kernel, dim3(1), dim3(64), 0, ctx->stream, L, dV, dC, eps, dN);
+    MLMC_HIP(ctx, hipGetLastError());
+    MLMC_HIP(ctx, hipMemcpyAsync(ctx->h_tmp + 2 * MLMC_MAX_LEVELS, dN, n * sizeof(double),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::memcpy(N, ctx->h_tmp + 2 * MLMC_MAX_LEVELS, n * sizeof(double));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                     const mlmc_run_opts* opts, mlmc_run_result* out)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (!opts || !out) return fail(ctx, MLMC_EINVAL, "opts and out must not be NULL");
+    const mlmc_run_opts& o = *opts;
+    mlmc_status st = check_level_args(ctx, model, payoff, 0, o.M, o.precision);
+    if (st) return st;
+    if (!(o.eps > 0)) return fail(ctx, MLMC_EINVAL, "eps must be > 0");
+    if (o.L_min < 1 || o.L_max < o.L_min || o.L_max > 12)
+        return fail(ctx, MLMC_EINVAL, "need 1 <= L_min <= L_max <= 12");
+    if ((o.M == 4 && o.L_max > 9)) return fail(ctx, MLMC_EINVAL, "L_max too deep for M = 4");
+    if (o.n_pilot < 2) return fail(ctx, MLMC_EINVAL, "n_pilot must be >= 2");
+    if (o.cv && o.precision != 32)
+        return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
+    ctx->err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    st = ensure_driver(ctx);
+    if (st) return st;
+    DriverState* h = (DriverState*)ctx->h_drv;
+    DriverState* d = (DriverState*)ctx->d_drv;
+    std::memset(h, 0, sizeof(DriverState));
+    h->eps = o.eps;
+    h->alpha = o.alpha > 0 ? o.alpha : 1.0;
+    h->beta = o.beta > 0 ? o.beta : 1.0;
+    h->M = o.M;
+    h->L_min = o.L_min;
+    h->L_max = o.L_max;
+    h->max_iterations = 1000;
+    h->L = o.L_min;
+    for (int l = 0; l <= o.L_min; ++l) h->dN[l] = (double)o.n_pilot;
+    MLMC_HIP(ctx, hipMemcpyAsync(d, h, sizeof(DriverState), hipMemcpyHostToDevice, ctx->stream));
+    if (o.persistent) {
+        st = run_persistent(ctx, *model, *payoff, o, d, h);
+        if (st) return st;
+    } else {
+        for (;;) {
+            for (int l = 0; l <= h->L; ++l) {
+                if (h->dN[l] <= 0) continue;
+                st = enqueue_level(ctx, *model, *payoff, l, o.M, (uint64_t)h->dN[l], o.seed,
+                                   (uint64_t)h->n[l], o.precision, kStreamNormal, 1, &d->batch[l],
+                                   nullptr, nullptr, o.cv);
+                if (st) return st;
+            }
+            MLMC_HIP(ctx, launch_driver_update(d, ctx->stream));
+            MLMC_HIP(ctx, hipMemcpyAsync(h, d, sizeof(DriverState), hipMemcpyDeviceToHost,
+                                         ctx->stream));
+            MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (h->done) break;
+        }
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    std::memset(out, 0, sizeof(*out));
+    out->estimate = h->estimate;
+    out->rmse_est = std::sqrt(h->var_est + h->bias_est * h->bias_est);
+    out->wall_s = std::chrono::duration<double>(t1 - t0).count();
+    out->L = h->L;
+    out->converged = h->converged;
+    out->iterations = h->iterations;
+    double cost = 0.0;
+    for (int l = 0; l <= h->L; ++l) {
+        out->N[l] = (uint64_t)h->n[l];
+        out->sum_y[l] = h->sum1[l];
+        out->sum_y2[l] = h->sum2[l];
+        out->E[l] = h->sum1[l] / h->n[l];
+        out->V[l] = h->sum2[l] / h->n[l] - out->E[l] * out->E[l];
+        out->C[l] = h->C[l];
+        cost += h->n[l] * h->C[l];
+    }
+    out->alpha = h->alpha_fit;
+    out->beta = h->beta_fit;
+    out->gamma = h->gamma_fit;
+    out->cost = cost;
+    out->n_nonfinite = h->n_nonfinite;
+    if (h->n_nonfinite)
+        return fail(ctx, MLMC_ENONFINITE, "non-finite samples were left out of the sums");
+    if (!h->converged) {
+        if (h->iterations >= h->max_iterations)
+            return fail(ctx, MLMC_EDEVICE, "driver did not settle within its iteration limit");
+        return fail(ctx, MLMC_ENOTCONV, "L_max reached before the bias test passed");
+    }
+    return MLMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,36 @@
+// Device-resident state of the adaptive MLMC driver.
+//
+// The sampler adds each level's batch sums into batch[l]; one small fp64
+// kernel (driver_update) then absorbs them, re-estimates E_l and V_l, sets the
+// optimal N_l and the next outstanding batch dN_l, runs the bias test and
+// adds a level when needed.  The host only reads this struct back to learn
+// what to launch next (or, in the persistent form, only the done flag).
+#pragma once
+#include <stdint.h>
+
+#include "reduce.hpp"
+
+namespace mlmc {
+
+constexpr int kMaxLevels = 16;
+
+struct DriverState {
+    // configuration
+    double eps, alpha, beta;
+    int M, L_min, L_max, max_iterations;
+    // progress
+    int L, done, converged, iterations;
+    double n[kMaxLevels];          // samples absorbed so far
+    double dN[kMaxLevels];         // outstanding batch (sampled next)
+    double sum1[kMaxLevels], sum2[kMaxLevels];
+    double E[kMaxLevels], V[kMaxLevels], C[kMaxLevels], Nopt[kMaxLevels];
+    double estimate, var_est, bias_est;
+    double alpha_fit, beta_fit, gamma_fit;
+    unsigned long long n_nonfinite;
+    // persistent form: work table bookkeeping (persistent.hip)
+    unsigned int work_head, work_count;
+    unsigned int pad0, pad1;
+    LevelAcc batch[kMaxLevels];
+};
+
+}  // namespace mlmc

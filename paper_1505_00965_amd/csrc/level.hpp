@@ -1,0 +1,43 @@
+// Level-sampler kernel arguments and host-side launchers shared by the
+// per-level entry points, the driver and the persistent kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mlmc.h"
+#include "reduce.hpp"
+#include "sampler.hpp"
+
+namespace mlmc {
+
+template <typename Real>
+struct LevelArgs {
+    StepParams<Real> P;
+    uint64_t seed;
+    uint64_t offset;      // index of the first sample
+    uint64_t N;           // number of samples
+    int l;                // level
+    int nf;               // fine steps M^l
+    uint32_t ngroups;     // ceil(nf / 4): groups of four fine steps
+    uint32_t stream;      // Philox stream of the Brownian normals
+    LevelAcc* acc;        // (payoff, level) record receiving the sums
+    double* pf_out;       // optional per-path dump (fp64), else null
+    double* pc_out;
+    int coupled;          // 0: standard MC (fine path only at level l)
+};
+
+// Host-side conversion of model/payoff to the kernel's parameter block.
+template <typename Real>
+StepParams<Real> make_step_params(const mlmc_model& m, const mlmc_payoff& p, int l, int M);
+
+// Launch shape actually used.
+struct LaunchShape {
+    int block, ppt, grid;
+};
+
+// Enqueue one level's sampler on `stream` (accumulating into args.acc).
+// Returns hipSuccess or the launch error.  Shape chosen by the caller.
+hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int precision,
+                        const void* args, LaunchShape shape, hipStream_t stream);
+
+}  // namespace mlmc

@@ -1,0 +1,171 @@
+// Fused coupled level sampler for gfx950: one lane advances PPT coupled
+// (fine, coarse) Euler--Maruyama path pairs of level l, all in registers.
+//
+// Level l: n_f = M^l fine steps of size h = T/n_f (eq. (eq:mlmc:Dtl)); the
+// coarse path takes n_f/M steps of size H = M h, each driven by the sum of
+// the M fine Brownian increments it covers (eq. (eq:Yldef) and Fig. 2); level
+// 0 has only the single-step path (eq. (eq:mlmc:Yzero)).  Steps follow
+// eq. (eq:em) in increment form, S <- S + S (r dt + vol dW), which in fp32
+// keeps the drift that the product form 1 + r dt would round away.
+//
+// Work per fine step lives in VGPRs: state, coarse increment sums, payoff
+// accumulators.  The generator block j (four 32-bit words) feeds four fine
+// steps of a one-factor model or two of the two-factor (Heston) model, so with
+// M = 4 one block is exactly one coarse step of GBM.  Nothing touches memory
+// inside the path loop.
+#pragma once
+#include "philox.hpp"
+
+namespace mlmc {
+
+enum ModelKind : int { kGBM = 0, kHeston = 1 };
+enum PayoffKind : int { kCall = 0, kAsian = 1, kLookback = 2, kDigital = 3 };
+
+// Model and payoff parameters converted once on the host.
+template <typename Real>
+struct StepParams {
+    Real S0, r, sigma, kappa, theta, xi, rho, rho_c, v0;
+    Real h, sqh, H, rh, rH;          // fine/coarse step sizes and r*dt
+    Real K, payout, disc, inv_T;     // payoff
+    Real lnu_scale;                  // -2 h ln(2): bridge term e = lnu_scale * log2(U)
+    Real asian_scale;                // h / (2T)
+};
+
+template <typename Real>
+__device__ __forceinline__ Real fsqrt(Real x);
+template <>
+__device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <>
+__device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
+
+template <typename Real>
+__device__ __forceinline__ Real flog2(Real x);
+template <>
+__device__ __forceinline__ float flog2<float>(float x) { return __builtin_amdgcn_logf(x); }
+template <>
+__device__ __forceinline__ double flog2<double>(double x) { return log2(x); }
+
+template <typename Real>
+__device__ __forceinline__ Real uniform01(uint32_t x);
+template <>
+__device__ __forceinline__ float uniform01<float>(uint32_t x) { return u01f(x); }
+template <>
+__device__ __forceinline__ double uniform01<double>(uint32_t x) { return u01d(x); }
+
+// Compensated (Neumaier) accumulation for the Asian average: the sum of up
+// to 65536 terms keeps ~1e-7 relative accuracy in fp32.
+template <typename Real>
+__device__ __forceinline__ void comp_add(Real& sum, Real& comp, Real y)
+{
+    const Real t = sum + y;
+    comp += (fabs(sum) >= fabs(y)) ? ((sum - t) + y) : ((y - t) + sum);
+    sum = t;
+}
+
+// Exact minimum of a Brownian bridge with frozen volatility b over a step,
+// (x0 + x1 - sqrt((x1 - x0)^2 - 2 b^2 dt ln U)) / 2, with e = -2 dt ln U.
+template <typename Real>
+__device__ __forceinline__ Real bridge_min(Real x0, Real x1, Real b, Real e)
+{
+    const Real d = x1 - x0;
+    return Real(0.5) * (x0 + x1 - fsqrt<Real>(d * d + (b * b) * e));
+}
+
+template <typename Real>
+struct PathPair {
+    Real S, v;                 // fine state
+    Real Sc, vc;               // coarse state
+    Real dw1c, dwpc;           // coarse increment sums (S factor, independent factor)
+    Real asum, acomp;          // fine trapezoid sum (compensated)
+    Real csum, ccomp;          // coarse trapezoid sum
+    Real mn, mnc;              // bridge minima
+    Real wpart;                // coarse lookback: fine Brownian path since the coarse step start
+    Real cvf, cvc;             // control-variate sums (unused without a network)
+};
+
+template <typename Real, int MODEL, int PAYOFF>
+__device__ __forceinline__ void init_pair(PathPair<Real>& q, const StepParams<Real>& P)
+{
+    q.S = P.S0; q.v = P.v0; q.Sc = P.S0; q.vc = P.v0;
+    q.dw1c = 0; q.dwpc = 0;
+    q.asum = 0; q.acomp = 0; q.csum = 0; q.ccomp = 0;
+    q.mn = Real(INFINITY); q.mnc = Real(INFINITY);
+    q.wpart = 0; q.cvf = 0; q.cvc = 0;
+}
+
+// One fine step with increments (dw1, dwp), bridge exponent e (lookback only)
+// and position k = n mod M inside the current coarse step.
+template <typename Real, int MODEL, int PAYOFF>
+__device__ __forceinline__ void fine_step(PathPair<Real>& q, const StepParams<Real>& P, Real dw1,
+                                          Real dwp, Real e, int k, bool coupled)
+{
+    const Real S0n = q.S;
+    Real vol;
+    if (MODEL == kGBM) {
+        vol = P.sigma;
+        q.S = __builtin_fma(q.S, __builtin_fma(P.sigma, dw1, P.rh), q.S);
+    } else {
+        const Real vp = q.v > Real(0) ? q.v : Real(0);
+        vol = fsqrt<Real>(vp);
+        const Real dw2 = __builtin_fma(P.rho, dw1, P.rho_c * dwp);
+        q.S = __builtin_fma(q.S, __builtin_fma(vol, dw1, P.rh), q.S);
+        q.v = __builtin_fma(P.xi * vol, dw2, __builtin_fma(P.kappa * P.h, P.theta - vp, q.v));
+    }
+    if (PAYOFF == kAsian) comp_add(q.asum, q.acomp, S0n + q.S);
+    if (PAYOFF == kLookback) {
+        const Real m = bridge_min(S0n, q.S, vol * S0n, e);
+        q.mn = m < q.mn ? m : q.mn;
+    }
+    if (!coupled) return;
+    q.dw1c += dw1;
+    if (MODEL == kHeston) q.dwpc += dwp;
+    if (PAYOFF == kLookback) {
+        // coarse path refined at the fine times with frozen coefficients:
+        // X(tau) = Sc + Sc (r tau + vol_c W(tau)), W from the coarse step start
+        const Real volc = (MODEL == kGBM) ? P.sigma
+                                         : fsqrt<Real>(q.vc > Real(0) ? q.vc : Real(0));
+        const Real x0 = __builtin_fma(q.Sc, __builtin_fma(volc, q.wpart, P.rh * Real(k)), q.Sc);
+        q.wpart += dw1;
+        const Real x1 = __builtin_fma(q.Sc, __builtin_fma(volc, q.wpart, P.rh * Real(k + 1)), q.Sc);
+        const Real m = bridge_min(x0, x1, volc * q.Sc, e);
+        q.mnc = m < q.mnc ? m : q.mnc;
+    }
+}
+
+// One coarse step from the accumulated sums.
+template <typename Real, int MODEL, int PAYOFF>
+__device__ __forceinline__ void coarse_step(PathPair<Real>& q, const StepParams<Real>& P)
+{
+    const Real S0c = q.Sc;
+    if (MODEL == kGBM) {
+        q.Sc = __builtin_fma(q.Sc, __builtin_fma(P.sigma, q.dw1c, P.rH), q.Sc);
+    } else {
+        const Real vp = q.vc > Real(0) ? q.vc : Real(0);
+        const Real sv = fsqrt<Real>(vp);
+        const Real dw2 = __builtin_fma(P.rho, q.dw1c, P.rho_c * q.dwpc);
+        q.Sc = __builtin_fma(q.Sc, __builtin_fma(sv, q.dw1c, P.rH), q.Sc);
+        q.vc = __builtin_fma(P.xi * sv, dw2, __builtin_fma(P.kappa * P.H, P.theta - vp, q.vc));
+    }
+    if (PAYOFF == kAsian) comp_add(q.csum, q.ccomp, S0c + q.Sc);
+    q.dw1c = 0;
+    q.dwpc = 0;
+    q.wpart = 0;
+}
+
+template <typename Real, int PAYOFF>
+__device__ __forceinline__ Real payoff_value(const StepParams<Real>& P, Real S, Real sum,
+                                             Real comp, Real mn, Real dt)
+{
+    // a path that overflowed stays visible as a non-finite payoff
+    if (!isfinite(S)) return S - S;
+    if (PAYOFF == kCall) return P.disc * (S > P.K ? S - P.K : Real(0));
+    if (PAYOFF == kDigital)
+        return S > P.K ? P.disc * P.payout : (S == P.K ? P.disc * Real(0.5) * P.payout : Real(0));
+    if (PAYOFF == kAsian) {
+        const Real A = (sum + comp) * (dt * Real(0.5)) * P.inv_T;
+        return P.disc * (A > P.K ? A - P.K : Real(0));
+    }
+    return P.disc * (S - mn);   // floating-strike lookback
+}
+
+}  // namespace mlmc

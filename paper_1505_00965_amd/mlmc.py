@@ -1,0 +1,229 @@
+"""Python binding of libmlmc.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels.  PyTorch supplies device
+memory (tensors passed as d_* pointers) and streams.  If the shared library
+is missing or fails to load, every call raises: there is no fallback.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlmc.so")
+
+MLMC_OK, MLMC_ENOTCONV, MLMC_EINVAL, MLMC_ENOMEM, MLMC_EDEVICE, MLMC_ENONFINITE = 0, 1, -1, -2, -3, -4
+GBM, HESTON = 0, 1
+CALL, ASIAN, LOOKBACK, DIGITAL = 0, 1, 2, 3
+STREAM_NORMAL, STREAM_BRIDGE, STREAM_TRAIN_NORMAL = 0, 1, 2
+MAX_LEVELS = 16
+
+EXPORTED = [
+    "mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_set_stream", "mlmc_last_error",
+    "mlmc_set_launch", "mlmc_level", "mlmc_level_paths", "mlmc_philox_words", "mlmc_normals",
+    "mlmc_stdmc", "mlmc_optimal_n", "mlmc_run",
+]
+
+
+class MLMCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mlmc status {status}: {msg}")
+        self.status = status
+
+
+class Model(C.Structure):
+    _fields_ = [("kind", C.c_int), ("S0", C.c_double), ("r", C.c_double),
+                ("sigma", C.c_double), ("T", C.c_double), ("kappa", C.c_double),
+                ("theta", C.c_double), ("xi", C.c_double), ("rho", C.c_double),
+                ("v0", C.c_double)]
+
+
+class Payoff(C.Structure):
+    _fields_ = [("kind", C.c_int), ("K", C.c_double), ("payout", C.c_double)]
+
+
+class LevelResult(C.Structure):
+    _fields_ = [("sum_y", C.c_double), ("sum_y2", C.c_double), ("sum_pf", C.c_double),
+                ("sum_pf2", C.c_double), ("sum_pc", C.c_double), ("sum_pc2", C.c_double),
+                ("cost", C.c_double), ("n", C.c_uint64), ("n_nonfinite", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RunOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("M", C.c_int), ("L_min", C.c_int), ("L_max", C.c_int),
+                ("n_pilot", C.c_uint64), ("seed", C.c_uint64), ("precision", C.c_int),
+                ("persistent", C.c_int), ("alpha", C.c_double), ("beta", C.c_double),
+                ("cv", C.c_void_p)]
+
+
+class RunResult(C.Structure):
+    L16 = MAX_LEVELS
+    _fields_ = [("estimate", C.c_double), ("rmse_est", C.c_double), ("wall_s", C.c_double),
+                ("L", C.c_int), ("converged", C.c_int), ("iterations", C.c_int),
+                ("N", C.c_uint64 * L16), ("E", C.c_double * L16), ("V", C.c_double * L16),
+                ("C", C.c_double * L16), ("sum_y", C.c_double * L16),
+                ("sum_y2", C.c_double * L16), ("alpha", C.c_double), ("beta", C.c_double),
+                ("gamma", C.c_double), ("cost", C.c_double), ("n_nonfinite", C.c_uint64)]
+
+    def as_dict(self):
+        L = self.L
+        d = {k: getattr(self, k) for k in ("estimate", "rmse_est", "wall_s", "L", "converged",
+                                           "iterations", "alpha", "beta", "gamma", "cost",
+                                           "n_nonfinite")}
+        d["converged"] = bool(d["converged"])
+        for k in ("N", "E", "V", "C", "sum_y", "sum_y2"):
+            d[k] = list(getattr(self, k))[:L + 1]
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libmlmc.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, u64, i32, d, u32 = C.c_void_p, C.c_uint64, C.c_int, C.c_double, C.c_uint32
+    M_, P_ = C.POINTER(Model), C.POINTER(Payoff)
+    L.mlmc_ctx_create.argtypes = [i32, C.POINTER(vp)]
+    L.mlmc_ctx_destroy.argtypes = [vp]
+    L.mlmc_set_stream.argtypes = [vp, vp]
+    L.mlmc_last_error.argtypes = [vp]
+    L.mlmc_last_error.restype = C.c_char_p
+    L.mlmc_set_launch.argtypes = [vp, i32, i32]
+    L.mlmc_level.argtypes = [vp, M_, P_, i32, i32, u64, u64, u64, i32, vp, C.POINTER(LevelResult)]
+    L.mlmc_level_paths.argtypes = [vp, M_, P_, i32, i32, u64, u64, u64, i32, vp, vp, vp,
+                                   C.POINTER(LevelResult)]
+    L.mlmc_philox_words.argtypes = [vp, u64, i32, u64, u32, u32, u64, vp]
+    L.mlmc_normals.argtypes = [vp, u64, i32, u64, u32, i32, i32, u64, i32, vp]
+    L.mlmc_stdmc.argtypes = [vp, M_, P_, i32, i32, u64, u64, u64, i32, C.POINTER(LevelResult)]
+    L.mlmc_optimal_n.argtypes = [vp, i32, C.POINTER(d), C.POINTER(d), d, C.POINTER(d)]
+    L.mlmc_run.argtypes = [vp, M_, P_, C.POINTER(RunOpts), C.POINTER(RunResult)]
+    for name in EXPORTED:
+        if name != "mlmc_last_error":
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def model(kind=GBM, S0=100.0, r=0.05, sigma=0.2, T=1.0, kappa=2.0, theta=0.04, xi=0.3,
+          rho=-0.7, v0=0.04):
+    return Model(kind, S0, r, sigma, T, kappa, theta, xi, rho, v0)
+
+
+def payoff(kind=CALL, K=100.0, payout=1.0):
+    return Payoff(kind, K, payout)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+class Context:
+    """Owns an mlmc_ctx on one device; methods mirror the C entry points."""
+
+    def __init__(self, device=0):
+        self._lib = lib()
+        h = C.c_void_p()
+        st = self._lib.mlmc_ctx_create(device, C.byref(h))
+        if st != MLMC_OK:
+            raise MLMCError(st, f"mlmc_ctx_create(device={device}) failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self._lib.mlmc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, allow=(MLMC_OK,)):
+        if st not in allow:
+            raise MLMCError(st, self._lib.mlmc_last_error(self.h).decode())
+        return st
+
+    def last_error(self):
+        return self._lib.mlmc_last_error(self.h).decode()
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream, a raw hipStream_t int, or None."""
+        raw = None if stream is None else getattr(stream, "cuda_stream", stream)
+        self._check(self._lib.mlmc_set_stream(self.h, raw))
+
+    def set_launch(self, block=0, ppt=0):
+        self._check(self._lib.mlmc_set_launch(self.h, block, ppt))
+
+    def mlmc_level(self, m, p, l, M, N, seed, path_offset=0, precision=32, cv=None,
+                   allow_nonfinite=False):
+        r = LevelResult()
+        allow = (MLMC_OK, MLMC_ENONFINITE) if allow_nonfinite else (MLMC_OK,)
+        self._check(self._lib.mlmc_level(self.h, C.byref(m), C.byref(p), l, M, N, seed,
+                                         path_offset, precision, _cvh(cv), C.byref(r)), allow)
+        return r.as_dict()
+
+    def mlmc_level_paths(self, m, p, l, M, N, seed, d_pf, d_pc, path_offset=0, precision=32,
+                         cv=None, allow_nonfinite=False):
+        r = LevelResult()
+        allow = (MLMC_OK, MLMC_ENONFINITE) if allow_nonfinite else (MLMC_OK,)
+        self._check(self._lib.mlmc_level_paths(self.h, C.byref(m), C.byref(p), l, M, N, seed,
+                                               path_offset, precision, _cvh(cv), _ptr(d_pf),
+                                               _ptr(d_pc), C.byref(r)), allow)
+        return r.as_dict()
+
+    def mlmc_philox_words(self, seed, level, s0, stream, nblocks, npaths, d_out):
+        self._check(self._lib.mlmc_philox_words(self.h, seed, level, s0, stream, nblocks, npaths,
+                                                _ptr(d_out)))
+
+    def mlmc_normals(self, seed, level, s0, stream, dim, nsteps, npaths, precision, d_out):
+        self._check(self._lib.mlmc_normals(self.h, seed, level, s0, stream, dim, nsteps, npaths,
+                                           precision, _ptr(d_out)))
+
+    def mlmc_stdmc(self, m, p, L, M, N, seed, path_offset=0, precision=32):
+        r = LevelResult()
+        self._check(self._lib.mlmc_stdmc(self.h, C.byref(m), C.byref(p), L, M, N, seed,
+                                         path_offset, precision, C.byref(r)))
+        return r.as_dict()
+
+    def mlmc_optimal_n(self, V, Cl, eps):
+        L = len(V) - 1
+        Va = (C.c_double * (L + 1))(*V)
+        Ca = (C.c_double * (L + 1))(*Cl)
+        Na = (C.c_double * (L + 1))()
+        self._check(self._lib.mlmc_optimal_n(self.h, L, Va, Ca, eps, Na))
+        return list(Na)
+
+    def mlmc_run(self, m, p, eps, M=4, L_min=2, L_max=8, n_pilot=10000, seed=1, precision=32,
+                 persistent=False, alpha=0.0, beta=0.0, cv=None, allow_notconv=False):
+        o = RunOpts(eps, M, L_min, L_max, n_pilot, seed, precision, int(persistent), alpha, beta,
+                    _cvh(cv))
+        r = RunResult()
+        allow = (MLMC_OK, MLMC_ENOTCONV) if allow_notconv else (MLMC_OK,)
+        self._check(self._lib.mlmc_run(self.h, C.byref(m), C.byref(p), C.byref(o), C.byref(r)),
+                    allow)
+        return r.as_dict()
+
+
+def _cvh(cv):
+    if cv is None:
+        return None
+    return cv.h

@@ -18,3 +18,20 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gctx():
+    """mlmc context on cuda:0 (GPU tests only): fails loudly without the library."""
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a ROCm device"
+    from paper_1505_00965_amd import mlmc
+    ctx = mlmc.Context(0)
+    yield ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="session")
+def torch_dev():
+    import torch
+    return torch.device("cuda:0")

@@ -1,0 +1,162 @@
+"""GPU level sampler vs the FP64 oracle, path by path and level by level.
+
+Bar: per path |dP| <= 1e-4 S0 for fp32 stepping (1e-9 S0 for fp64); digital
+paths whose S_N lies within the fp32 path error of the strike may flip and
+are excluded; per-level sums equal the fp64 re-sum of the GPU's own paths to
+1e-12 relative; fp64 level means equal the oracle's to 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+from paper_1505_00965_amd import mlmc, workloads as W
+
+pytestmark = pytest.mark.gpu
+S0 = 100.0
+
+
+def gpu_paths(gctx, m, p, l, M, N, seed, offset, precision):
+    import torch
+    pf = torch.empty(N, dtype=torch.float64, device="cuda")
+    pc = torch.empty(N, dtype=torch.float64, device="cuda")
+    res = gctx.mlmc_level_paths(m, p, l, M, N, seed, pf, pc, path_offset=offset,
+                                precision=precision)
+    return pf.cpu().numpy(), pc.cpu().numpy(), res
+
+
+def models(orc, kind):
+    d = W.GBM_MODEL if kind == 0 else W.HESTON_MODEL
+    return mlmc.model(**d), orc.model(**d)
+
+
+def pays(orc, name):
+    d = W.PAYOFFS[name]
+    return mlmc.payoff(**d), orc.payoff(**d)
+
+
+CASES = [(M, l) for M, ls in ((2, (0, 1, 2, 5)), (4, (0, 1, 2, 4))) for l in ls]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("pname", ["call", "asian", "lookback", "digital"])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_per_path_parity(gctx, orc, kind, pname, precision):
+    gm, om = models(orc, kind)
+    gp, op = pays(orc, pname)
+    N = 3000
+    for (M, l) in CASES:
+        for offset in (0, (1 << 32) - 1000):
+            print(f"case kind={kind} payoff={pname} prec={precision} M={M} l={l} off={offset}",
+                  flush=True)
+            pf, pc, res = gpu_paths(gctx, gm, gp, l, M, N, 1, offset, precision)
+            rf, rc = orc.level_paths(om, op, l, M, N, 1, offset, nthreads=8)
+            tol = 1e-9 * S0 if precision == 64 else 1e-4 * S0
+            bad = (np.abs(pf - rf) > tol) | (np.abs(pc - rc) > tol)
+            if pname == "digital" and precision == 32 and bad.any():
+                # flips are allowed only where S_N is within the path error of K
+                k0 = orc.payoff(kind=0, K=0.0)
+                sf, sc = orc.level_paths(om, k0, l, M, N, 1, offset, nthreads=8)
+                disc = np.exp(-om.r * om.T)
+                near = (np.abs(sf / disc - 100.0) < 2e-2) | (np.abs(sc / disc - 100.0) < 2e-2)
+                assert np.all(near[bad]), (M, l, offset, np.where(bad & ~near))
+                assert bad.sum() <= max(2, 1e-2 * N)
+            else:
+                i = np.argmax(np.abs(pf - rf))
+                assert not bad.any(), (M, l, offset, i, pf[i], rf[i],
+                                       np.abs(pc - rc).max())
+            if l == 0:
+                assert np.all(pc == 0)
+            # the reduction equals the fp64 re-sum of the same paths
+            y = pf - pc
+            for key, ref in (("sum_y", y.sum()), ("sum_y2", (y * y).sum()),
+                             ("sum_pf", pf.sum()), ("sum_pc", pc.sum())):
+                assert abs(res[key] - ref) <= 1e-12 * max(1.0, abs(ref)) + 1e-12 * np.abs(y).sum(), key
+            assert res["n"] == N and res["n_nonfinite"] == 0
+
+
+def test_parity_set_fp64_level_means(gctx, orc):
+    """GBM call, M=2, l=0..5, N=20000, seed 1, fp64: level means to 1e-6 relative."""
+    gm, om = models(orc, 0)
+    gp, op = pays(orc, "call")
+    S = W.PARITY_SET
+    est = 0.0
+    var = 0.0
+    for l in S["levels"]:
+        g = gctx.mlmc_level(gm, gp, l, S["M"], S["N"], S["seed"], precision=64)
+        o = orc.level(om, op, l, S["M"], S["N"], S["seed"], nthreads=8)
+        gmean, omean = g["sum_y"] / S["N"], o["sum_y"] / S["N"]
+        print(f"l={l} gpu mean {gmean:.12g} oracle {omean:.12g} var {g['sum_y2']/S['N'] - gmean**2:.6g}")
+        assert abs(gmean - omean) <= 1e-6 * abs(omean)
+        assert abs(g["sum_y2"] - o["sum_y2"]) <= 1e-6 * o["sum_y2"]
+        assert g["cost"] == o["cost"]
+        est += gmean
+        var += (g["sum_y2"] / S["N"] - gmean**2) / S["N"]
+    assert abs(est - orc.bs_call()) < 4 * np.sqrt(var) + 0.03
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_launch_shape_invariance(gctx, precision):
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.ASIAN)
+    base = None
+    shapes = [(64, 1), (256, 2), (1024, 4), (128, 4), (512, 1)]
+    for block, ppt in shapes:
+        gctx.set_launch(block, ppt)
+        r = gctx.mlmc_level(gm, gp, 3, 4, 100003, 7, path_offset=55, precision=precision)
+        if base is None:
+            base = r
+        for k in ("sum_y", "sum_y2", "sum_pf", "sum_pc"):
+            assert abs(r[k] - base[k]) <= 1e-12 * abs(base[k]), (block, ppt, k)
+    gctx.set_launch(0, 0)
+
+
+def test_edge_cases(gctx, orc):
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    r = gctx.mlmc_level(gm, gp, 2, 4, 0, 1)
+    assert r["n"] == 0 and r["sum_y"] == 0 and r["cost"] == 0
+    r = gctx.mlmc_level(gm, gp, 2, 4, 1, 1, path_offset=123, precision=64)
+    pf, pc, _, _ = orc.level_sample(orc.model(**W.GBM_MODEL), orc.payoff(**W.CALL), 2, 4, 1, 123)
+    assert abs(r["sum_y"] - (pf - pc)) < 1e-9
+    # deepest level: 4^9 = 262144 steps, few paths, per-path parity
+    pf, pc, _ = gpu_paths(gctx, gm, gp, 9, 4, 70, 3, 0, 32)
+    rf, rc = orc.level_paths(orc.model(**W.GBM_MODEL), orc.payoff(**W.CALL), 9, 4, 70, 3, 0,
+                             nthreads=8)
+    assert np.abs(pf - rf).max() < 1e-4 * S0 and np.abs(pc - rc).max() < 1e-4 * S0
+    for bad in [dict(l=-1, M=4), dict(l=2, M=3), dict(l=10, M=4)]:
+        with pytest.raises(mlmc.MLMCError) as e:
+            gctx.mlmc_level(gm, gp, bad["l"], bad["M"], 10, 1)
+        assert e.value.status == mlmc.MLMC_EINVAL
+    with pytest.raises(mlmc.MLMCError):
+        gctx.mlmc_level(gm, gp, 1, 4, 10, 1, precision=16)
+    with pytest.raises(mlmc.MLMCError):
+        gctx.mlmc_level(mlmc.model(kind=5), gp, 1, 4, 10, 1)
+
+
+def test_nonfinite_samples_are_counted(gctx):
+    # a huge volatility drives fp32 paths to overflow: counted, not summed
+    # (the lookback payoff S_N - min keeps an overflowed path non-finite)
+    gm = mlmc.model(**dict(W.GBM_MODEL, sigma=1e3))
+    gp = mlmc.payoff(**W.LOOKBACK)
+    r = gctx.mlmc_level(gm, gp, 6, 4, 4096, 1, allow_nonfinite=True)
+    assert r["n_nonfinite"] > 0 and np.isfinite(r["sum_y"])
+    with pytest.raises(mlmc.MLMCError) as e:
+        gctx.mlmc_level(gm, gp, 6, 4, 4096, 1)
+    assert e.value.status == mlmc.MLMC_ENONFINITE
+
+
+def test_stdmc_matches_oracle(gctx, orc):
+    gm, om = models(orc, 0)
+    gp, op = pays(orc, "call")
+    g = gctx.mlmc_stdmc(gm, gp, 3, 4, 20000, 5, precision=64)
+    o = orc.stdmc(om, op, 3, 4, 20000, 5, nthreads=8)
+    assert abs(g["sum_y"] - o["sum_y"]) <= 1e-9 * abs(o["sum_y"])
+    assert g["cost"] == o["cost"]
+
+
+def test_user_stream(gctx):
+    import torch
+    s = torch.cuda.Stream()
+    gctx.set_stream(s)
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    a = gctx.mlmc_level(gm, gp, 2, 4, 5000, 1, precision=64)
+    gctx.set_stream(None)
+    b = gctx.mlmc_level(gm, gp, 2, 4, 5000, 1, precision=64)
+    assert abs(a["sum_y"] - b["sum_y"]) <= 1e-12 * abs(b["sum_y"])
