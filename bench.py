@@ -1,0 +1,153 @@
+"""Benchmark: adaptive MLMC on one MI355X, fine path-steps per second.
+
+One step = one complete adaptive MLMC estimate (every level sampled by the
+HIP level sampler, the fp64 driver update on the device) of the GBM European
+call (S0=100, r=0.05, sigma=0.2, T=1, K=100), M=4, fp32 paths with fp64 sums,
+one level per launch.  The target RMSE defaults to 2e-5*S0: with it the driver
+reaches about 10^8 samples at level 0, the scale that workload is described
+at (its listed RMSEs of 2e-3..5e-4*S0 need only 1.4e4..2.2e5 there).
+
+value = fine path steps computed by all steps / wall time of the K timed
+steps.  The JSON line also carries the roofline of the dominant kernel, timed
+with HIP events on the launch stream, the CPU oracle timed on a bounded sample
+of the same workload, and seconds to RMSE 1e-3*S0.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "seconds to RMSE 1e-3·S0 (learned-CV vs plain MLMC); fine path-steps/s"
+UNIT = "fine path-steps/s"
+
+# Algorithmic VALU operations per fine path step of the GBM call sampler with
+# M = 4 (Philox 10 + uniform/Box-Muller 5.5 + increment 1 + Euler step 2 +
+# coarse sum 1 + coarse step 0.5); derivation in the design doc.
+OPS_PER_FINE_STEP = 20.0
+# MI355X vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--eps", type=float, default=2e-5, help="target RMSE in units of S0")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU work for the oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tta", action="store_true", help="skip seconds-to-RMSE runs")
+    return ap.parse_args()
+
+
+def fine_steps_of(res, M):
+    return float(sum(n * M**l for l, n in enumerate(res["N"])))
+
+
+def cpu_baseline(ref_run, M, budget_s):
+    """The oracle, as it stands, on a bounded sample of the same levels."""
+    import oracle
+    from paper_1505_00965_amd import workloads as W
+    om, op = oracle.model(**W.GBM_MODEL), oracle.payoff(**W.CALL)
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    # calibrate on a small sample, then scale each level's count to the budget
+    probe = 2000
+    t0 = time.perf_counter()
+    oracle.level(om, op, 3, M, probe, 1, nthreads=cores)
+    rate = probe * (M**3 + M**2) / max(time.perf_counter() - t0, 1e-6)
+    total_cost = sum(n * (M**l + (M ** (l - 1) if l else 0)) for l, n in enumerate(ref_run["N"]))
+    scale = min(1.0, budget_s * rate / total_cost)
+    fine = 0.0
+    t0 = time.perf_counter()
+    for l, n in enumerate(ref_run["N"]):
+        nn = max(1, int(n * scale))
+        oracle.level(om, op, l, M, nn, 1, nthreads=cores)
+        fine += nn * M**l
+    dt = time.perf_counter() - t0
+    return {"value": fine / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": f"levels 0..{len(ref_run['N']) - 1} of one adaptive run with every N_l "
+                      f"scaled by {scale:.3g} ({fine:.3g} fine path steps, {dt:.1f} s, fp64)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build runs no cross-GPU work "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1505_00965_amd import mlmc, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    ctx = mlmc.Context(0)
+    stream = torch.cuda.current_stream()
+    ctx.set_stream(stream)
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    M = 4
+    eps = args.eps * W.S0
+
+    def step(seed):
+        return ctx.mlmc_run(gm, gp, eps, M=M, L_min=2, L_max=9, n_pilot=10000, seed=seed,
+                            precision=32)
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step(1 + i) for i in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = ctx.kernel_stats()
+    ctx.set_timing(False)
+
+    fine = sum(fine_steps_of(r, M) for r in runs)
+    value = fine / dt
+    # dominant kernel: the level whose launches took the most time
+    lv = max(range(16), key=lambda l: stats[l]["ms"])
+    s = stats[lv]
+    avg_ms = s["ms"] / max(1, s["launches"])
+    ops_per_launch = OPS_PER_FINE_STEP * s["fine_steps"] / max(1, s["launches"])
+    achieved = ops_per_launch / (avg_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                "kernel": f"level_kernel<GBM,call,fp32,M=4> at level {lv}",
+                "avg_launch_ms": avg_ms, "launches": s["launches"],
+                "fine_steps_per_launch": s["fine_steps"] / max(1, s["launches"])}
+
+    line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"adaptive MLMC, GBM European call S0=100 r=0.05 sigma=0.2 "
+                                   f"T=1 K=100, M=4, RMSE {args.eps:g}*S0, fp32 paths fp64 sums, "
+                                   f"one level per launch",
+                       "levels": runs[-1]["L"] + 1, "N_l": runs[-1]["N"],
+                       "estimate": runs[-1]["estimate"]},
+            "roofline": roofline}
+
+    if not args.no_tta:
+        tta = {}
+        for name, pd in (("gbm_call", W.CALL), ("gbm_asian", W.ASIAN)):
+            pp = mlmc.payoff(**pd)
+            ts = []
+            for seed in range(1, 6):
+                r = ctx.mlmc_run(gm, pp, 1e-3 * W.S0, M=M, seed=seed, precision=32)
+                ts.append(r["wall_s"])
+            ts.sort()
+            tta[f"plain_{name}"] = ts[len(ts) // 2]
+        line["seconds_to_rmse_1e-3_S0"] = tta
+
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(runs[-1], M, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -101,6 +101,22 @@ const char* mlmc_last_error(const mlmc_ctx* ctx);
  * choice.  Results do not depend on it (see determinism above).            */
 mlmc_status mlmc_set_launch(mlmc_ctx* ctx, int block, int ppt);
 
+/* Kernel timing with HIP events on the context's stream.  Slots:
+ *   0..15  level sampler launches at level l (per-level entry points and
+ *          per-level driver iterations), 16 persistent all-levels launches,
+ *   17     driver update kernel, 18 control-variate training steps.
+ * fine_steps / coarse_steps: path steps those launches computed.          */
+#define MLMC_STAT_SLOTS 20
+typedef struct {
+    uint64_t launches;
+    double ms;              /* summed event-measured duration */
+    double fine_steps, coarse_steps;
+} mlmc_kernel_stat;
+/* on != 0: start recording (clears the statistics); 0: stop. */
+mlmc_status mlmc_set_timing(mlmc_ctx* ctx, int on);
+/* Copy MLMC_STAT_SLOTS statistics into out (host array). */
+mlmc_status mlmc_kernel_stats(mlmc_ctx* ctx, mlmc_kernel_stat* out);
+
 /* Level estimator sums (eqs. (eq:mlmc:Yzero), (eq:Yldef)).
  *   l >= 0, M in {2, 4}, M^l <= 4^8 * 4 (262144 steps), N >= 0 paths
  *   seed: Philox key; path_offset: index of the first sample, so further
@@ -139,6 +155,24 @@ mlmc_status mlmc_normals(mlmc_ctx* ctx, uint64_t seed, int level, uint64_t s0, u
 mlmc_status mlmc_stdmc(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
                        int L, int M, uint64_t N, uint64_t seed, uint64_t path_offset,
                        int precision, mlmc_level_result* out);
+
+/* Persistent all-levels form (fp32 paths).  Samples every (payoff, level)
+ * of one MLMC iteration -- levels 0..L, npayoffs payoffs on one model -- in
+ * ONE launch of a persistent kernel, replayed from a captured HIP graph:
+ * a plan kernel cuts the samples into items of about equal cost (deepest
+ * level first), resident blocks take items from an atomic counter.
+ *   N[k * (L+1) + l]: samples of payoff k at level l (0 allowed);
+ *   offsets: same layout, first sample index (NULL = all 0);
+ *   out[k * (L+1) + l]: the level sums, identical in law (and, up to fp64
+ *   summation order, in value) to mlmc_level with the same arguments.
+ * 1 <= npayoffs <= 4, L < 16.                                               */
+mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoffs,
+                              int npayoffs, int M, int L, const uint64_t* N,
+                              const uint64_t* offsets, uint64_t seed, mlmc_level_result* out);
+/* Launch shape of the persistent kernel: block in {64..1024}, ppt in
+ * {1,2,4}, blocks_per_cu resident blocks per compute unit; block = 0 returns
+ * to the tuned/default shape.                                               */
+mlmc_status mlmc_set_persistent_launch(mlmc_ctx* ctx, int block, int ppt, int blocks_per_cu);
 
 /* ---------------------------------------------------------------- driver
  * Sample counts N_l = ceil(2 eps^-2 sqrt(V_l/C_l) sum_k sqrt(V_k C_k)) for

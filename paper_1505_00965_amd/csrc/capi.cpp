@@ -109,6 +109,56 @@ static LevelArgs<Real> make_args(const mlmc_model& m, const mlmc_payoff& p, int 
     return a;
 }
 
+static hipEvent_t pool_event(mlmc_ctx* ctx)
+{
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int timed_begin(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_steps)
+{
+    if (!ctx->timing) return -1;
+    mlmc_ctx::Timed t;
+    t.start = pool_event(ctx);
+    t.stop = pool_event(ctx);
+    if (!t.start || !t.stop) return -1;
+    t.slot = slot;
+    t.fine_steps = fine_steps;
+    t.coarse_steps = coarse_steps;
+    hipEventRecord(t.start, ctx->stream);
+    ctx->pending.push_back(t);
+    return (int)ctx->pending.size() - 1;
+}
+
+void timed_end(mlmc_ctx* ctx, int idx)
+{
+    if (idx < 0) return;
+    hipEventRecord(ctx->pending[idx].stop, ctx->stream);
+}
+
+void harvest_timing(mlmc_ctx* ctx)
+{
+    for (auto& t : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+            mlmc_kernel_stat& s = ctx->stats[t.slot];
+            s.launches += 1;
+            s.ms += ms;
+            s.fine_steps += t.fine_steps;
+            s.coarse_steps += t.coarse_steps;
+        }
+        ctx->event_pool.push_back(t.start);
+        ctx->event_pool.push_back(t.stop);
+    }
+    ctx->pending.clear();
+}
+
 mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
                           uint64_t N, uint64_t seed, uint64_t offset, int precision, uint32_t stream,
                           int coupled, LevelAcc* acc, double* d_pf, double* d_pc, const mlmc_cv* cv)
@@ -116,6 +166,9 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
     if (N == 0) return MLMC_OK;
     if (cv) return fail(ctx, MLMC_EINVAL, "control variate not available in this build");
     const LaunchShape shape = choose_shape(ctx, m, p, l, M, precision, N);
+    const double nf = (double)level_steps(l, M);
+    const int tix = timed_begin(ctx, l < 16 ? l : 15, (double)N * nf,
+                                (coupled && l > 0) ? (double)N * nf / M : 0.0);
     hipError_t e;
     if (precision == 64) {
         auto a = make_args<double>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
@@ -124,6 +177,7 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
         auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
         e = launch_level(m, p, M, 32, &a, shape, ctx->stream);
     }
+    timed_end(ctx, tix);
     if (e != hipSuccess) return hip_fail(ctx, e, "level kernel launch");
     return MLMC_OK;
 }
@@ -134,6 +188,7 @@ static mlmc_status finish_level(mlmc_ctx* ctx, uint64_t N, int l, int M, int cou
     MLMC_HIP(ctx, hipMemcpyAsync(ctx->h_acc, ctx->d_acc, sizeof(LevelAcc), hipMemcpyDeviceToHost,
                                  ctx->stream));
     MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    harvest_timing(ctx);
     const LevelAcc& r = ctx->h_acc[0];
     if (out) {
         out->sum_y = r.sum[0];
@@ -196,6 +251,12 @@ mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx)
     hipSetDevice(ctx->device);
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     mlmc_driver_free(ctx);
+    free_persistent(ctx);
+    for (auto& t : ctx->pending) {
+        hipEventDestroy(t.start);
+        hipEventDestroy(t.stop);
+    }
+    for (auto e : ctx->event_pool) hipEventDestroy(e);
     if (ctx->d_acc) hipFree(ctx->d_acc);
     if (ctx->h_acc) hipHostFree(ctx->h_acc);
     if (ctx->d_tmp) hipFree(ctx->d_tmp);
@@ -215,6 +276,26 @@ mlmc_status mlmc_set_stream(mlmc_ctx* ctx, void* hip_stream)
 const char* mlmc_last_error(const mlmc_ctx* ctx)
 {
     return ctx ? ctx->err.c_str() : "null context";
+}
+
+mlmc_status mlmc_set_timing(mlmc_ctx* ctx, int on)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    harvest_timing(ctx);
+    ctx->timing = on ? 1 : 0;
+    if (on)
+        for (auto& s : ctx->stats) s = mlmc_kernel_stat{};
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_kernel_stats(mlmc_ctx* ctx, mlmc_kernel_stat* out)
+{
+    if (!ctx || !out) return MLMC_EINVAL;
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    harvest_timing(ctx);
+    for (int i = 0; i < MLMC_STAT_SLOTS; ++i) out[i] = ctx->stats[i];
+    return MLMC_OK;
 }
 
 mlmc_status mlmc_set_launch(mlmc_ctx* ctx, int block, int ppt)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/mlmc.h"
 #include "level.hpp"
@@ -14,6 +15,8 @@ struct mlmc_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int launch_block = 0, launch_ppt = 0;   // 0: tuned/default
+    int persist_block = 0, persist_ppt = 0, persist_bpc = 0;
+    void* persist = nullptr;                // persistent-form buffers (persistent.hip)
     // Level accumulators: kAccSlots records (payoff x level) + host mirror.
     mlmc::LevelAcc* d_acc = nullptr;
     mlmc::LevelAcc* h_acc = nullptr;
@@ -22,6 +25,16 @@ struct mlmc_ctx {
     void* h_drv = nullptr;
     double* d_tmp = nullptr;                // small fp64 scratch (optimal_n)
     double* h_tmp = nullptr;
+    // kernel timing (mlmc_set_timing)
+    struct Timed {
+        hipEvent_t start, stop;
+        int slot;
+        double fine_steps, coarse_steps;
+    };
+    int timing = 0;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<Timed> pending;
+    mlmc_kernel_stat stats[MLMC_STAT_SLOTS] = {};
 };
 
 namespace mlmc {
@@ -51,6 +64,15 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
                           const mlmc_cv* cv);
 // Zero `n` records with a fill kernel (safe inside graph capture).
 hipError_t zero_records(LevelAcc* acc, int n, hipStream_t st);
+
+// Bracket a launch with timing events when timing is on (no-op otherwise).
+// timed_begin returns an index for timed_end, or -1.
+int timed_begin(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_steps);
+void timed_end(mlmc_ctx* ctx, int idx);
+// After the stream has been synchronised: fold finished events into stats.
+void harvest_timing(mlmc_ctx* ctx);
+
+void free_persistent(mlmc_ctx* ctx);
 
 hipError_t launch_philox_words(uint64_t seed, int level, uint64_t s0, uint32_t stream,
                                uint32_t nblocks, uint64_t npaths, uint32_t* out, hipStream_t st);

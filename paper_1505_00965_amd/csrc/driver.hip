@@ -244,10 +244,13 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
                                    nullptr, nullptr, o.cv);
                 if (st) return st;
             }
+            const int tix = timed_begin(ctx, 17, 0.0, 0.0);
             MLMC_HIP(ctx, launch_driver_update(d, ctx->stream));
+            timed_end(ctx, tix);
             MLMC_HIP(ctx, hipMemcpyAsync(h, d, sizeof(DriverState), hipMemcpyDeviceToHost,
                                          ctx->stream));
             MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            harvest_timing(ctx);
             if (h->done) break;
         }
     }

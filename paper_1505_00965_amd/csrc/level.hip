@@ -11,6 +11,7 @@
 #include <cmath>
 
 #include "level.hpp"
+#include "sampler_impl.hpp"
 
 namespace mlmc {
 
@@ -46,66 +47,6 @@ StepParams<Real> make_step_params(const mlmc_model& m, const mlmc_payoff& p, int
 template StepParams<float> make_step_params<float>(const mlmc_model&, const mlmc_payoff&, int, int);
 template StepParams<double> make_step_params<double>(const mlmc_model&, const mlmc_payoff&, int, int);
 
-// Advance PPT coupled pairs through all fine steps of the level.
-template <int MODEL, int PAYOFF, typename Real, int M, int PPT>
-__device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_t (&s)[PPT],
-                                         PathPair<Real> (&q)[PPT])
-{
-    const StepParams<Real>& P = a.P;
-    PathKey key[PPT], bkey[PPT];
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        key[p] = make_path_key(a.seed, a.l, s[p], a.stream);
-        bkey[p] = make_path_key(a.seed, a.l, s[p], a.stream + 1u);
-        init_pair<Real, MODEL, PAYOFF>(q[p], P);
-    }
-    const bool coupled = a.coupled && a.l > 0;
-    const bool full = a.nf >= 4;
-    for (uint32_t g = 0; g < a.ngroups; ++g) {
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            Real dw1[4], dwp[4], e[4];
-            if (MODEL == kGBM) {
-                const u32x4 w = path_block(key[p], g);
-                Real z0, z1, z2, z3;
-                box_muller(w.x, w.y, z0, z1);
-                box_muller(w.z, w.w, z2, z3);
-                dw1[0] = P.sqh * z0; dw1[1] = P.sqh * z1;
-                dw1[2] = P.sqh * z2; dw1[3] = P.sqh * z3;
-                dwp[0] = dwp[1] = dwp[2] = dwp[3] = Real(0);
-            } else {
-                const u32x4 wa = path_block(key[p], 2 * g);
-                const u32x4 wb = path_block(key[p], 2 * g + 1);
-                Real z0, z1, z2, z3, z4, z5, z6, z7;
-                box_muller(wa.x, wa.y, z0, z1);
-                box_muller(wa.z, wa.w, z2, z3);
-                box_muller(wb.x, wb.y, z4, z5);
-                box_muller(wb.z, wb.w, z6, z7);
-                dw1[0] = P.sqh * z0; dwp[0] = P.sqh * z1;
-                dw1[1] = P.sqh * z2; dwp[1] = P.sqh * z3;
-                dw1[2] = P.sqh * z4; dwp[2] = P.sqh * z5;
-                dw1[3] = P.sqh * z6; dwp[3] = P.sqh * z7;
-            }
-            if (PAYOFF == kLookback) {
-                const u32x4 u = path_block(bkey[p], g);
-                e[0] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.x));
-                e[1] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.y));
-                e[2] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.z));
-                e[3] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.w));
-            } else {
-                e[0] = e[1] = e[2] = e[3] = Real(0);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (full || (int)(4 * g + k) < a.nf) {
-                    fine_step<Real, MODEL, PAYOFF>(q[p], P, dw1[k], dwp[k], e[k], k % M, coupled);
-                    if (coupled && ((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(q[p], P);
-                }
-            }
-        }
-    }
-}
-
 template <int MODEL, int PAYOFF, typename Real, int M, int PPT>
 __global__ __launch_bounds__(1024) void level_kernel(LevelArgs<Real> a)
 {
@@ -113,42 +54,8 @@ __global__ __launch_bounds__(1024) void level_kernel(LevelArgs<Real> a)
     unsigned nonfinite = 0;
     const uint64_t chunk = (uint64_t)blockDim.x * PPT;
     const uint64_t nchunks = (a.N + chunk - 1) / chunk;
-    const bool coupled = a.coupled && a.l > 0;
-    const Real dtf = a.P.h, dtc = a.P.H;
-    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        uint64_t idx[PPT], s[PPT];
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            idx[p] = c * chunk + (uint64_t)p * blockDim.x + threadIdx.x;
-            s[p] = a.offset + idx[p];
-        }
-        PathPair<Real> q[PPT];
-        simulate<MODEL, PAYOFF, Real, M, PPT>(a, s, q);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            const Real pf = payoff_value<Real, PAYOFF>(a.P, q[p].S, q[p].asum, q[p].acomp, q[p].mn, dtf);
-            const Real pc = coupled ? payoff_value<Real, PAYOFF>(a.P, q[p].Sc, q[p].csum, q[p].ccomp,
-                                                                q[p].mnc, dtc)
-                                    : Real(0);
-            if (idx[p] >= a.N) continue;
-            const double df = (double)pf, dc = (double)pc;
-            if (a.pf_out) {
-                a.pf_out[idx[p]] = df;
-                a.pc_out[idx[p]] = dc;
-            }
-            const double y = df - dc;
-            if (!isfinite(y)) {
-                ++nonfinite;
-                continue;
-            }
-            sums[0] += y;
-            sums[1] = __builtin_fma(y, y, sums[1]);
-            sums[2] += df;
-            sums[3] = __builtin_fma(df, df, sums[3]);
-            sums[4] += dc;
-            sums[5] = __builtin_fma(dc, dc, sums[5]);
-        }
-    }
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+        process_chunk<MODEL, PAYOFF, Real, M, PPT>(a, c * chunk, sums, nonfinite);
     block_reduce_add(sums, nonfinite, a.acc);
 }
 

@@ -1,13 +1,438 @@
-// Persistent all-levels form (work table + graph): see run_persistent.
+// Persistent all-levels sampler: every level (and payoff) of one MLMC
+// iteration in a single launch, captured once in a HIP graph.
+//
+// Levels are independent (Sec. 5, after eq. (eq:Yldef)), so one iteration's
+// work is a set of (payoff, level, sample range) items.  Their costs differ by
+// orders of magnitude: level l costs M^l + M^(l-1) steps per sample (the
+// paper's cost measure, Sec. 3) and N_l falls with l.  A plan kernel cuts the
+// outstanding samples into items of roughly equal cost, deepest levels first
+// (longest-processing-time order), and a resident grid of blocks takes items
+// from an atomic counter until none are left, so cheap levels fill in around
+// the long deep-level items.  Every parameter the launches read lives in
+// device memory and is rewritten between launches (by the driver kernel or
+// by host copies), so the graph is captured once and replayed.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
 #include "context.hpp"
 #include "driver.hpp"
+#include "sampler_impl.hpp"
 
 namespace mlmc {
 
-mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model&, const mlmc_payoff&,
-                           const mlmc_run_opts&, DriverState*, DriverState*)
+constexpr int kMaxSlots = 4;          // payoffs per batch
+constexpr int kItemsPerBlock = 4;     // target items per resident block
+constexpr unsigned kItemsPerPair = 1024;
+constexpr unsigned kMaxItems = kMaxSlots * kMaxLevels * kItemsPerPair;
+
+struct WorkItem {
+    uint64_t first;     // first sample index of the range
+    uint32_t n;         // number of samples
+    uint16_t level;
+    uint8_t slot;       // payoff slot
+    uint8_t pad;
+};
+
+// Device-resident batch description (rewritten before each launch).
+struct BatchDesc {
+    int nslots, L, M, pad;
+    int payoff_kind[kMaxSlots];
+    StepParams<float> params[kMaxSlots][kMaxLevels];
+    uint64_t seed;
+    // outstanding samples and their first index, per (slot, level); for the
+    // driver these alias DriverState::dN / n (slot 0 only)
+    const double* dN;
+    const double* offset;
+    LevelAcc* acc;                    // acc[slot * kMaxLevels + level]
+    WorkItem* items;
+    unsigned* head;                   // work dispenser
+    unsigned* count;                  // number of items
+    unsigned resident_blocks;         // grid size of the sampler
+    unsigned chunk;                   // blockDim * PPT of the sampler
+};
+
+// One thread plans every item of the batch.
+__global__ void plan_kernel(const BatchDesc* d)
 {
-    return fail(ctx, MLMC_EINVAL, "persistent form not available yet");
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int L = d->L, M = d->M;
+    double total = 0.0;
+    for (int s = 0; s < d->nslots; ++s)
+        for (int l = 0; l <= L; ++l) {
+            const double nf = pow((double)M, (double)l);
+            total += d->dN[s * kMaxLevels + l] * (nf + (l ? nf / M : 0.0));
+        }
+    double target = total / ((double)d->resident_blocks * kItemsPerBlock);
+    unsigned count = 0;
+    // deepest (longest) items first
+    for (int l = L; l >= 0; --l) {
+        const double nf = pow((double)M, (double)l);
+        const double per = nf + (l ? nf / M : 0.0);
+        double want = target / per;
+        uint64_t paths = (uint64_t)want;
+        // whole chunks where possible; small items at least one wave
+        if (paths >= d->chunk) paths = (paths / d->chunk) * d->chunk;
+        else if (paths < 64) paths = 64;
+        if (paths > (1ull << 31)) paths = 1ull << 31;   // item counts fit 32 bits
+        for (int s = 0; s < d->nslots; ++s) {
+            uint64_t left = (uint64_t)d->dN[s * kMaxLevels + l];
+            uint64_t first = (uint64_t)d->offset[s * kMaxLevels + l];
+            // at most kItemsPerPair items per (slot, level), so the table
+            // (kMaxSlots * kMaxLevels * kItemsPerPair = kMaxItems) never fills
+            const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
+            const uint64_t per_item = paths > min_items ? paths : min_items;
+            while (left > 0) {
+                const uint64_t n = left < per_item ? left : per_item;
+                WorkItem w;
+                w.first = first;
+                w.n = (uint32_t)n;
+                w.level = (uint16_t)l;
+                w.slot = (uint8_t)s;
+                w.pad = 0;
+                d->items[count++] = w;
+                first += n;
+                left -= n;
+            }
+        }
+    }
+    *d->count = count;
+    *d->head = 0;
+}
+
+template <int MODEL, int PAYOFF, int M, int PPT>
+__device__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[kNumSums],
+                         unsigned& nonfinite)
+{
+    LevelArgs<float> a;
+    a.P = d->params[w.slot][w.level];
+    a.seed = d->seed;
+    a.offset = w.first;
+    a.N = w.n;
+    a.l = w.level;
+    int nf = 1;
+    for (int i = 0; i < a.l; ++i) nf *= M;
+    a.nf = nf;
+    a.ngroups = (uint32_t)((nf + 3) / 4);
+    a.stream = kStreamNormal;
+    a.acc = nullptr;
+    a.pf_out = a.pc_out = nullptr;
+    a.coupled = 1;
+    if (w.n <= blockDim.x) {
+        // fewer samples than lanes: one per lane
+        process_chunk<MODEL, PAYOFF, float, M, 1>(a, 0, sums, nonfinite);
+    } else {
+        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
+        for (uint64_t base = 0; base < w.n; base += chunk)
+            process_chunk<MODEL, PAYOFF, float, M, PPT>(a, base, sums, nonfinite);
+    }
+}
+
+template <int MODEL, int M, int PPT>
+__global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
+{
+    __shared__ unsigned s_item;
+    const unsigned count = *d->count;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(d->head, 1u);
+        __syncthreads();
+        const unsigned it = s_item;
+        __syncthreads();
+        if (it >= count) break;
+        const WorkItem w = d->items[it];
+        double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+        unsigned nonfinite = 0;
+        switch (d->payoff_kind[w.slot]) {
+        case kCall: run_item<MODEL, kCall, M, PPT>(d, w, sums, nonfinite); break;
+        case kAsian: run_item<MODEL, kAsian, M, PPT>(d, w, sums, nonfinite); break;
+        case kLookback: run_item<MODEL, kLookback, M, PPT>(d, w, sums, nonfinite); break;
+        default: run_item<MODEL, kDigital, M, PPT>(d, w, sums, nonfinite); break;
+        }
+        block_reduce_add(sums, nonfinite, &d->acc[w.slot * kMaxLevels + w.level]);
+    }
+}
+
+using PersistentFn = void (*)(const BatchDesc*);
+
+template <int MODEL, int M>
+static PersistentFn pick_ppt(int ppt)
+{
+    switch (ppt) {
+    case 1: return persistent_kernel<MODEL, M, 1>;
+    case 2: return persistent_kernel<MODEL, M, 2>;
+    default: return persistent_kernel<MODEL, M, 4>;
+    }
+}
+
+static PersistentFn pick_persistent(int model, int M, int ppt)
+{
+    if (model == kGBM) return M == 2 ? pick_ppt<kGBM, 2>(ppt) : pick_ppt<kGBM, 4>(ppt);
+    return M == 2 ? pick_ppt<kHeston, 2>(ppt) : pick_ppt<kHeston, 4>(ppt);
+}
+
+hipError_t launch_driver_update(DriverState* st, hipStream_t stream);
+
+// Device buffers of the persistent form, owned by the context.
+struct PersistentBufs {
+    BatchDesc* d_desc = nullptr;
+    BatchDesc* h_desc = nullptr;
+    WorkItem* d_items = nullptr;
+    unsigned* d_counters = nullptr;   // head, count
+    LevelAcc* d_acc = nullptr;        // batch records [kMaxSlots][kMaxLevels]
+    double* d_req = nullptr;          // dN[kMaxSlots][kMaxLevels], offset[...]
+    double* h_req = nullptr;
+    hipGraphExec_t graph = nullptr;   // cached batch graph
+    int graph_key[5] = {-1, -1, -1, -1, -1};
+};
+
+static PersistentBufs* bufs_of(mlmc_ctx* ctx);
+
+struct PersistentShape {
+    int block, ppt, blocks_per_cu;
+};
+
+static PersistentShape persistent_shape(const mlmc_ctx* ctx)
+{
+    PersistentShape s;
+    s.block = ctx->persist_block ? ctx->persist_block : 256;
+    s.ppt = ctx->persist_ppt ? ctx->persist_ppt : 2;
+    s.blocks_per_cu = ctx->persist_bpc ? ctx->persist_bpc : 4;
+    return s;
+}
+
+static mlmc_status ensure_bufs(mlmc_ctx* ctx)
+{
+    if (ctx->persist) return MLMC_OK;
+    auto* b = new (std::nothrow) PersistentBufs();
+    if (!b) return fail(ctx, MLMC_ENOMEM, "host allocation failed");
+    ctx->persist = b;
+    MLMC_HIP(ctx, hipMalloc(&b->d_desc, sizeof(BatchDesc)));
+    MLMC_HIP(ctx, hipHostMalloc(&b->h_desc, sizeof(BatchDesc)));
+    MLMC_HIP(ctx, hipMalloc(&b->d_items, sizeof(WorkItem) * kMaxItems));
+    MLMC_HIP(ctx, hipMalloc(&b->d_counters, sizeof(unsigned) * 4));
+    MLMC_HIP(ctx, hipMalloc(&b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels));
+    MLMC_HIP(ctx, hipMalloc(&b->d_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels));
+    MLMC_HIP(ctx, hipHostMalloc(&b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels));
+    return MLMC_OK;
+}
+
+static PersistentBufs* bufs_of(mlmc_ctx* ctx) { return (PersistentBufs*)ctx->persist; }
+
+void free_persistent(mlmc_ctx* ctx)
+{
+    auto* b = bufs_of(ctx);
+    if (!b) return;
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    if (b->d_desc) hipFree(b->d_desc);
+    if (b->h_desc) hipHostFree(b->h_desc);
+    if (b->d_items) hipFree(b->d_items);
+    if (b->d_counters) hipFree(b->d_counters);
+    if (b->d_acc) hipFree(b->d_acc);
+    if (b->d_req) hipFree(b->d_req);
+    if (b->h_req) hipHostFree(b->h_req);
+    delete b;
+    ctx->persist = nullptr;
+}
+
+// Fill the host copy of the descriptor (parameters for every slot and level).
+static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const mlmc_payoff* p,
+                      int np, int L, int M, uint64_t seed, const double* dN, const double* off,
+                      LevelAcc* acc)
+{
+    auto* b = bufs_of(ctx);
+    const PersistentShape s = persistent_shape(ctx);
+    std::memset(h, 0, sizeof(*h));
+    h->nslots = np;
+    h->L = L;
+    h->M = M;
+    for (int k = 0; k < np; ++k) {
+        h->payoff_kind[k] = p[k].kind;
+        for (int l = 0; l <= L; ++l) h->params[k][l] = make_step_params<float>(m, p[k], l, M);
+    }
+    h->seed = seed;
+    h->dN = dN;
+    h->offset = off;
+    h->acc = acc;
+    h->items = b->d_items;
+    h->head = b->d_counters;
+    h->count = b->d_counters + 1;
+    h->resident_blocks = (unsigned)(ctx->num_cu * s.blocks_per_cu);
+    h->chunk = (unsigned)(s.block * s.ppt);
+}
+
+// Capture [prologue?] -> plan -> persistent -> [epilogue] into a graph.
+static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
+                           DriverState* driver, hipGraphExec_t* out)
+{
+    auto* b = bufs_of(ctx);
+    const PersistentShape s = persistent_shape(ctx);
+    hipStream_t cs;
+    MLMC_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess && zero_batch) e = zero_records(b->d_acc, kMaxSlots * kMaxLevels, cs);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, cs, (const BatchDesc*)b->d_desc);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pick_persistent(model, M, s.ppt), dim3(ctx->num_cu * s.blocks_per_cu),
+                           dim3(s.block), 0, cs, (const BatchDesc*)b->d_desc);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && driver) e = launch_driver_update(driver, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(ctx, e, "persistent graph capture");
+    return MLMC_OK;
+}
+
+// mlmc_run with persistent = 1: one graph launch per driver iteration.
+mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p,
+                           const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st)
+{
+    if (o.precision != 32) return fail(ctx, MLMC_EINVAL, "the persistent form runs fp32 paths");
+    if (o.cv) return fail(ctx, MLMC_EINVAL, "the persistent form runs plain MLMC");
+    mlmc_status st = ensure_bufs(ctx);
+    if (st) return st;
+    auto* b = bufs_of(ctx);
+    fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, o.seed, d_st->dN, d_st->n, d_st->batch);
+    MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
+                                 ctx->stream));
+    hipGraphExec_t g = nullptr;
+    st = capture(ctx, m.kind, o.M, false, d_st, &g);
+    if (st) return st;
+    for (;;) {
+        const int tix = timed_begin(ctx, 16, 0.0, 0.0);
+        hipError_t e = hipGraphLaunch(g, ctx->stream);
+        timed_end(ctx, tix);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_st, d_st, sizeof(DriverState), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            hipGraphExecDestroy(g);
+            return hip_fail(ctx, e, "persistent iteration");
+        }
+        harvest_timing(ctx);
+        if (h_st->done) break;
+    }
+    hipGraphExecDestroy(g);
+    return MLMC_OK;
 }
 
 }  // namespace mlmc
+
+using namespace mlmc;
+
+extern "C" {
+
+mlmc_status mlmc_set_persistent_launch(mlmc_ctx* ctx, int block, int ppt, int blocks_per_cu)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (block == 0) {
+        ctx->persist_block = ctx->persist_ppt = ctx->persist_bpc = 0;
+    } else {
+        if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+            return fail(ctx, MLMC_EINVAL, "block must be 64, 128, 256, 512 or 1024");
+        if (ppt != 1 && ppt != 2 && ppt != 4) return fail(ctx, MLMC_EINVAL, "ppt must be 1, 2 or 4");
+        if (blocks_per_cu < 1 || blocks_per_cu * block > 4096)
+            return fail(ctx, MLMC_EINVAL, "blocks_per_cu * block must be in 1..4096 threads");
+        ctx->persist_block = block;
+        ctx->persist_ppt = ppt;
+        ctx->persist_bpc = blocks_per_cu;
+    }
+    if (auto* b = bufs_of(ctx)) {
+        if (b->graph) hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        b->graph_key[0] = -1;
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoffs,
+                              int npayoffs, int M, int L, const uint64_t* N,
+                              const uint64_t* offsets, uint64_t seed, mlmc_level_result* out)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (!payoffs || !N || !out) return fail(ctx, MLMC_EINVAL, "payoffs, N and out must not be NULL");
+    if (npayoffs < 1 || npayoffs > kMaxSlots)
+        return fail(ctx, MLMC_EINVAL, "npayoffs must be in 1..4");
+    mlmc_status st = MLMC_OK;
+    for (int k = 0; k < npayoffs && !st; ++k) st = check_level_args(ctx, model, &payoffs[k], L, M, 32);
+    if (st) return st;
+    if (L >= kMaxLevels) return fail(ctx, MLMC_EINVAL, "L must be < 16");
+    for (int i = 0; i < npayoffs * (L + 1); ++i) {
+        if (N[i] > (1ull << 40)) return fail(ctx, MLMC_EINVAL, "N too large (max 2^40 per level)");
+        if (((offsets ? offsets[i] : 0) + N[i]) >> 56)
+            return fail(ctx, MLMC_EINVAL, "path index beyond 2^56");
+    }
+    ctx->err.clear();
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    st = ensure_bufs(ctx);
+    if (st) return st;
+    auto* b = bufs_of(ctx);
+    // request: dN and offsets per (slot, level)
+    std::memset(b->h_req, 0, sizeof(double) * 2 * kMaxSlots * kMaxLevels);
+    for (int k = 0; k < npayoffs; ++k)
+        for (int l = 0; l <= L; ++l) {
+            b->h_req[k * kMaxLevels + l] = (double)N[k * (L + 1) + l];
+            b->h_req[kMaxSlots * kMaxLevels + k * kMaxLevels + l] =
+                offsets ? (double)offsets[k * (L + 1) + l] : 0.0;
+        }
+    fill_desc(ctx, b->h_desc, *model, payoffs, npayoffs, L, M, seed, b->d_req,
+              b->d_req + kMaxSlots * kMaxLevels, b->d_acc);
+    MLMC_HIP(ctx, hipMemcpyAsync(b->d_req, b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels,
+                                 hipMemcpyHostToDevice, ctx->stream));
+    MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
+                                 ctx->stream));
+    const PersistentShape s = persistent_shape(ctx);
+    const int key[5] = {model->kind, M, s.block, s.ppt, s.blocks_per_cu};
+    if (!b->graph || std::memcmp(key, b->graph_key, sizeof(key)) != 0) {
+        if (b->graph) hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        st = capture(ctx, model->kind, M, true, nullptr, &b->graph);
+        if (st) return st;
+        std::memcpy(b->graph_key, key, sizeof(key));
+    }
+    double fine = 0.0, coarse = 0.0;
+    for (int k = 0; k < npayoffs; ++k)
+        for (int l = 0; l <= L; ++l) {
+            const double nf = std::pow((double)M, (double)l);
+            fine += (double)N[k * (L + 1) + l] * nf;
+            coarse += l ? (double)N[k * (L + 1) + l] * nf / M : 0.0;
+        }
+    const int tix = timed_begin(ctx, 16, fine, coarse);
+    MLMC_HIP(ctx, hipGraphLaunch(b->graph, ctx->stream));
+    timed_end(ctx, tix);
+    LevelAcc* h_acc = ctx->h_acc;   // kAccSlots >= kMaxSlots * kMaxLevels
+    MLMC_HIP(ctx, hipMemcpyAsync(h_acc, b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels,
+                                 hipMemcpyDeviceToHost, ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    harvest_timing(ctx);
+    uint64_t nonfinite = 0;
+    for (int k = 0; k < npayoffs; ++k)
+        for (int l = 0; l <= L; ++l) {
+            const LevelAcc& r = h_acc[k * kMaxLevels + l];
+            mlmc_level_result& o = out[k * (L + 1) + l];
+            o.sum_y = r.sum[0];
+            o.sum_y2 = r.sum[1];
+            o.sum_pf = r.sum[2];
+            o.sum_pf2 = r.sum[3];
+            o.sum_pc = r.sum[4];
+            o.sum_pc2 = r.sum[5];
+            const double nf = std::pow((double)M, (double)l);
+            o.n = N[k * (L + 1) + l];
+            o.cost = (double)o.n * (l ? nf + nf / M : 1.0);
+            o.n_nonfinite = r.n_nonfinite;
+            nonfinite += r.n_nonfinite;
+        }
+    if (nonfinite) return fail(ctx, MLMC_ENONFINITE, "non-finite samples left out of the sums");
+    return MLMC_OK;
+}
+
+}  // extern "C"

@@ -19,8 +19,11 @@ MAX_LEVELS = 16
 EXPORTED = [
     "mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_set_stream", "mlmc_last_error",
     "mlmc_set_launch", "mlmc_level", "mlmc_level_paths", "mlmc_philox_words", "mlmc_normals",
-    "mlmc_stdmc", "mlmc_optimal_n", "mlmc_run",
+    "mlmc_stdmc", "mlmc_optimal_n", "mlmc_run", "mlmc_set_timing", "mlmc_kernel_stats",
+    "mlmc_levels_batch", "mlmc_set_persistent_launch",
 ]
+STAT_SLOTS = 20
+STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
 
 
 class MLMCError(RuntimeError):
@@ -47,6 +50,11 @@ class LevelResult(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("ms", C.c_double), ("fine_steps", C.c_double),
+                ("coarse_steps", C.c_double)]
 
 
 class RunOpts(C.Structure):
@@ -103,6 +111,11 @@ def lib():
     L.mlmc_stdmc.argtypes = [vp, M_, P_, i32, i32, u64, u64, u64, i32, C.POINTER(LevelResult)]
     L.mlmc_optimal_n.argtypes = [vp, i32, C.POINTER(d), C.POINTER(d), d, C.POINTER(d)]
     L.mlmc_run.argtypes = [vp, M_, P_, C.POINTER(RunOpts), C.POINTER(RunResult)]
+    L.mlmc_levels_batch.argtypes = [vp, M_, P_, i32, i32, i32, C.POINTER(u64), C.POINTER(u64),
+                                    u64, C.POINTER(LevelResult)]
+    L.mlmc_set_persistent_launch.argtypes = [vp, i32, i32, i32]
+    L.mlmc_set_timing.argtypes = [vp, i32]
+    L.mlmc_kernel_stats.argtypes = [vp, C.POINTER(KernelStat)]
     for name in EXPORTED:
         if name != "mlmc_last_error":
             getattr(L, name).restype = i32
@@ -170,6 +183,15 @@ class Context:
         raw = None if stream is None else getattr(stream, "cuda_stream", stream)
         self._check(self._lib.mlmc_set_stream(self.h, raw))
 
+    def set_timing(self, on=True):
+        self._check(self._lib.mlmc_set_timing(self.h, int(on)))
+
+    def kernel_stats(self):
+        """Per-slot {launches, ms, fine_steps, coarse_steps} (slots 0..15 = level)."""
+        arr = (KernelStat * STAT_SLOTS)()
+        self._check(self._lib.mlmc_kernel_stats(self.h, arr))
+        return [{k: getattr(a, k) for k, _ in KernelStat._fields_} for a in arr]
+
     def set_launch(self, block=0, ppt=0):
         self._check(self._lib.mlmc_set_launch(self.h, block, ppt))
 
@@ -203,6 +225,25 @@ class Context:
         self._check(self._lib.mlmc_stdmc(self.h, C.byref(m), C.byref(p), L, M, N, seed,
                                          path_offset, precision, C.byref(r)))
         return r.as_dict()
+
+    def mlmc_levels_batch(self, m, payoffs, M, L, N, seed, offsets=None, allow_nonfinite=False):
+        """payoffs: list of Payoff; N[k][l]; returns results[k][l] dicts."""
+        npay = len(payoffs)
+        P = (Payoff * npay)(*payoffs)
+        flat = [int(N[k][l]) for k in range(npay) for l in range(L + 1)]
+        Na = (C.c_uint64 * len(flat))(*flat)
+        Oa = None
+        if offsets is not None:
+            of = [int(offsets[k][l]) for k in range(npay) for l in range(L + 1)]
+            Oa = (C.c_uint64 * len(of))(*of)
+        R = (LevelResult * len(flat))()
+        allow = (MLMC_OK, MLMC_ENONFINITE) if allow_nonfinite else (MLMC_OK,)
+        self._check(self._lib.mlmc_levels_batch(self.h, C.byref(m), P, npay, M, L, Na, Oa, seed, R),
+                    allow)
+        return [[R[k * (L + 1) + l].as_dict() for l in range(L + 1)] for k in range(npay)]
+
+    def set_persistent_launch(self, block=0, ppt=0, blocks_per_cu=0):
+        self._check(self._lib.mlmc_set_persistent_launch(self.h, block, ppt, blocks_per_cu))
 
     def mlmc_optimal_n(self, V, Cl, eps):
         L = len(V) - 1

@@ -1,0 +1,79 @@
+"""GPU adaptive driver vs the oracle's driver and the closed form.
+
+The N_l arithmetic runs on the device in fp64 and must equal the oracle's
+bit for bit; a whole fp64 run must take the same decisions as the oracle's
+(same L, same N_l, same iterations); fp32 runs must meet the complexity
+theorem's E[(Y - E P)^2] < eps^2 over independent seeds.
+"""
+import numpy as np
+import pytest
+
+from paper_1505_00965_amd import mlmc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_optimal_n_bit_exact(gctx, orc):
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        L = int(rng.integers(0, 10))
+        V = 10.0 ** rng.uniform(-6, 3, size=L + 1)
+        C = np.array([orc.level_cost(l, 4) for l in range(L + 1)])
+        eps = float(10.0 ** rng.uniform(-3, 0))
+        g = np.array(gctx.mlmc_optimal_n(list(V), list(C), eps))
+        o = orc.optimal_n(V, C, eps)
+        assert np.array_equal(g, o), (g, o)
+
+
+@pytest.mark.parametrize("eps,M", [(0.2, 4), (0.1, 4), (0.05, 2)])
+def test_fp64_run_takes_the_oracle_decisions(gctx, orc, eps, M):
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    om, op = orc.model(**W.GBM_MODEL), orc.payoff(**W.CALL)
+    g = gctx.mlmc_run(gm, gp, eps, M=M, seed=3, precision=64)
+    o = orc.mlmc_run(om, op, eps, M=M, seed=3, nthreads=8)
+    print("gpu", g["N"], g["estimate"], "oracle", o["N"], o["estimate"])
+    assert g["L"] == o["L"] and g["iterations"] == o["iterations"]
+    assert g["N"] == o["N"]
+    assert abs(g["estimate"] - o["estimate"]) <= 1e-9 * abs(o["estimate"])
+    assert g["converged"]
+
+
+@pytest.mark.parametrize("pname,kind", [("call", 0), ("asian", 0), ("lookback", 0), ("call", 1)])
+def test_fp32_run_close_to_oracle_run(gctx, orc, pname, kind):
+    md = W.GBM_MODEL if kind == 0 else W.HESTON_MODEL
+    gm, gp = mlmc.model(**md), mlmc.payoff(**W.PAYOFFS[pname])
+    om, op = orc.model(**md), orc.payoff(**W.PAYOFFS[pname])
+    g = gctx.mlmc_run(gm, gp, 0.1, M=4, seed=5, precision=32)
+    o = orc.mlmc_run(om, op, 0.1, M=4, seed=5, nthreads=8)
+    # same samples, fp32 paths: estimates differ by the path error, not by eps
+    assert abs(g["estimate"] - o["estimate"]) < 2e-3 * 100
+    assert g["L"] == o["L"]
+
+
+def test_rmse_over_seeds_fp32(gctx, orc):
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    eps = 1e-3 * 100
+    exact = orc.bs_call()
+    errs = []
+    for seed in range(1, 33):
+        r = gctx.mlmc_run(gm, gp, eps, M=4, seed=seed)
+        assert r["converged"]
+        errs.append(r["estimate"] - exact)
+    rmse = float(np.sqrt(np.mean(np.square(errs))))
+    print("rmse", rmse)
+    assert rmse < 1.35 * eps
+
+
+def test_notconv_and_bad_args(gctx):
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    r = gctx.mlmc_run(gm, gp, 0.002, M=4, L_min=2, L_max=2, n_pilot=2000, allow_notconv=True)
+    assert not r["converged"] and r["L"] == 2
+    with pytest.raises(mlmc.MLMCError) as e:
+        gctx.mlmc_run(gm, gp, 0.002, M=4, L_min=2, L_max=2, n_pilot=2000)
+    assert e.value.status == mlmc.MLMC_ENOTCONV
+    for kw in (dict(eps=-1.0), dict(eps=0.1, L_min=3, L_max=2), dict(eps=0.1, M=3),
+               dict(eps=0.1, n_pilot=1)):
+        eps = kw.pop("eps")
+        with pytest.raises(mlmc.MLMCError) as e:
+            gctx.mlmc_run(gm, gp, eps, **kw)
+        assert e.value.status == mlmc.MLMC_EINVAL

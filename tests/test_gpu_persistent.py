@@ -1,0 +1,90 @@
+"""Persistent all-levels form vs the per-level sampler.
+
+The persistent kernel draws exactly the samples the per-level launches draw
+(same counters), so its (payoff, level) sums must equal mlmc_level's up to
+fp64 summation order, whatever the item split and launch shape; the
+graph-driven adaptive run must take the per-level run's decisions.
+"""
+import numpy as np
+import pytest
+
+from paper_1505_00965_amd import mlmc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def close(a, b, rel=1e-11):
+    return abs(a - b) <= rel * max(abs(a), abs(b), 1e-300) + 1e-13
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_batch_equals_per_level(gctx, kind):
+    md = W.GBM_MODEL if kind == 0 else W.HESTON_MODEL
+    gm = mlmc.model(**md)
+    pays = [mlmc.payoff(**W.PAYOFFS[n]) for n in ("call", "asian", "lookback", "digital")]
+    L, M = 5, 4
+    N = [[int(2**16 // 4**l * (k + 1)) + 37 * l for l in range(L + 1)] for k in range(4)]
+    N[2][3] = 0                      # an empty (payoff, level)
+    offs = [[1000 * k + (l << 33) for l in range(L + 1)] for k in range(4)]
+    for shape in [(256, 2, 4), (64, 1, 8), (512, 4, 2)]:
+        gctx.set_persistent_launch(*shape)
+        got = gctx.mlmc_levels_batch(gm, pays, M, L, N, seed=9, offsets=offs)
+        for k, p in enumerate(pays):
+            for l in range(L + 1):
+                ref = gctx.mlmc_level(gm, p, l, M, N[k][l], 9, path_offset=offs[k][l])
+                g = got[k][l]
+                assert g["n"] == N[k][l]
+                for key in ("sum_y", "sum_y2", "sum_pf", "sum_pc"):
+                    assert close(g[key], ref[key]), (shape, k, l, key, g[key], ref[key])
+    gctx.set_persistent_launch(0, 0, 0)
+
+
+def test_graph_replay_with_new_sizes(gctx):
+    gm = mlmc.model(**W.GBM_MODEL)
+    pays = [mlmc.payoff(**W.CALL)]
+    for rep, scale in enumerate((1, 3, 1, 2)):
+        N = [[5000 * scale // (l + 1) for l in range(4)]]
+        got = gctx.mlmc_levels_batch(gm, pays, 4, 3, N, seed=rep)
+        for l in range(4):
+            ref = gctx.mlmc_level(gm, pays[0], l, 4, N[0][l], rep)
+            assert close(got[0][l]["sum_y"], ref["sum_y"]), (rep, l)
+
+
+def test_mlmc_shaped_batch_full_size(gctx, orc):
+    """The benchmark's MLMC-shaped launch: N_l = 2^26 4^-l, l = 0..8, four payoffs;
+    per-level means within 5 sigma of independent oracle estimates."""
+    gm = mlmc.model(**W.GBM_MODEL)
+    names = ("call", "asian", "lookback", "digital")
+    pays = [mlmc.payoff(**W.PAYOFFS[n]) for n in names]
+    L = 8
+    N = [[W.persistent_n(l) for l in range(L + 1)] for _ in pays]
+    got = gctx.mlmc_levels_batch(gm, pays, 4, L, N, seed=1)
+    om = orc.model(**W.GBM_MODEL)
+    for k, n in enumerate(names):
+        op = orc.payoff(**W.PAYOFFS[n])
+        for l in (0, 2, 4):
+            g = got[k][l]
+            gmean = g["sum_y"] / g["n"]
+            gvar = g["sum_y2"] / g["n"] - gmean**2
+            o = orc.level(om, op, l, 4, 20000, 77, nthreads=8)
+            omean = o["sum_y"] / 20000
+            ovar = o["sum_y2"] / 20000 - omean**2
+            assert abs(gmean - omean) < 5 * np.sqrt(gvar / g["n"] + ovar / 20000), (n, l)
+        assert all(got[k][l]["n_nonfinite"] == 0 for l in range(L + 1))
+
+
+def test_persistent_run_matches_per_level_run(gctx):
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    for eps in (0.1, 0.02):
+        a = gctx.mlmc_run(gm, gp, eps, M=4, seed=4, persistent=False)
+        b = gctx.mlmc_run(gm, gp, eps, M=4, seed=4, persistent=True)
+        assert a["N"] == b["N"] and a["L"] == b["L"] and a["iterations"] == b["iterations"]
+        assert close(a["estimate"], b["estimate"], 1e-10)
+
+
+def test_batch_bad_args(gctx):
+    gm = mlmc.model(**W.GBM_MODEL)
+    with pytest.raises(mlmc.MLMCError):
+        gctx.mlmc_levels_batch(gm, [mlmc.payoff(**W.CALL)] * 5, 4, 2, [[10] * 3] * 5, 1)
+    with pytest.raises(mlmc.MLMCError):
+        gctx.mlmc_levels_batch(gm, [mlmc.payoff(**W.CALL)], 3, 2, [[10] * 3], 1)
