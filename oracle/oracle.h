@@ -87,7 +87,8 @@ void orc_counter(uint32_t j, uint64_t s, int level, int stream, uint32_t ctr[4])
 void orc_path_words(uint64_t seed, int level, uint64_t s, int stream,
                     uint32_t nblocks, uint32_t *out);
 /* Standard normals of path s: dim=1 -> z[n], n < nsteps;
- * dim=2 -> z[2n], z[2n+1] are the two factors of step n.                 */
+ * dim=2 -> z[2n], z[2n+1] are the two factors of step n.  Paths needing
+ * fewer than four normals share a generator block (see rng.c).           */
 void orc_path_normals(uint64_t seed, int level, uint64_t s, int stream, int dim,
                       int nsteps, double *z);
 /* Uniforms for the bridge minimum of step n (stream+1 of the normals). */

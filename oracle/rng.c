@@ -17,6 +17,10 @@
  *   word 2 = level + 256 * (s >> 32),
  *   word 3 = stream id.
  * Key = (seed mod 2^32, seed >> 32).
+ * A path that needs fewer than four numbers from a stream (total = 1 or 2)
+ * shares one block with q = 4/total neighbouring paths instead of leaving
+ * words unused: path s reads block (0, s/q, ...) from word (s mod q) * total,
+ * with s/q in place of s in words 1 and 2.
  *
  * Uniforms: u = ((x >> 8) + 1/2) 2^-24, exactly representable and in (0,1).
  * Normals: Box--Muller on a pair (u1, u2): rho = sqrt(-2 ln u1),
@@ -101,6 +105,16 @@ void orc_path_normals(uint64_t seed, int level, uint64_t s, int stream, int dim,
     uint32_t key[2], ctr[4], w[4];
     seed_key(seed, key);
     int total = nsteps * dim;           /* normals needed */
+    if (total > 0 && total < 4) {       /* shared block, see above */
+        int q = 4 / total;
+        orc_counter(0, s / (uint64_t)q, level, stream, ctr);
+        orc_philox4x32_10(ctr, key, w);
+        double zz[4];
+        orc_box_muller(w[0], w[1], &zz[0], &zz[1]);
+        orc_box_muller(w[2], w[3], &zz[2], &zz[3]);
+        for (int i = 0; i < total; ++i) z[i] = zz[(int)(s % (uint64_t)q) * total + i];
+        return;
+    }
     int nblocks = (total + 3) / 4;
     for (int j = 0; j < nblocks; ++j) {
         orc_counter((uint32_t)j, s, level, stream, ctr);
@@ -119,6 +133,13 @@ void orc_path_uniforms(uint64_t seed, int level, uint64_t s, int stream,
 {
     uint32_t key[2], ctr[4], w[4];
     seed_key(seed, key);
+    if (nsteps > 0 && nsteps < 4) {     /* shared block */
+        int q = 4 / nsteps;
+        orc_counter(0, s / (uint64_t)q, level, stream, ctr);
+        orc_philox4x32_10(ctr, key, w);
+        for (int i = 0; i < nsteps; ++i) u[i] = orc_u01(w[(int)(s % (uint64_t)q) * nsteps + i]);
+        return;
+    }
     int nblocks = (nsteps + 3) / 4;
     for (int j = 0; j < nblocks; ++j) {
         orc_counter((uint32_t)j, s, level, stream, ctr);

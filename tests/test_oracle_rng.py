@@ -117,3 +117,26 @@ def test_box_muller_is_polar_map(orc):
         ang = np.arctan2(z1, z0) % (2 * np.pi)
         assert np.isclose(ang, (2 * np.pi * u2) % (2 * np.pi), atol=1e-9) or \
             np.isclose(abs(ang - 2 * np.pi * u2), 2 * np.pi, atol=1e-9)
+
+
+def test_short_paths_share_a_block(orc):
+    # fewer than four numbers per path: q = 4/total paths read one block
+    for dim, nsteps in [(1, 1), (1, 2), (2, 1)]:
+        total = dim * nsteps
+        q = 4 // total
+        for s in (0, 1, 2, 3, 6, 2**33 + 5):
+            w = orc.philox([0, (s // q) & 0xFFFFFFFF, 4 + 256 * ((s // q) >> 32), 0], [1, 0])
+            zz = orc.box_muller(w[0], w[1]) + orc.box_muller(w[2], w[3])
+            z = orc.path_normals(1, 4, s, 0, dim, nsteps)
+            r = s % q
+            assert np.array_equal(z, np.array(zz[r * total:(r + 1) * total]))
+    # neighbouring paths get different numbers; the set of a block is all used
+    zs = np.concatenate([orc.path_normals(1, 0, s, 0, 1, 1) for s in range(8)])
+    assert len(set(zs)) == 8
+    for nsteps in (1, 2):
+        q = 4 // nsteps
+        for s in (0, 3, 5):
+            w = orc.philox([0, s // q, 2, 1], [1, 0])
+            u = orc.path_uniforms(1, 2, s, 1, nsteps)
+            r = s % q
+            assert np.array_equal(u, np.array([orc.u01(int(x)) for x in w[r * nsteps:(r + 1) * nsteps]]))
