@@ -63,11 +63,18 @@ LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_pa
         const uint64_t lanes = (N + s.ppt - 1) / s.ppt;
         if (lanes < (uint64_t)ctx->num_cu * 256) s.ppt = 1;
     }
+    const int nf = level_steps(l, M);
+    uint64_t units = N;   // samples, or generator blocks for one/two-step levels
+    if (nf < 4) {
+        const int q = 4 / (nf * (m.kind == MLMC_HESTON ? 2 : 1));
+        units = (N + q - 1) / q + 1;
+        if (s.ppt > 2) s.ppt = 2;
+    }
     const uint64_t chunk = (uint64_t)s.block * s.ppt;
-    const uint64_t chunks = (N + chunk - 1) / chunk;
+    const uint64_t chunks = (units + chunk - 1) / chunk;
     const uint64_t cap = (uint64_t)ctx->num_cu * (2048 / s.block);
     s.grid = (int)std::max<uint64_t>(1, std::min(chunks, cap));
-    (void)m; (void)p; (void)l; (void)M;
+    (void)p;
     return s;
 }
 

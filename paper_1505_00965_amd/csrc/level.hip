@@ -59,17 +59,39 @@ __global__ __launch_bounds__(1024) void level_kernel(LevelArgs<Real> a)
     block_reduce_add(sums, nonfinite, a.acc);
 }
 
+// Levels with one or two fine steps: samples share generator blocks.
+template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT>
+__global__ __launch_bounds__(1024) void short_level_kernel(LevelArgs<Real> a)
+{
+    constexpr int Q = 4 / (NF * (MODEL == kGBM ? 1 : 2));
+    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+    unsigned nonfinite = 0;
+    const uint64_t nblk = short_blocks(a.offset, a.N, Q);
+    const uint64_t chunk = (uint64_t)blockDim.x * PPT;
+    const uint64_t nchunks = (nblk + chunk - 1) / chunk;
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+        process_short<MODEL, PAYOFF, Real, NF, M, PPT>(a, c * chunk, sums, nonfinite);
+    block_reduce_add(sums, nonfinite, a.acc);
+}
+
 // ------------------------------------------------------------ dispatch
 template <typename Real>
 using KernelFn = void (*)(LevelArgs<Real>);
 
+// nf: 1 or 2 selects the short-level kernel, anything else the general one.
 template <int MODEL, int PAYOFF, typename Real, int M>
-static KernelFn<Real> pick_ppt(int ppt)
+static KernelFn<Real> pick_ppt(int ppt, int nf)
 {
     if constexpr (sizeof(Real) == 8) {
         (void)ppt;   // fp64 paths: one per lane (register budget)
+        if (nf == 1) return short_level_kernel<MODEL, PAYOFF, Real, 1, M, 1>;
+        if (nf == 2) return short_level_kernel<MODEL, PAYOFF, Real, 2, M, 1>;
         return level_kernel<MODEL, PAYOFF, Real, M, 1>;
     } else {
+        if (nf == 1) return ppt == 1 ? short_level_kernel<MODEL, PAYOFF, Real, 1, M, 1>
+                                     : short_level_kernel<MODEL, PAYOFF, Real, 1, M, 2>;
+        if (nf == 2) return ppt == 1 ? short_level_kernel<MODEL, PAYOFF, Real, 2, M, 1>
+                                     : short_level_kernel<MODEL, PAYOFF, Real, 2, M, 2>;
         switch (ppt) {
         case 1: return level_kernel<MODEL, PAYOFF, Real, M, 1>;
         case 2: return level_kernel<MODEL, PAYOFF, Real, M, 2>;
@@ -79,27 +101,28 @@ static KernelFn<Real> pick_ppt(int ppt)
 }
 
 template <int MODEL, int PAYOFF, typename Real>
-static KernelFn<Real> pick_m(int M, int ppt)
+static KernelFn<Real> pick_m(int M, int ppt, int nf)
 {
-    return M == 2 ? pick_ppt<MODEL, PAYOFF, Real, 2>(ppt) : pick_ppt<MODEL, PAYOFF, Real, 4>(ppt);
+    return M == 2 ? pick_ppt<MODEL, PAYOFF, Real, 2>(ppt, nf)
+                  : pick_ppt<MODEL, PAYOFF, Real, 4>(ppt, nf);
 }
 
 template <int MODEL, typename Real>
-static KernelFn<Real> pick_payoff(int payoff, int M, int ppt)
+static KernelFn<Real> pick_payoff(int payoff, int M, int ppt, int nf)
 {
     switch (payoff) {
-    case kCall: return pick_m<MODEL, kCall, Real>(M, ppt);
-    case kAsian: return pick_m<MODEL, kAsian, Real>(M, ppt);
-    case kLookback: return pick_m<MODEL, kLookback, Real>(M, ppt);
-    default: return pick_m<MODEL, kDigital, Real>(M, ppt);
+    case kCall: return pick_m<MODEL, kCall, Real>(M, ppt, nf);
+    case kAsian: return pick_m<MODEL, kAsian, Real>(M, ppt, nf);
+    case kLookback: return pick_m<MODEL, kLookback, Real>(M, ppt, nf);
+    default: return pick_m<MODEL, kDigital, Real>(M, ppt, nf);
     }
 }
 
 template <typename Real>
-static KernelFn<Real> pick(int model, int payoff, int M, int ppt)
+static KernelFn<Real> pick(int model, int payoff, int M, int ppt, int nf)
 {
-    return model == kGBM ? pick_payoff<kGBM, Real>(payoff, M, ppt)
-                         : pick_payoff<kHeston, Real>(payoff, M, ppt);
+    return model == kGBM ? pick_payoff<kGBM, Real>(payoff, M, ppt, nf)
+                         : pick_payoff<kHeston, Real>(payoff, M, ppt, nf);
 }
 
 hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int precision,
@@ -107,11 +130,13 @@ hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int pr
 {
     dim3 grid(shape.grid), block(shape.block);
     if (precision == 64) {
-        auto fn = pick<double>(m.kind, p.kind, M, 1);
-        hipLaunchKernelGGL(fn, grid, block, 0, stream, *(const LevelArgs<double>*)args);
+        const auto& a = *(const LevelArgs<double>*)args;
+        auto fn = pick<double>(m.kind, p.kind, M, 1, a.nf);
+        hipLaunchKernelGGL(fn, grid, block, 0, stream, a);
     } else {
-        auto fn = pick<float>(m.kind, p.kind, M, shape.ppt);
-        hipLaunchKernelGGL(fn, grid, block, 0, stream, *(const LevelArgs<float>*)args);
+        const auto& a = *(const LevelArgs<float>*)args;
+        auto fn = pick<float>(m.kind, p.kind, M, shape.ppt, a.nf);
+        hipLaunchKernelGGL(fn, grid, block, 0, stream, a);
     }
     return hipGetLastError();
 }
@@ -132,6 +157,8 @@ __global__ void philox_words_kernel(uint64_t seed, int level, uint64_t s0, uint3
     }
 }
 
+// Normals of each path as the sampler reads them (paths needing fewer than
+// four share a block: q = 4/total_per_path of them, block s/q).
 template <typename Real>
 __global__ void normals_kernel(uint64_t seed, int level, uint64_t s0, uint32_t stream,
                                uint32_t nblocks, int total_per_path, uint64_t npaths, double* out)
@@ -141,14 +168,19 @@ __global__ void normals_kernel(uint64_t seed, int level, uint64_t s0, uint32_t s
          t += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t i = t / nblocks;
         const uint32_t j = (uint32_t)(t % nblocks);
-        const PathKey k = make_path_key(seed, level, s0 + i, stream);
+        const uint64_t s = s0 + i;
+        const int q = total_per_path < 4 ? 4 / total_per_path : 1;
+        const PathKey k = make_path_key(seed, level, s / q, stream);
         const u32x4 w = path_block(k, j);
         Real z[4];
         box_muller(w.x, w.y, z[0], z[1]);
         box_muller(w.z, w.w, z[2], z[3]);
-        for (int q = 0; q < 4; ++q) {
-            const int n = 4 * (int)j + q;
-            if (n < total_per_path) out[i * total_per_path + n] = (double)z[q];
+        const int first = q > 1 ? (int)(s % q) * total_per_path : 4 * (int)j;
+        for (int n = 0; n < total_per_path && q > 1; ++n)
+            out[i * total_per_path + n] = (double)z[first + n];
+        for (int w4 = 0; w4 < 4 && q == 1; ++w4) {
+            const int n = first + w4;
+            if (n < total_per_path) out[i * total_per_path + n] = (double)z[w4];
         }
     }
 }

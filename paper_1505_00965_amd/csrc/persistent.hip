@@ -120,7 +120,17 @@ __device__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[k
     a.acc = nullptr;
     a.pf_out = a.pc_out = nullptr;
     a.coupled = 1;
-    if (w.n <= blockDim.x) {
+    if (nf < 4) {
+        // one or two steps: samples share generator blocks
+        constexpr int D = (MODEL == kGBM) ? 1 : 2;
+        const int q = 4 / (nf * D);
+        const uint64_t nblk = short_blocks(w.first, w.n, q);
+        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
+        for (uint64_t base = 0; base < nblk; base += chunk) {
+            if (nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT>(a, base, sums, nonfinite);
+            else process_short<MODEL, PAYOFF, float, 2, M, PPT>(a, base, sums, nonfinite);
+        }
+    } else if (w.n <= blockDim.x) {
         // fewer samples than lanes: one per lane
         process_chunk<MODEL, PAYOFF, float, M, 1>(a, 0, sums, nonfinite);
     } else {

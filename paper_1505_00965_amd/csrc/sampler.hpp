@@ -31,6 +31,10 @@ struct StepParams {
     Real asian_scale;                // h / (2T)
 };
 
+// Fused multiply-add in the path's own precision (no promotion to fp64).
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename Real>
 __device__ __forceinline__ Real fsqrt(Real x);
 template <>
@@ -103,13 +107,13 @@ __device__ __forceinline__ void fine_step(PathPair<Real>& q, const StepParams<Re
     Real vol;
     if (MODEL == kGBM) {
         vol = P.sigma;
-        q.S = __builtin_fma(q.S, __builtin_fma(P.sigma, dw1, P.rh), q.S);
+        q.S = fmaT(q.S, fmaT(P.sigma, dw1, P.rh), q.S);
     } else {
         const Real vp = q.v > Real(0) ? q.v : Real(0);
         vol = fsqrt<Real>(vp);
-        const Real dw2 = __builtin_fma(P.rho, dw1, P.rho_c * dwp);
-        q.S = __builtin_fma(q.S, __builtin_fma(vol, dw1, P.rh), q.S);
-        q.v = __builtin_fma(P.xi * vol, dw2, __builtin_fma(P.kappa * P.h, P.theta - vp, q.v));
+        const Real dw2 = fmaT(P.rho, dw1, P.rho_c * dwp);
+        q.S = fmaT(q.S, fmaT(vol, dw1, P.rh), q.S);
+        q.v = fmaT(P.xi * vol, dw2, fmaT(P.kappa * P.h, P.theta - vp, q.v));
     }
     if (PAYOFF == kAsian) comp_add(q.asum, q.acomp, S0n + q.S);
     if (PAYOFF == kLookback) {
@@ -124,9 +128,9 @@ __device__ __forceinline__ void fine_step(PathPair<Real>& q, const StepParams<Re
         // X(tau) = Sc + Sc (r tau + vol_c W(tau)), W from the coarse step start
         const Real volc = (MODEL == kGBM) ? P.sigma
                                          : fsqrt<Real>(q.vc > Real(0) ? q.vc : Real(0));
-        const Real x0 = __builtin_fma(q.Sc, __builtin_fma(volc, q.wpart, P.rh * Real(k)), q.Sc);
+        const Real x0 = fmaT(q.Sc, fmaT(volc, q.wpart, P.rh * Real(k)), q.Sc);
         q.wpart += dw1;
-        const Real x1 = __builtin_fma(q.Sc, __builtin_fma(volc, q.wpart, P.rh * Real(k + 1)), q.Sc);
+        const Real x1 = fmaT(q.Sc, fmaT(volc, q.wpart, P.rh * Real(k + 1)), q.Sc);
         const Real m = bridge_min(x0, x1, volc * q.Sc, e);
         q.mnc = m < q.mnc ? m : q.mnc;
     }
@@ -138,13 +142,13 @@ __device__ __forceinline__ void coarse_step(PathPair<Real>& q, const StepParams<
 {
     const Real S0c = q.Sc;
     if (MODEL == kGBM) {
-        q.Sc = __builtin_fma(q.Sc, __builtin_fma(P.sigma, q.dw1c, P.rH), q.Sc);
+        q.Sc = fmaT(q.Sc, fmaT(P.sigma, q.dw1c, P.rH), q.Sc);
     } else {
         const Real vp = q.vc > Real(0) ? q.vc : Real(0);
         const Real sv = fsqrt<Real>(vp);
-        const Real dw2 = __builtin_fma(P.rho, q.dw1c, P.rho_c * q.dwpc);
-        q.Sc = __builtin_fma(q.Sc, __builtin_fma(sv, q.dw1c, P.rH), q.Sc);
-        q.vc = __builtin_fma(P.xi * sv, dw2, __builtin_fma(P.kappa * P.H, P.theta - vp, q.vc));
+        const Real dw2 = fmaT(P.rho, q.dw1c, P.rho_c * q.dwpc);
+        q.Sc = fmaT(q.Sc, fmaT(sv, q.dw1c, P.rH), q.Sc);
+        q.vc = fmaT(P.xi * sv, dw2, fmaT(P.kappa * P.H, P.theta - vp, q.vc));
     }
     if (PAYOFF == kAsian) comp_add(q.csum, q.ccomp, S0c + q.Sc);
     q.dw1c = 0;

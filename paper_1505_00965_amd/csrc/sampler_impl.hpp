@@ -4,7 +4,30 @@
 
 namespace mlmc {
 
-// Advance PPT coupled pairs through all fine steps of the level.
+// Add one sample's payoffs into the lane sums (and the optional dump).
+template <typename Real>
+__device__ __forceinline__ void accumulate(const LevelArgs<Real>& a, uint64_t idx, Real pf, Real pc,
+                                           double (&sums)[kNumSums], unsigned& nonfinite)
+{
+    const double df = (double)pf, dc = (double)pc;
+    if (a.pf_out) {
+        a.pf_out[idx] = df;
+        a.pc_out[idx] = dc;
+    }
+    const double y = df - dc;
+    if (!isfinite(y)) {
+        ++nonfinite;
+        return;
+    }
+    sums[0] += y;
+    sums[1] = __builtin_fma(y, y, sums[1]);
+    sums[2] += df;
+    sums[3] = __builtin_fma(df, df, sums[3]);
+    sums[4] += dc;
+    sums[5] = __builtin_fma(dc, dc, sums[5]);
+}
+
+// Advance PPT coupled pairs through all n_f >= 4 fine steps of the level.
 template <int MODEL, int PAYOFF, typename Real, int M, int PPT>
 __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_t (&s)[PPT],
                                          PathPair<Real> (&q)[PPT])
@@ -18,7 +41,7 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
         init_pair<Real, MODEL, PAYOFF>(q[p], P);
     }
     const bool coupled = a.coupled && a.l > 0;
-    const bool full = a.nf >= 4;
+    // n_f >= 4 here (a multiple of 4): every group holds four fine steps
     for (uint32_t g = 0; g < a.ngroups; ++g) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
@@ -55,10 +78,8 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (full || (int)(4 * g + k) < a.nf) {
-                    fine_step<Real, MODEL, PAYOFF>(q[p], P, dw1[k], dwp[k], e[k], k % M, coupled);
-                    if (coupled && ((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(q[p], P);
-                }
+                fine_step<Real, MODEL, PAYOFF>(q[p], P, dw1[k], dwp[k], e[k], k % M, coupled);
+                if (coupled && ((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(q[p], P);
             }
         }
     }
@@ -88,24 +109,71 @@ __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t
                                                                 q[p].mnc, dtc)
                                     : Real(0);
             if (idx[p] >= a.N) continue;
-            const double df = (double)pf, dc = (double)pc;
-            if (a.pf_out) {
-                a.pf_out[idx[p]] = df;
-                a.pc_out[idx[p]] = dc;
-            }
-            const double y = df - dc;
-            if (!isfinite(y)) {
-                ++nonfinite;
-                continue;
-            }
-            sums[0] += y;
-            sums[1] = __builtin_fma(y, y, sums[1]);
-            sums[2] += df;
-            sums[3] = __builtin_fma(df, df, sums[3]);
-            sums[4] += dc;
-            sums[5] = __builtin_fma(dc, dc, sums[5]);
+            accumulate(a, idx[p], pf, pc, sums, nonfinite);
         }
     }
+}
+
+// Levels with n_f = NF in {1, 2}: Q = 4/(NF d) consecutive samples share one
+// generator block (d = 1 for GBM, 2 for Heston), as do 4/NF samples one
+// bridge block.  A lane takes PPT blocks, i.e. Q * PPT samples; block B of
+// the level covers samples Q B .. Q B + Q - 1 (those outside
+// [offset, offset + N) are computed and dropped).  blk_base indexes blocks
+// from B0 = offset / Q.
+template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT>
+__device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t blk_base,
+                                              double (&sums)[kNumSums], unsigned& nonfinite)
+{
+    constexpr int D = (MODEL == kGBM) ? 1 : 2;
+    constexpr int T = NF * D;             // normals per sample: 1, 2 or 4
+    constexpr int Q = 4 / T;              // samples per generator block
+    constexpr int QU = 4 / NF;            // samples per bridge block
+    const StepParams<Real>& P = a.P;
+    const bool coupled = a.coupled && a.l > 0;   // NF == 2 with M == 2 only
+    const uint64_t B0 = a.offset / Q;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const uint64_t B = B0 + blk_base + (uint64_t)p * blockDim.x + threadIdx.x;
+        const u32x4 w = path_block(make_path_key(a.seed, a.l, B, a.stream), 0);
+        Real z[4];
+        box_muller(w.x, w.y, z[0], z[1]);
+        box_muller(w.z, w.w, z[2], z[3]);
+        Real e[4] = {Real(0), Real(0), Real(0), Real(0)};
+        if (PAYOFF == kLookback) {
+            // every sample of this generator block reads bridge block B / D
+            const u32x4 u = path_block(make_path_key(a.seed, a.l, B / D, a.stream + 1u), 0);
+            e[0] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.x));
+            e[1] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.y));
+            e[2] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.z));
+            e[3] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.w));
+        }
+#pragma unroll
+        for (int r = 0; r < Q; ++r) {
+            const uint64_t s = B * Q + r;
+            PathPair<Real> q;
+            init_pair<Real, MODEL, PAYOFF>(q, P);
+            const int ub = (int)(s % QU) * NF;   // first bridge word of the sample
+#pragma unroll
+            for (int k = 0; k < NF; ++k) {
+                const Real dw1 = P.sqh * z[r * T + k * D];
+                const Real dwp = (D == 2) ? P.sqh * z[r * T + k * D + 1] : Real(0);
+                fine_step<Real, MODEL, PAYOFF>(q, P, dw1, dwp, e[(ub + k) & 3], k % M, coupled);
+            }
+            if (NF == 2 && coupled) coarse_step<Real, MODEL, PAYOFF>(q, P);
+            const Real pf = payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
+            const Real pc = coupled ? payoff_value<Real, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H)
+                                    : Real(0);
+            if (s < a.offset || s - a.offset >= a.N) continue;
+            accumulate(a, s - a.offset, pf, pc, sums, nonfinite);
+        }
+    }
+}
+
+// Number of generator blocks a short level's range [offset, offset + N) touches.
+__host__ __device__ inline uint64_t short_blocks(uint64_t offset, uint64_t N, int q)
+{
+    if (N == 0) return 0;
+    return (offset + N - 1) / q - offset / q + 1;
 }
 
 }  // namespace mlmc

@@ -44,7 +44,7 @@ def test_per_path_parity(gctx, orc, kind, pname, precision):
     gp, op = pays(orc, pname)
     N = 3000
     for (M, l) in CASES:
-        for offset in (0, (1 << 32) - 1000):
+        for offset in (0, 3, (1 << 32) - 1001):
             print(f"case kind={kind} payoff={pname} prec={precision} M={M} l={l} off={offset}",
                   flush=True)
             pf, pc, res = gpu_paths(gctx, gm, gp, l, M, N, 1, offset, precision)
