@@ -24,10 +24,20 @@ sys.path.insert(0, ROOT)
 METRIC = "seconds to RMSE 1e-3·S0 (learned-CV vs plain MLMC); fine path-steps/s"
 UNIT = "fine path-steps/s"
 
-# Algorithmic VALU operations per fine path step of the GBM call sampler with
-# M = 4 (Philox 10 + uniform/Box-Muller 5.5 + increment 1 + Euler step 2 +
-# coarse sum 1 + coarse step 0.5); derivation in the design doc.
-OPS_PER_FINE_STEP = 20.0
+# Algorithmic vector-ALU operations of the GBM call sampler, M = 4 (the
+# derivation is in the design doc): per fine step, a quarter Philox4x32-10 call
+# (10 rounds of 2 32x32->64 products and 2 three-input xors: 10), half a
+# Box-Muller pair (6.5), increment and Euler step (3), coarse increment sum
+# and a quarter coarse step (1.5); per sample, payoffs and fp64 sums.
+OPS_PER_FINE_STEP = 21.0
+OPS_PER_SAMPLE_L0 = 25.5      # level 0: the one step plus payoff and Y, Y^2 sums
+OPS_PER_SAMPLE = 11.0         # levels >= 1: two payoffs, difference, sums
+
+
+def algorithmic_ops(level, fine_steps, samples):
+    if level == 0:
+        return OPS_PER_SAMPLE_L0 * samples
+    return OPS_PER_FINE_STEP * fine_steps + OPS_PER_SAMPLE * samples
 # MI355X vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
@@ -42,6 +52,8 @@ def parse():
                     help="approximate CPU work for the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip seconds-to-RMSE runs")
+    ap.add_argument("--persistent", type=int, default=0,
+                    help="1: each driver iteration is one graph launch of the persistent kernel")
     return ap.parse_args()
 
 
@@ -93,7 +105,7 @@ def main():
 
     def step(seed):
         return ctx.mlmc_run(gm, gp, eps, M=M, L_min=2, L_max=9, n_pilot=10000, seed=seed,
-                            precision=32)
+                            precision=32, persistent=bool(args.persistent))
 
     for i in range(args.warmup):
         step(1000 + i)
@@ -108,17 +120,39 @@ def main():
 
     fine = sum(fine_steps_of(r, M) for r in runs)
     value = fine / dt
-    # dominant kernel: the level whose launches took the most time
-    lv = max(range(16), key=lambda l: stats[l]["ms"])
-    s = stats[lv]
-    avg_ms = s["ms"] / max(1, s["launches"])
-    ops_per_launch = OPS_PER_FINE_STEP * s["fine_steps"] / max(1, s["launches"])
-    achieved = ops_per_launch / (avg_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                "kernel": f"level_kernel<GBM,call,fp32,M=4> at level {lv}",
-                "avg_launch_ms": avg_ms, "launches": s["launches"],
-                "fine_steps_per_launch": s["fine_steps"] / max(1, s["launches"])}
+    roofline = None
+    if args.persistent:
+        # one graph launch (plan, persistent sampler, driver update) per iteration
+        s = stats[mlmc.STAT_PERSISTENT]
+        if s["launches"]:
+            avg_ms = s["ms"] / s["launches"]
+            samples = sum(sum(r["N"]) for r in runs) / s["launches"]
+            ops_per_launch = (OPS_PER_FINE_STEP * s["fine_steps"] / s["launches"]
+                              + OPS_PER_SAMPLE * samples)
+            achieved = ops_per_launch / (avg_ms * 1e-3)
+            roofline = {"bound": "alu", "achieved": achieved / 1e12,
+                        "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
+                        "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                        "kernel": "persistent_kernel<GBM,M=4> graph (plan + sampler + update)",
+                        "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_ms,
+                        "launches": s["launches"]}
+    else:
+        # dominant kernel: the level whose launches took the most time
+        lv = max(range(16), key=lambda l: stats[l]["ms"])
+        s = stats[lv]
+        if s["launches"]:
+            avg_ms = s["ms"] / s["launches"]
+            samples = s["fine_steps"] / M**lv
+            ops_per_launch = algorithmic_ops(lv, s["fine_steps"], samples) / s["launches"]
+            achieved = ops_per_launch / (avg_ms * 1e-3)
+            roofline = {"bound": "alu", "achieved": achieved / 1e12,
+                        "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
+                        "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                        "kernel": ("short_level_kernel<GBM,call,fp32,n_f=1> (level 0)" if lv == 0
+                                   else f"level_kernel<GBM,call,fp32,M=4> at level {lv}"),
+                        "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_ms,
+                        "launches": s["launches"],
+                        "fine_steps_per_launch": s["fine_steps"] / s["launches"]}
 
     line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
@@ -126,7 +160,8 @@ def main():
             "data": "synthetic",
             "config": {"workload": f"adaptive MLMC, GBM European call S0=100 r=0.05 sigma=0.2 "
                                    f"T=1 K=100, M=4, RMSE {args.eps:g}*S0, fp32 paths fp64 sums, "
-                                   f"one level per launch",
+                                   + ("one graph launch per driver iteration" if args.persistent
+                                      else "one level per launch"),
                        "levels": runs[-1]["L"] + 1, "N_l": runs[-1]["N"],
                        "estimate": runs[-1]["estimate"]},
             "roofline": roofline}

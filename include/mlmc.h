@@ -223,6 +223,53 @@ typedef struct {
 mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
                      const mlmc_run_opts* opts, mlmc_run_result* out);
 
+/* ------------------------------------------------------- control variate
+ * Learned martingale control variate (Sec. 5, "Exploiting Structure": a
+ * control variate with known mean).  Each payoff P of a level sample is
+ * replaced by P - sum_n phi(t_n, X_n) dW1_n on its own grid (fine path:
+ * fine steps and increments; coarse path: coarse steps and summed
+ * increments), phi evaluated at the left point, so the sum has mean exactly
+ * zero and every level keeps its expectation.  phi is an MLP
+ * in_dim -> 64 -> 64 -> 1 with tanh, inputs (t/T, ln(S/S0)/(sref sqrt T)
+ * [, (v - theta)/theta]) and output scale sref S0 (sref = sigma for GBM,
+ * sqrt(theta) for Heston); for Heston it multiplies dW1 only.  Parameters
+ * are fp32 (layout W1[64][in_dim], b1[64], W2[64][64], b2[64], w3[64], b3);
+ * the 64x64 layer runs on bf16 matrix cores with fp32 accumulation.
+ * A network belongs to the context it was created on.                    */
+/* in_dim 2 (GBM) or 3 (Heston), hidden 64; Xavier-uniform weights from
+ * Philox stream 6 keyed by init_seed (word i % 4 of block i / 4 for
+ * parameter i), zero biases.                                              */
+mlmc_status mlmc_cv_create(mlmc_ctx* ctx, int in_dim, int hidden, uint64_t init_seed,
+                           mlmc_cv** out);
+mlmc_status mlmc_cv_destroy(mlmc_cv* cv);
+/* Number of parameters (4417 for in_dim 2, 4481 for 3); 0 for NULL. */
+size_t mlmc_cv_nparams(const mlmc_cv* cv);
+/* Copy the fp32 parameters to / from a host array of exactly nparams. */
+mlmc_status mlmc_cv_get_params(const mlmc_cv* cv, float* host, size_t n);
+mlmc_status mlmc_cv_set_params(mlmc_cv* cv, const float* host, size_t n);
+
+/* Training objective on B samples per level l = 0..lmax from the training
+ * streams (Philox streams 2 and 3, disjoint from estimation), sample indices
+ * step * B .. step * B + B - 1:
+ *   loss = sum_l sqrt(C_l Var_batch(Y_l)),  C_l the level cost,
+ * (the MLMC cost functional, total cost ~ (sum_l sqrt(V_l C_l))^2) and its
+ * gradient with respect to the fp32 parameters, computed by the device's
+ * forward pass (per-sample Y), per-sample weights dLoss/dY, and a backward
+ * pass that regenerates every path from its counters.
+ *   grad: host array of nparams floats (may be NULL); var: lmax+1 batch
+ *   variances (may be NULL); loss (may be NULL).  0 <= lmax <= 6,
+ *   2 <= batch <= 2^24.                                                   */
+mlmc_status mlmc_cv_loss_grad(mlmc_cv* cv, const mlmc_model* model, const mlmc_payoff* payoff,
+                              int M, int lmax, uint64_t batch, uint64_t seed, uint64_t step,
+                              float* grad, double* var, double* loss);
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
+ * the objective above, each on fresh training samples (the step counter of
+ * the network continues across calls).  loss_hist: host array of `steps`
+ * losses (may be NULL).                                                    */
+mlmc_status mlmc_cv_train(mlmc_cv* cv, const mlmc_model* model, const mlmc_payoff* payoff, int M,
+                          int lmax, int steps, uint64_t batch, double lr, uint64_t seed,
+                          float* loss_hist);
+
 #ifdef __cplusplus
 }
 #endif

@@ -113,6 +113,7 @@ static LevelArgs<Real> make_args(const mlmc_model& m, const mlmc_payoff& p, int 
     a.pf_out = d_pf;
     a.pc_out = d_pc;
     a.coupled = coupled;
+    a.phi0 = nullptr;
     return a;
 }
 
@@ -171,7 +172,32 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
                           int coupled, LevelAcc* acc, double* d_pf, double* d_pc, const mlmc_cv* cv)
 {
     if (N == 0) return MLMC_OK;
-    if (cv) return fail(ctx, MLMC_EINVAL, "control variate not available in this build");
+    if (cv) {
+        if (precision != 32) return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
+        if (cv_in_dim(cv) != (m.kind == MLMC_HESTON ? 3 : 2))
+            return fail(ctx, MLMC_EINVAL, "network inputs do not match the model (2: GBM, 3: Heston)");
+        const double nf = (double)level_steps(l, M);
+        auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
+        hipError_t e;
+        if (l == 0) {
+            // one step from (0, S0): phi is the single value phi(0, S0)
+            e = cv_launch_phi0(cv, m, ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "phi(0, S0) launch");
+            a.phi0 = cv_phi0_ptr(cv);
+            LaunchShape shape = choose_shape(ctx, m, p, l, M, 32, N);
+            const int tix = timed_begin(ctx, 0, (double)N, 0.0);
+            e = launch_level(m, p, M, 32, &a, shape, ctx->stream);
+            timed_end(ctx, tix);
+        } else {
+            const uint64_t chunks = (N + 255) / 256;
+            const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, (uint64_t)ctx->num_cu * 8));
+            const int tix = timed_begin(ctx, l < 16 ? l : 15, (double)N * nf, (double)N * nf / M);
+            e = cv_launch_level(cv, m, p, M, a, grid, ctx->stream);
+            timed_end(ctx, tix);
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "control-variate level launch");
+        return MLMC_OK;
+    }
     const LaunchShape shape = choose_shape(ctx, m, p, l, M, precision, N);
     const double nf = (double)level_steps(l, M);
     const int tix = timed_begin(ctx, l < 16 ? l : 15, (double)N * nf,

@@ -74,6 +74,13 @@ void harvest_timing(mlmc_ctx* ctx);
 
 void free_persistent(mlmc_ctx* ctx);
 
+// Control variate (cv.hip).
+hipError_t cv_launch_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st);
+hipError_t cv_launch_level(const mlmc_cv* cv, const mlmc_model& m, const mlmc_payoff& p, int M,
+                           const LevelArgs<float>& a, int grid, hipStream_t st);
+const float* cv_phi0_ptr(const mlmc_cv* cv);
+int cv_in_dim(const mlmc_cv* cv);
+
 hipError_t launch_philox_words(uint64_t seed, int level, uint64_t s0, uint32_t stream,
                                uint32_t nblocks, uint64_t npaths, uint32_t* out, hipStream_t st);
 hipError_t launch_normals(uint64_t seed, int level, uint64_t s0, uint32_t stream, int dim,

@@ -1,0 +1,734 @@
+// Learned control variate: parameters, the sampler with the control variate
+// (forward), the training backward pass, and Adam -- all device kernels.
+//
+// Level estimators with the control variate (eqs. (eq:mlmc:Yzero),
+// (eq:Yldef) with each payoff replaced by P - sum_n phi(t_n, X_n) dW1_n on
+// its own grid): the fine path uses its fine increments, the coarse path its
+// coarse (summed) increments, both evaluated at the left point of each step.
+// At t = 0 every sample sits at (0, S0), so level 0 needs only the one value
+// phi(0, S0), computed once per launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "context.hpp"
+#include "cv.hpp"
+#include "sampler_impl.hpp"
+
+using namespace mlmc::cvnet;
+
+struct mlmc_cv {
+    mlmc_ctx* ctx = nullptr;
+    int D = 2;                    // network inputs
+    int np = 0;                   // parameter count
+    float* d_params = nullptr;    // fp32 master
+    float* d_m1 = nullptr;        // Adam moments
+    float* d_m2 = nullptr;
+    bf16x8* d_afwd = nullptr;     // bf16 W2 operands (forward), 8 x 64 entries
+    bf16x8* d_abwd = nullptr;     // bf16 W2 operands (backward, permuted)
+    float* d_phi0 = nullptr;      // phi(0, S0) of the last model used
+    int adam_t = 0;
+    // training scratch
+    float* d_gpart = nullptr;     // per-block gradient partials
+    int gpart_blocks = 0;
+    double* d_y = nullptr;        // per-sample Y of a training batch (all levels)
+    float* d_w = nullptr;         // per-sample loss weights
+    double* d_loss = nullptr;     // loss and per-level variances
+    uint64_t batch_cap = 0;
+};
+
+namespace mlmc {
+
+// ------------------------------------------------------------ parameters
+// Xavier-uniform weights from the init stream: parameter i takes word i % 4
+// of generator block i / 4 at (sample 0, level 0); biases zero.
+__global__ void cv_init_kernel(float* params, int D, uint64_t seed)
+{
+    const int np = nparams(D);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    float a = 0.0f;
+    if (i < off_b1(D)) a = sqrtf(6.0f / (float)(D + H));
+    else if (i >= off_W2(D) && i < off_b2(D)) a = sqrtf(6.0f / (float)(2 * H));
+    else if (i >= off_w3(D) && i < off_b3(D)) a = sqrtf(6.0f / (float)(H + 1));
+    if (a == 0.0f) {
+        params[i] = 0.0f;
+        return;
+    }
+    const u32x4 w = path_block(make_path_key(seed, 0, 0, kStreamInit), (uint32_t)(i / 4));
+    const uint32_t word = (i % 4 == 0) ? w.x : (i % 4 == 1) ? w.y : (i % 4 == 2) ? w.z : w.w;
+    params[i] = a * (2.0f * (float)u01d(word) - 1.0f);
+}
+
+// Row of the permuted backward operand: physical row rho of e1 = W2^T d2
+// holds logical unit unit_of_row(rho), chosen so that e1's accumulator
+// registers line up with the forward pass's layer-1 slots (unit_b).
+__host__ __device__ inline int unit_of_row(int rho)
+{
+    const int kt = rho / 32, rem = rho % 32;
+    const int h = (rem % 8) / 4;
+    const int r = 4 * (rem / 8) + rem % 4;
+    return 32 * kt + 16 * (r / 8) + 8 * h + r % 8;
+}
+
+// Contraction position kappa of e1's B operand (d2 straight from the layer-2
+// accumulators) holds logical output unit j_of_pos(kappa).
+__host__ __device__ inline int j_of_pos(int kappa)
+{
+    const int kb = kappa / 16, rem = kappa % 16;
+    const int h = rem / 8, i = rem % 8;
+    const int t = 8 * kb + i;            // register order within the half
+    return row_d(h, t / 16, t % 16);
+}
+
+// bf16 operand arrays from the fp32 W2 (round to nearest even).
+__global__ void cv_prepare_kernel(const float* params, int D, bf16x8* afwd, bf16x8* abwd)
+{
+    const float* W2 = params + off_W2(D);
+    const int t = threadIdx.x;            // 64 lanes x 8 operand sets
+    for (int idx = t; idx < 8 * 64; idx += blockDim.x) {
+        const int set = idx / 64, lane = idx % 64;
+        const int hi = lane / 32;
+        const int tile = set / 4, kb = set % 4;
+        bf16x8 f, b;
+        for (int i = 0; i < 8; ++i) {
+            const int j = 32 * tile + lane % 32, k = 16 * kb + 8 * hi + i;
+            f[i] = (__bf16)W2[j * H + k];
+            // backward: row rho = 32 tile + lane % 32, position kappa = k
+            const int rho = 32 * tile + lane % 32;
+            b[i] = (__bf16)W2[j_of_pos(k) * H + unit_of_row(rho)];
+        }
+        afwd[idx] = f;
+        abwd[idx] = b;
+    }
+}
+
+struct CvKernelArgs {
+    const float* params;
+    const bf16x8* afwd;
+    NetConsts nc;
+    int D;
+};
+
+template <int D>
+__global__ void cv_phi0_kernel(CvKernelArgs c, float S0, float v0, float* out)
+{
+    __shared__ NetShared sh;
+    load_shared<D>(sh, c.params, c.nc);
+    __syncthreads();
+    bf16x8 a[2][4];
+    load_afwd(c.afwd, a);
+    const float phi = phi_eval<D>(sh, a, 0.0f, S0, v0);
+    if (threadIdx.x == 0) *out = phi;
+}
+
+// ------------------------------------------------------- sampler with cv
+// Four fine increments of group g of sample s, either from the sample's own
+// generator blocks (n_f >= 4) or from a block shared with q - 1 neighbours.
+template <int MODEL, int PAYOFF>
+__device__ __forceinline__ void fetch_group(const LevelArgs<float>& a, uint64_t s, uint32_t g,
+                                            float (&dw1)[4], float (&dwp)[4], float (&e)[4])
+{
+    const StepParams<float>& P = a.P;
+    constexpr int D = (MODEL == kGBM) ? 1 : 2;
+    const PathKey key = make_path_key(a.seed, a.l, s, a.stream);
+    if (a.nf >= 4) {
+        if (MODEL == kGBM) {
+            const u32x4 w = path_block(key, g);
+            float z[4];
+            box_muller(w.x, w.y, z[0], z[1]);
+            box_muller(w.z, w.w, z[2], z[3]);
+            for (int k = 0; k < 4; ++k) { dw1[k] = P.sqh * z[k]; dwp[k] = 0.0f; }
+        } else {
+            const u32x4 wa = path_block(key, 2 * g), wb = path_block(key, 2 * g + 1);
+            float z[8];
+            box_muller(wa.x, wa.y, z[0], z[1]);
+            box_muller(wa.z, wa.w, z[2], z[3]);
+            box_muller(wb.x, wb.y, z[4], z[5]);
+            box_muller(wb.z, wb.w, z[6], z[7]);
+            for (int k = 0; k < 4; ++k) { dw1[k] = P.sqh * z[2 * k]; dwp[k] = P.sqh * z[2 * k + 1]; }
+        }
+        if (PAYOFF == kLookback) {
+            const u32x4 u = path_block(make_path_key(a.seed, a.l, s, a.stream + 1u), g);
+            e[0] = P.lnu_scale * flog2<float>(u01f(u.x));
+            e[1] = P.lnu_scale * flog2<float>(u01f(u.y));
+            e[2] = P.lnu_scale * flog2<float>(u01f(u.z));
+            e[3] = P.lnu_scale * flog2<float>(u01f(u.w));
+        }
+        return;
+    }
+    const int T = a.nf * D, q = 4 / T;
+    const u32x4 w = path_block(make_path_key(a.seed, a.l, s / q, a.stream), 0);
+    float z[4];
+    box_muller(w.x, w.y, z[0], z[1]);
+    box_muller(w.z, w.w, z[2], z[3]);
+    const int base = (int)(s % q) * T;
+    for (int k = 0; k < 4; ++k) {
+        const int i1 = (base + k * D) & 3, i2 = (base + k * D + 1) & 3;
+        const float z1 = i1 == 0 ? z[0] : i1 == 1 ? z[1] : i1 == 2 ? z[2] : z[3];
+        const float z2 = i2 == 0 ? z[0] : i2 == 1 ? z[1] : i2 == 2 ? z[2] : z[3];
+        dw1[k] = P.sqh * z1;
+        dwp[k] = D == 2 ? P.sqh * z2 : 0.0f;
+    }
+    if (PAYOFF == kLookback) {
+        const int qu = 4 / a.nf;
+        const u32x4 u = path_block(make_path_key(a.seed, a.l, s / qu, a.stream + 1u), 0);
+        const int ub = (int)(s % qu) * a.nf;
+        for (int k = 0; k < 4; ++k) {
+            const int iw = (ub + k) & 3;
+            const uint32_t word = iw == 0 ? u.x : iw == 1 ? u.y : iw == 2 ? u.z : u.w;
+            e[k] = P.lnu_scale * flog2<float>(u01f(word));
+        }
+    }
+}
+
+// One sample per lane; every lane runs every network evaluation (samples
+// past the range are simulated and dropped), so waves stay converged.
+template <int MODEL, int PAYOFF, int M>
+__global__ __launch_bounds__(256) void cv_level_kernel(LevelArgs<float> a, CvKernelArgs c)
+{
+    constexpr int D = (MODEL == kGBM) ? 2 : 3;
+    __shared__ NetShared sh;
+    load_shared<D>(sh, c.params, c.nc);
+    __syncthreads();
+    bf16x8 A[2][4];
+    load_afwd(c.afwd, A);
+    const StepParams<float>& P = a.P;
+    const bool coupled = a.coupled && a.l > 0;
+    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+    unsigned nonfinite = 0;
+    const uint64_t nchunks = (a.N + blockDim.x - 1) / blockDim.x;
+    for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const uint64_t idx = ch * blockDim.x + threadIdx.x;
+        const uint64_t s = a.offset + idx;
+        PathPair<float> q;
+        init_pair<float, MODEL, PAYOFF>(q, P);
+        float phic = 0.0f;
+        for (uint32_t g = 0; g < a.ngroups; ++g) {
+            float dw1[4], dwp[4], e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            fetch_group<MODEL, PAYOFF>(a, s, g, dw1, dwp, e);
+            // not unrolled: one copy of each network evaluation in the code
+#pragma unroll 1
+            for (int k = 0; k < 4; ++k) {
+                const int n = 4 * (int)g + k;
+                if (n >= a.nf) break;                       // wave-uniform
+                const float d1 = k == 0 ? dw1[0] : k == 1 ? dw1[1] : k == 2 ? dw1[2] : dw1[3];
+                const float dp = k == 0 ? dwp[0] : k == 1 ? dwp[1] : k == 2 ? dwp[2] : dwp[3];
+                const float ek = k == 0 ? e[0] : k == 1 ? e[1] : k == 2 ? e[2] : e[3];
+                const float x0 = (float)n * P.h * sh.inv_T;
+                const float phif = phi_eval<D>(sh, A, x0, q.S, q.v);
+                q.cvf = __builtin_fmaf(phif, d1, q.cvf);
+                if (coupled && (n & (M - 1)) == 0) phic = phi_eval<D>(sh, A, x0, q.Sc, q.vc);
+                fine_step<float, MODEL, PAYOFF>(q, P, d1, dp, ek, n & (M - 1), coupled);
+                if (coupled && ((n + 1) & (M - 1)) == 0) {
+                    q.cvc = __builtin_fmaf(phic, q.dw1c, q.cvc);
+                    coarse_step<float, MODEL, PAYOFF>(q, P);
+                }
+            }
+        }
+        const float pf = payoff_value<float, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h) - q.cvf;
+        const float pc = coupled
+                             ? payoff_value<float, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H) - q.cvc
+                             : 0.0f;
+        if (idx < a.N) accumulate(a, idx, pf, pc, sums, nonfinite);
+    }
+    block_reduce_add(sums, nonfinite, a.acc);
+}
+
+// ------------------------------------------------------------ training
+// Loss over levels 0..lmax (the MLMC cost functional; total cost scales as
+// (sum_l sqrt(V_l C_l))^2):  loss = sum_l sqrt(C_l Var_batch(Y_l)),
+// dLoss/dY_i = sqrt(C_l / V_l) (Y_i - mean_l) / (B - 1).
+// One block per level: weights of every sample, the level's variance, and
+// its loss term (added into loss[0]).
+__global__ void cv_weights_kernel(const LevelAcc* rec, const double* ydump, uint64_t B, int M,
+                                  float* w, double* loss)
+{
+    const int l = blockIdx.x;
+    const double n = (double)B;
+    const double mean = rec[l].sum[0] / n;
+    double var = (rec[l].sum[1] - n * mean * mean) / (n - 1.0);
+    if (var < 0) var = 0;
+    double C = 1.0;
+    if (l > 0) {
+        double a = 1.0;
+        for (int i = 0; i < l - 1; ++i) a *= M;
+        C = a * M + a;
+    }
+    const double scale = var > 0 ? sqrt(C / var) / (n - 1.0) : 0.0;
+    const double* pf = ydump + 2 * (uint64_t)l * B;
+    const double* pc = pf + B;
+    for (uint64_t i = threadIdx.x; i < B; i += blockDim.x)
+        w[(uint64_t)l * B + i] = (float)(scale * ((pf[i] - pc[i]) - mean));
+    if (threadIdx.x == 0) {
+        loss[1 + l] = var;
+        atomicAdd(&loss[0], sqrt(C * var));
+    }
+}
+
+// Backward pass over the samples of one level (one wave per block): the
+// same paths as the forward pass, regenerated from their counters; every
+// evaluation point contributes with g = -w dW1 (fine) or +w dW1c (coarse).
+template <int MODEL, int PAYOFF, int M>
+__global__ __launch_bounds__(64) void cv_backward_kernel(LevelArgs<float> a, CvKernelArgs c,
+                                                          const bf16x8* abwd, const float* w,
+                                                          float* gpart)
+{
+    constexpr int D = (MODEL == kGBM) ? 2 : 3;
+    __shared__ NetShared sh;
+    __shared__ bf16x8 afw[8 * 64], abw[8 * 64];
+    __shared__ Stage st;
+    load_shared<D>(sh, c.params, c.nc);
+    for (int i = threadIdx.x; i < 8 * 64; i += blockDim.x) {
+        afw[i] = c.afwd[i];
+        abw[i] = abwd[i];
+    }
+    __syncthreads();
+    GradAcc acc;
+    zero_acc(acc);
+    const StepParams<float>& P = a.P;
+    const bool coupled = a.l > 0;
+    const int lane = threadIdx.x & 63;
+    const uint64_t nchunks = (a.N + 63) / 64;
+    for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const uint64_t idx = ch * 64 + lane;
+        const uint64_t s = a.offset + idx;
+        const float wp = idx < a.N ? w[idx] : 0.0f;
+        PathPair<float> q;
+        init_pair<float, MODEL, PAYOFF>(q, P);
+        for (uint32_t g = 0; g < a.ngroups; ++g) {
+            float dw1[4], dwp[4], e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            fetch_group<MODEL, PAYOFF>(a, s, g, dw1, dwp, e);
+#pragma unroll 1
+            for (int k = 0; k < 4; ++k) {
+                const int n = 4 * (int)g + k;
+                if (n >= a.nf) break;
+                const float d1 = k == 0 ? dw1[0] : k == 1 ? dw1[1] : k == 2 ? dw1[2] : dw1[3];
+                const float dp = k == 0 ? dwp[0] : k == 1 ? dwp[1] : k == 2 ? dwp[2] : dwp[3];
+                const float ek = k == 0 ? e[0] : k == 1 ? e[1] : k == 2 ? e[2] : e[3];
+                const float x0 = (float)n * P.h * sh.inv_T;
+                eval_backward<D>(sh, afw, abw, st, x0, q.S, q.v, -wp * d1, acc);
+                if (coupled && (n & (M - 1)) == 0) {
+                    // the coarse step starting here sums the next M fine increments
+                    const float dwc = (M == 4) ? dw1[0] + dw1[1] + dw1[2] + dw1[3]
+                                               : (k == 0 ? dw1[0] + dw1[1] : dw1[2] + dw1[3]);
+                    eval_backward<D>(sh, afw, abw, st, x0, q.Sc, q.vc, wp * dwc, acc);
+                }
+                fine_step<float, MODEL, PAYOFF>(q, P, d1, dp, ek, n & (M - 1), coupled);
+                if (coupled && ((n + 1) & (M - 1)) == 0) coarse_step<float, MODEL, PAYOFF>(q, P);
+            }
+        }
+    }
+    // per-block partial gradient (row blockIdx.x of gpart)
+    const int np = nparams(D);
+    float* row = gpart + (uint64_t)blockIdx.x * np;
+    const int h = lane >> 5;
+    float b3 = acc.gb3;
+    for (int m = 1; m < 64; m <<= 1) b3 += __shfl_xor(b3, m);
+    if (lane == 0) row[off_b3(D)] = b3;
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+        float v3 = acc.gw3[t], v2 = acc.gb2[t], v1 = acc.gb1[t];
+        float u0 = acc.gW1[0][t], u1 = acc.gW1[1][t], u2 = acc.gW1[2][t];
+        for (int m = 1; m < 32; m <<= 1) {     // sum over the lane's half
+            v3 += __shfl_xor(v3, m);
+            v2 += __shfl_xor(v2, m);
+            v1 += __shfl_xor(v1, m);
+            u0 += __shfl_xor(u0, m);
+            u1 += __shfl_xor(u1, m);
+            if (D == 3) u2 += __shfl_xor(u2, m);
+        }
+        if ((lane & 31) == 0) {
+            const int j = row_d(h, t / 16, t % 16);
+            row[off_w3(D) + j] = v3;
+            row[off_b2(D) + j] = v2 * sh.w3[j];
+            const int u = unit_b(h, t);
+            row[off_b1(D) + u] = v1;
+            row[u * D + 0] = u0;
+            row[u * D + 1] = u1;
+            if (D == 3) row[u * D + 2] = u2;
+        }
+    }
+#pragma unroll
+    for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+        for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int u = row_d(h, ut, r);             // rows of G are units
+                const int j = 32 * jt + (lane & 31);       // columns are layer-2 units
+                row[off_W2(D) + j * H + u] = acc.G[ut][jt][r];
+            }
+}
+
+// grad[i] = sum over the partial rows (fixed order).
+__global__ void cv_reduce_kernel(const float* gpart, int rows, int np, float* grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r) s += gpart[(uint64_t)r * np + i];
+    grad[i] = s;
+}
+
+// Adam (Kingma and Ba 2015) on the fp32 master parameters.
+__global__ void cv_adam_kernel(float* params, float* m1, float* m2, const float* grad, int np,
+                               float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float g = grad[i];
+    const float a = b1 * m1[i] + (1.0f - b1) * g;
+    const float v = b2 * m2[i] + (1.0f - b2) * g * g;
+    m1[i] = a;
+    m2[i] = v;
+    params[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// ----------------------------------------------------------- dispatch
+using CvFn = void (*)(LevelArgs<float>, CvKernelArgs);
+using CvBwdFn = void (*)(LevelArgs<float>, CvKernelArgs, const bf16x8*, const float*, float*);
+
+template <int MODEL, int PAYOFF>
+static CvBwdFn pick_bwd_m(int M)
+{
+    return M == 2 ? cv_backward_kernel<MODEL, PAYOFF, 2> : cv_backward_kernel<MODEL, PAYOFF, 4>;
+}
+
+template <int MODEL>
+static CvBwdFn pick_bwd_payoff(int payoff, int M)
+{
+    switch (payoff) {
+    case kCall: return pick_bwd_m<MODEL, kCall>(M);
+    case kAsian: return pick_bwd_m<MODEL, kAsian>(M);
+    case kLookback: return pick_bwd_m<MODEL, kLookback>(M);
+    default: return pick_bwd_m<MODEL, kDigital>(M);
+    }
+}
+
+template <int MODEL, int PAYOFF>
+static CvFn pick_cv_m(int M)
+{
+    return M == 2 ? cv_level_kernel<MODEL, PAYOFF, 2> : cv_level_kernel<MODEL, PAYOFF, 4>;
+}
+
+template <int MODEL>
+static CvFn pick_cv_payoff(int payoff, int M)
+{
+    switch (payoff) {
+    case kCall: return pick_cv_m<MODEL, kCall>(M);
+    case kAsian: return pick_cv_m<MODEL, kAsian>(M);
+    case kLookback: return pick_cv_m<MODEL, kLookback>(M);
+    default: return pick_cv_m<MODEL, kDigital>(M);
+    }
+}
+
+NetConsts net_consts(const mlmc_model& m)
+{
+    NetConsts c;
+    const double sref = m.kind == MLMC_GBM ? m.sigma : std::sqrt(m.theta);
+    c.scale = (float)(sref * m.S0);
+    const double a = std::log(2.0) / (sref * std::sqrt(m.T));
+    c.x1a = (float)a;
+    c.x1b = (float)(std::log2(m.S0) * a);
+    c.x2a = m.kind == MLMC_HESTON ? (float)(1.0 / m.theta) : 0.0f;
+    c.x2b = m.kind == MLMC_HESTON ? 1.0f : 0.0f;
+    c.inv_T = (float)(1.0 / m.T);
+    c.s_floor = (float)(m.S0 * std::ldexp(1.0, -40));
+    return c;
+}
+
+// phi(0, S0) for level 0 (written to cv->d_phi0 on the context's stream).
+hipError_t cv_launch_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st)
+{
+    CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
+    if (cv->D == 2)
+        hipLaunchKernelGGL(cv_phi0_kernel<2>, dim3(1), dim3(64), 0, st, c, (float)m.S0,
+                           (float)m.v0, cv->d_phi0);
+    else
+        hipLaunchKernelGGL(cv_phi0_kernel<3>, dim3(1), dim3(64), 0, st, c, (float)m.S0,
+                           (float)m.v0, cv->d_phi0);
+    return hipGetLastError();
+}
+
+hipError_t cv_launch_level(const mlmc_cv* cv, const mlmc_model& m, const mlmc_payoff& p, int M,
+                           const LevelArgs<float>& a, int grid, hipStream_t st)
+{
+    CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
+    CvFn fn = m.kind == MLMC_GBM ? pick_cv_payoff<kGBM>(p.kind, M) : pick_cv_payoff<kHeston>(p.kind, M);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, st, a, c);
+    return hipGetLastError();
+}
+
+// Scratch for a training batch of B samples per level, levels 0..lmax.
+static mlmc_status ensure_train(mlmc_cv* cv, uint64_t B, int lmax)
+{
+    mlmc_ctx* ctx = cv->ctx;
+    const uint64_t need = B * (uint64_t)(lmax + 1);
+    const int rows = (int)(((B + 63) / 64 < 512 ? (B + 63) / 64 : 512) * (lmax + 1));
+    if (cv->batch_cap < need) {
+        if (cv->d_y) hipFree(cv->d_y);
+        if (cv->d_w) hipFree(cv->d_w);
+        cv->d_y = nullptr;
+        cv->d_w = nullptr;
+        MLMC_HIP(ctx, hipMalloc(&cv->d_y, sizeof(double) * 2 * need));
+        MLMC_HIP(ctx, hipMalloc(&cv->d_w, sizeof(float) * need));
+        cv->batch_cap = need;
+    }
+    if (cv->gpart_blocks < rows + 1) {
+        if (cv->d_gpart) hipFree(cv->d_gpart);
+        cv->d_gpart = nullptr;
+        MLMC_HIP(ctx, hipMalloc(&cv->d_gpart, sizeof(float) * (uint64_t)(rows + 1) * cv->np));
+        cv->gpart_blocks = rows + 1;
+    }
+    return MLMC_OK;
+}
+
+// One loss/gradient evaluation: forward pass with per-sample dumps, weights,
+// backward pass into per-block partials, reduction into the last row of
+// d_gpart.  Everything is enqueued on the context's stream.
+static mlmc_status enqueue_loss_grad(mlmc_cv* cv, const mlmc_model& m, const mlmc_payoff& p, int M,
+                                     int lmax, uint64_t B, uint64_t seed, uint64_t step,
+                                     LevelAcc* rec, float** grad_out)
+{
+    mlmc_ctx* ctx = cv->ctx;
+    mlmc_status st = ensure_train(cv, B, lmax);
+    if (st) return st;
+    MLMC_HIP(ctx, zero_records(rec, lmax + 1, ctx->stream));
+    MLMC_HIP(ctx, hipMemsetAsync(cv->d_loss, 0, sizeof(double) * 64, ctx->stream));
+    const uint64_t offset = step * B;
+    for (int l = 0; l <= lmax; ++l) {
+        double* pf = cv->d_y + 2 * (uint64_t)l * B;
+        st = enqueue_level(ctx, m, p, l, M, B, seed, offset, 32, kStreamTrainNormal, 1, &rec[l], pf,
+                           pf + B, cv);
+        if (st) return st;
+    }
+    hipLaunchKernelGGL(cv_weights_kernel, dim3(lmax + 1), dim3(256), 0, ctx->stream,
+                       (const LevelAcc*)rec, (const double*)cv->d_y, B, M, cv->d_w, cv->d_loss);
+    MLMC_HIP(ctx, hipGetLastError());
+    CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
+    const int per_level = (int)((B + 63) / 64 < 512 ? (B + 63) / 64 : 512);
+    int row0 = 0;
+    const int tix = timed_begin(ctx, 18, 0.0, 0.0);
+    for (int l = 0; l <= lmax; ++l) {
+        LevelArgs<float> a;
+        a.P = make_step_params<float>(m, p, l, M);
+        a.seed = seed;
+        a.offset = offset;
+        a.N = B;
+        a.l = l;
+        int nf = 1;
+        for (int i = 0; i < l; ++i) nf *= M;
+        a.nf = nf;
+        a.ngroups = (uint32_t)((nf + 3) / 4);
+        a.stream = kStreamTrainNormal;
+        a.acc = nullptr;
+        a.pf_out = a.pc_out = nullptr;
+        a.coupled = 1;
+        a.phi0 = nullptr;
+        CvBwdFn fn = m.kind == MLMC_GBM ? pick_bwd_payoff<kGBM>(p.kind, M)
+                                        : pick_bwd_payoff<kHeston>(p.kind, M);
+        hipLaunchKernelGGL(fn, dim3(per_level), dim3(64), 0, ctx->stream, a, c,
+                           (const bf16x8*)cv->d_abwd, (const float*)(cv->d_w + (uint64_t)l * B),
+                           cv->d_gpart + (uint64_t)row0 * cv->np);
+        MLMC_HIP(ctx, hipGetLastError());
+        row0 += per_level;
+    }
+    float* grad = cv->d_gpart + (uint64_t)row0 * cv->np;
+    hipLaunchKernelGGL(cv_reduce_kernel, dim3((cv->np + 255) / 256), dim3(256), 0, ctx->stream,
+                       (const float*)cv->d_gpart, row0, cv->np, grad);
+    MLMC_HIP(ctx, hipGetLastError());
+    timed_end(ctx, tix);
+    *grad_out = grad;
+    return MLMC_OK;
+}
+
+static mlmc_status check_train_args(mlmc_cv* cv, const mlmc_model* m, const mlmc_payoff* p, int M,
+                                    int lmax, uint64_t B)
+{
+    mlmc_ctx* ctx = cv->ctx;
+    mlmc_status st = check_level_args(ctx, m, p, lmax < 0 ? 0 : lmax, M, 32);
+    if (st) return st;
+    if (lmax < 0 || lmax > 6) return fail(ctx, MLMC_EINVAL, "lmax must be in 0..6");
+    if (B < 2 || B > (1ull << 24)) return fail(ctx, MLMC_EINVAL, "batch must be in 2..2^24 per level");
+    if (cv->D != (m->kind == MLMC_HESTON ? 3 : 2))
+        return fail(ctx, MLMC_EINVAL, "network inputs do not match the model (2: GBM, 3: Heston)");
+    return MLMC_OK;
+}
+
+const float* cv_phi0_ptr(const mlmc_cv* cv) { return cv->d_phi0; }
+int cv_in_dim(const mlmc_cv* cv) { return cv->D; }
+
+static hipError_t cv_prepare(mlmc_cv* cv, hipStream_t st)
+{
+    hipLaunchKernelGGL(cv_prepare_kernel, dim3(1), dim3(256), 0, st, (const float*)cv->d_params,
+                       cv->D, cv->d_afwd, cv->d_abwd);
+    return hipGetLastError();
+}
+
+}  // namespace mlmc
+
+using namespace mlmc;
+
+extern "C" {
+
+mlmc_status mlmc_cv_destroy(mlmc_cv* cv)
+{
+    if (!cv) return MLMC_OK;
+    if (cv->ctx) hipSetDevice(cv->ctx->device);
+    for (void* p : {(void*)cv->d_params, (void*)cv->d_m1, (void*)cv->d_m2, (void*)cv->d_afwd,
+                    (void*)cv->d_abwd, (void*)cv->d_phi0, (void*)cv->d_gpart, (void*)cv->d_y,
+                    (void*)cv->d_w, (void*)cv->d_loss})
+        if (p) hipFree(p);
+    delete cv;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_cv_create(mlmc_ctx* ctx, int in_dim, int hidden, uint64_t init_seed, mlmc_cv** out)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (!out) return fail(ctx, MLMC_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if ((in_dim != 2 && in_dim != 3) || hidden != H)
+        return fail(ctx, MLMC_EINVAL, "in_dim must be 2 (GBM) or 3 (Heston) and hidden 64");
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    mlmc_cv* cv = new (std::nothrow) mlmc_cv();
+    if (!cv) return fail(ctx, MLMC_ENOMEM, "host allocation failed");
+    cv->ctx = ctx;
+    cv->D = in_dim;
+    cv->np = nparams(in_dim);
+    hipError_t e = hipMalloc(&cv->d_params, sizeof(float) * cv->np);
+    if (e == hipSuccess) e = hipMalloc(&cv->d_m1, sizeof(float) * cv->np);
+    if (e == hipSuccess) e = hipMalloc(&cv->d_m2, sizeof(float) * cv->np);
+    if (e == hipSuccess) e = hipMalloc(&cv->d_afwd, sizeof(bf16x8) * 8 * 64);
+    if (e == hipSuccess) e = hipMalloc(&cv->d_abwd, sizeof(bf16x8) * 8 * 64);
+    if (e == hipSuccess) e = hipMalloc(&cv->d_phi0, sizeof(float) * 4);
+    if (e == hipSuccess) e = hipMalloc(&cv->d_loss, sizeof(double) * 64);
+    if (e == hipSuccess) e = hipMemsetAsync(cv->d_m1, 0, sizeof(float) * cv->np, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(cv->d_m2, 0, sizeof(float) * cv->np, ctx->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(cv_init_kernel, dim3((cv->np + 255) / 256), dim3(256), 0, ctx->stream,
+                           cv->d_params, in_dim, init_seed);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = cv_prepare(cv, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        mlmc_cv_destroy(cv);
+        return hip_fail(ctx, e, "control variate allocation/initialisation");
+    }
+    *out = cv;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_cv_get_params(const mlmc_cv* cv, float* host, size_t n)
+{
+    if (!cv) return MLMC_EINVAL;
+    mlmc_ctx* ctx = cv->ctx;
+    if (!host || n != (size_t)cv->np) return fail(ctx, MLMC_EINVAL, "need a host array of nparams floats");
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    MLMC_HIP(ctx, hipMemcpyAsync(host, cv->d_params, sizeof(float) * n, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_cv_set_params(mlmc_cv* cv, const float* host, size_t n)
+{
+    if (!cv) return MLMC_EINVAL;
+    mlmc_ctx* ctx = cv->ctx;
+    if (!host || n != (size_t)cv->np) return fail(ctx, MLMC_EINVAL, "need a host array of nparams floats");
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(host[i])) return fail(ctx, MLMC_EINVAL, "parameters must be finite");
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    MLMC_HIP(ctx, hipMemcpyAsync(cv->d_params, host, sizeof(float) * n, hipMemcpyHostToDevice,
+                                 ctx->stream));
+    MLMC_HIP(ctx, cv_prepare(cv, ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return MLMC_OK;
+}
+
+size_t mlmc_cv_nparams(const mlmc_cv* cv) { return cv ? (size_t)cv->np : 0; }
+
+mlmc_status mlmc_cv_loss_grad(mlmc_cv* cv, const mlmc_model* model, const mlmc_payoff* payoff,
+                              int M, int lmax, uint64_t batch, uint64_t seed, uint64_t step,
+                              float* grad, double* var, double* loss)
+{
+    if (!cv) return MLMC_EINVAL;
+    mlmc_ctx* ctx = cv->ctx;
+    mlmc_status st = check_train_args(cv, model, payoff, M, lmax, batch);
+    if (st) return st;
+    ctx->err.clear();
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    float* d_grad = nullptr;
+    st = enqueue_loss_grad(cv, *model, *payoff, M, lmax, batch, seed, step, ctx->d_acc, &d_grad);
+    if (st) return st;
+    if (grad)
+        MLMC_HIP(ctx, hipMemcpyAsync(grad, d_grad, sizeof(float) * cv->np, hipMemcpyDeviceToHost,
+                                     ctx->stream));
+    double hl[64];
+    MLMC_HIP(ctx, hipMemcpyAsync(hl, cv->d_loss, sizeof(hl), hipMemcpyDeviceToHost, ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    harvest_timing(ctx);
+    if (loss) *loss = hl[0];
+    if (var)
+        for (int l = 0; l <= lmax; ++l) var[l] = hl[1 + l];
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_cv_train(mlmc_cv* cv, const mlmc_model* model, const mlmc_payoff* payoff, int M,
+                          int lmax, int steps, uint64_t batch, double lr, uint64_t seed,
+                          float* loss_hist)
+{
+    if (!cv) return MLMC_EINVAL;
+    mlmc_ctx* ctx = cv->ctx;
+    mlmc_status st = check_train_args(cv, model, payoff, M, lmax, batch);
+    if (st) return st;
+    if (steps < 0 || !(lr > 0)) return fail(ctx, MLMC_EINVAL, "need steps >= 0 and lr > 0");
+    ctx->err.clear();
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    double* d_hist = nullptr;
+    if (loss_hist && steps > 0) MLMC_HIP(ctx, hipMalloc(&d_hist, sizeof(double) * steps));
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int k = 0; k < steps; ++k) {
+        float* d_grad = nullptr;
+        // each step draws fresh training samples: indices t * batch .. (t+1) * batch - 1
+        st = enqueue_loss_grad(cv, *model, *payoff, M, lmax, batch, seed, (uint64_t)cv->adam_t, ctx->d_acc,
+                               &d_grad);
+        if (st) break;
+        cv->adam_t += 1;
+        const float c1 = 1.0f - std::pow(b1, (float)cv->adam_t);
+        const float c2 = 1.0f - std::pow(b2, (float)cv->adam_t);
+        hipLaunchKernelGGL(cv_adam_kernel, dim3((cv->np + 255) / 256), dim3(256), 0, ctx->stream,
+                           cv->d_params, cv->d_m1, cv->d_m2, (const float*)d_grad, cv->np, (float)lr,
+                           b1, b2, eps, c1, c2);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = cv_prepare(cv, ctx->stream);
+        if (e == hipSuccess && d_hist)
+            e = hipMemcpyAsync(d_hist + k, cv->d_loss, sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream);
+        if (e != hipSuccess) {
+            st = hip_fail(ctx, e, "training step");
+            break;
+        }
+    }
+    if (!st && d_hist) {
+        std::vector<double> h(steps);
+        hipError_t e = hipMemcpyAsync(h.data(), d_hist, sizeof(double) * steps,
+                                      hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = hip_fail(ctx, e, "loss history copy");
+        for (int k = 0; k < steps; ++k) loss_hist[k] = (float)h[k];
+    }
+    if (!st) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = hip_fail(ctx, e, "training");
+        harvest_timing(ctx);
+    }
+    if (d_hist) hipFree(d_hist);
+    return st;
+}
+
+}  // extern "C"

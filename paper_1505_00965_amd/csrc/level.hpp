@@ -24,6 +24,7 @@ struct LevelArgs {
     double* pf_out;       // optional per-path dump (fp64), else null
     double* pc_out;
     int coupled;          // 0: standard MC (fine path only at level l)
+    const float* phi0;    // level 0 with the control variate: phi(0, S0), else null
 };
 
 // Host-side conversion of model/payoff to the kernel's parameter block.

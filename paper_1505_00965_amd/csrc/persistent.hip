@@ -120,6 +120,7 @@ __device__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[k
     a.acc = nullptr;
     a.pf_out = a.pc_out = nullptr;
     a.coupled = 1;
+    a.phi0 = nullptr;
     if (nf < 4) {
         // one or two steps: samples share generator blocks
         constexpr int D = (MODEL == kGBM) ? 1 : 2;
@@ -318,7 +319,14 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     st = capture(ctx, m.kind, o.M, false, d_st, &g);
     if (st) return st;
     for (;;) {
-        const int tix = timed_begin(ctx, 16, 0.0, 0.0);
+        // the host copy holds the batch this launch samples (for timing only)
+        double fine = 0.0, coarse = 0.0;
+        for (int l = 0; l <= h_st->L; ++l) {
+            const double nf = std::pow((double)o.M, (double)l);
+            fine += h_st->dN[l] * nf;
+            coarse += l ? h_st->dN[l] * nf / o.M : 0.0;
+        }
+        const int tix = timed_begin(ctx, 16, fine, coarse);
         hipError_t e = hipGraphLaunch(g, ctx->stream);
         timed_end(ctx, tix);
         if (e == hipSuccess)

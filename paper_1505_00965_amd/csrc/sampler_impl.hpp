@@ -160,7 +160,9 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
                 fine_step<Real, MODEL, PAYOFF>(q, P, dw1, dwp, e[(ub + k) & 3], k % M, coupled);
             }
             if (NF == 2 && coupled) coarse_step<Real, MODEL, PAYOFF>(q, P);
-            const Real pf = payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
+            Real pf = payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
+            // level 0 with the control variate: every sample starts at (0, S0)
+            if (NF == 1 && a.phi0) pf -= (Real)(*a.phi0) * (P.sqh * z[r * T]);
             const Real pc = coupled ? payoff_value<Real, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H)
                                     : Real(0);
             if (s < a.offset || s - a.offset >= a.N) continue;

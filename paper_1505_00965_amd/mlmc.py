@@ -21,6 +21,8 @@ EXPORTED = [
     "mlmc_set_launch", "mlmc_level", "mlmc_level_paths", "mlmc_philox_words", "mlmc_normals",
     "mlmc_stdmc", "mlmc_optimal_n", "mlmc_run", "mlmc_set_timing", "mlmc_kernel_stats",
     "mlmc_levels_batch", "mlmc_set_persistent_launch",
+    "mlmc_cv_create", "mlmc_cv_destroy", "mlmc_cv_nparams", "mlmc_cv_get_params",
+    "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train",
 ]
 STAT_SLOTS = 20
 STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
@@ -114,11 +116,20 @@ def lib():
     L.mlmc_levels_batch.argtypes = [vp, M_, P_, i32, i32, i32, C.POINTER(u64), C.POINTER(u64),
                                     u64, C.POINTER(LevelResult)]
     L.mlmc_set_persistent_launch.argtypes = [vp, i32, i32, i32]
+    L.mlmc_cv_create.argtypes = [vp, i32, i32, u64, C.POINTER(vp)]
+    L.mlmc_cv_destroy.argtypes = [vp]
+    L.mlmc_cv_nparams.argtypes = [vp]
+    L.mlmc_cv_get_params.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
+    L.mlmc_cv_set_params.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
+    L.mlmc_cv_loss_grad.argtypes = [vp, M_, P_, i32, i32, u64, u64, u64, C.POINTER(C.c_float),
+                                    C.POINTER(d), C.POINTER(d)]
+    L.mlmc_cv_train.argtypes = [vp, M_, P_, i32, i32, i32, u64, d, u64, C.POINTER(C.c_float)]
     L.mlmc_set_timing.argtypes = [vp, i32]
     L.mlmc_kernel_stats.argtypes = [vp, C.POINTER(KernelStat)]
     for name in EXPORTED:
         if name != "mlmc_last_error":
             getattr(L, name).restype = i32
+    L.mlmc_cv_nparams.restype = C.c_size_t
     _lib = L
     return L
 
@@ -268,3 +279,63 @@ def _cvh(cv):
     if cv is None:
         return None
     return cv.h
+
+
+class ControlVariate:
+    """An mlmc_cv network on a Context (parameters live on the device)."""
+
+    def __init__(self, ctx, in_dim=2, hidden=64, init_seed=1):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        h = C.c_void_p()
+        ctx._check(self._lib.mlmc_cv_create(ctx.h, in_dim, hidden, init_seed, C.byref(h)))
+        self.h = h
+        self.in_dim = in_dim
+
+    def close(self):
+        if self.h:
+            self._lib.mlmc_cv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nparams(self):
+        return int(self._lib.mlmc_cv_nparams(self.h))
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.nparams, dtype=np.float32)
+        self.ctx._check(self._lib.mlmc_cv_get_params(
+            self.h, out.ctypes.data_as(C.POINTER(C.c_float)), out.size))
+        return out
+
+    def loss_grad(self, m, p, M, lmax, batch, seed, step):
+        """(loss, grad[nparams] float32, var[lmax+1]) of one training batch."""
+        import numpy as np
+        g = np.zeros(self.nparams, dtype=np.float32)
+        var = (C.c_double * (lmax + 1))()
+        loss = C.c_double()
+        self.ctx._check(self._lib.mlmc_cv_loss_grad(
+            self.h, C.byref(m), C.byref(p), M, lmax, batch, seed, step,
+            g.ctypes.data_as(C.POINTER(C.c_float)), var, C.byref(loss)))
+        return loss.value, g, list(var)
+
+    def train(self, m, p, M=4, lmax=3, steps=2000, batch=16384, lr=1e-3, seed=1):
+        """Adam training on the device; returns the loss history (float32)."""
+        import numpy as np
+        hist = np.zeros(max(steps, 1), dtype=np.float32)
+        self.ctx._check(self._lib.mlmc_cv_train(
+            self.h, C.byref(m), C.byref(p), M, lmax, steps, batch, lr, seed,
+            hist.ctypes.data_as(C.POINTER(C.c_float))))
+        return hist[:steps]
+
+    def set_params(self, values):
+        import numpy as np
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        self.ctx._check(self._lib.mlmc_cv_set_params(
+            self.h, v.ctypes.data_as(C.POINTER(C.c_float)), v.size))
