@@ -42,6 +42,28 @@ def algorithmic_ops(level, fine_steps, samples):
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def measured_traffic(kernel_label):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None if the kernel sources changed since it was taken."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("philox.hpp", "sampler.hpp", "sampler_impl.hpp", "reduce.hpp", "level.hip",
+              "level.hpp"):
+        with open(os.path.join(ROOT, "paper_1505_00965_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*pmc*.md")):
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", "-", " ")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("kernel") == kernel_label and fields.get("kernel_sources_sha256") == digest:
+            return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +74,10 @@ def parse():
                     help="approximate CPU work for the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip seconds-to-RMSE runs")
+    ap.add_argument("--cv-steps", type=int, default=2000,
+                    help="Adam steps for the control-variate networks (0: plain only)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 256 MiB device copy first (scales HBM byte counters)")
     ap.add_argument("--persistent", type=int, default=0,
                     help="1: each driver iteration is one graph launch of the persistent kernel")
     return ap.parse_args()
@@ -86,6 +112,87 @@ def cpu_baseline(ref_run, M, budget_s):
                       f"scaled by {scale:.3g} ({fine:.3g} fine path steps, {dt:.1f} s, fp64)"}
 
 
+def median_run(ctx, m, p, eps, M, cv, seeds):
+    """Median wall seconds (measured inside mlmc_run) and the median run."""
+    runs = sorted((ctx.mlmc_run(m, p, eps, M=M, seed=s, precision=32, cv=cv) for s in seeds),
+                  key=lambda r: r["wall_s"])
+    mid = runs[len(runs) // 2]
+    return mid["wall_s"], mid
+
+
+def time_to_accuracy(ctx, mlmc, W, args):
+    """Seconds to RMSE eps, plain MLMC vs the learned control variate.
+
+    The network is trained once per model (Adam, lr 1e-3, batch 16384 samples
+    per level on levels 0..3, i.e. 65536 per step) on the training streams;
+    its training time is reported separately and is not part of the
+    estimation timings, since a trained network is reused.
+    """
+    import torch
+    out = {}
+    cases = (("gbm_asian", W.GBM_MODEL, W.ASIAN, 2), ("heston_call", W.HESTON_MODEL, W.CALL, 3),
+             ("gbm_call", W.GBM_MODEL, W.CALL, 2))
+    seeds = range(1, 6)
+    for name, md, pd, d in cases:
+        m, p = mlmc.model(**md), mlmc.payoff(**pd)
+        entry = {}
+        cv = None
+        if name != "gbm_call" and args.cv_steps > 0:
+            cv = mlmc.ControlVariate(ctx, d, init_seed=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hist = cv.train(m, p, M=4, lmax=3, steps=args.cv_steps, batch=16384, lr=1e-3, seed=2)
+            torch.cuda.synchronize()
+            entry["train_s"] = time.perf_counter() - t0
+            entry["train_steps"] = args.cv_steps
+            entry["loss_first_last"] = [float(hist[0]), float(hist[-1])]
+        for eps in (1e-3, 5e-4):
+            key = f"eps_{eps:g}_S0"
+            tp, rp = median_run(ctx, m, p, eps * W.S0, 4, None, seeds)
+            e = {"plain_s": tp, "plain_cost": rp["cost"], "plain_N": rp["N"],
+                 "plain_V": [round(v, 6) for v in rp["V"]]}
+            if cv is not None:
+                tc, rc = median_run(ctx, m, p, eps * W.S0, 4, cv, seeds)
+                e.update({"cv_s": tc, "cv_cost": rc["cost"], "cv_N": rc["N"],
+                          "cv_V": [round(v, 6) for v in rc["V"]], "speedup": tp / tc})
+            entry[key] = e
+        if cv is not None:
+            cv.close()
+        out[name] = entry
+    return out
+
+
+def persistent_batch(ctx, mlmc, W, reps=3):
+    """All levels 0..8 of four payoffs (N_l = 2^26 4^-l) in one graph-replayed
+    persistent launch, against the sum of the 36 per-level launches."""
+    import torch
+    gm = mlmc.model(**W.GBM_MODEL)
+    names = ("call", "asian", "lookback", "digital")
+    pays = [mlmc.payoff(**W.PAYOFFS[n]) for n in names]
+    L = 8
+    N = [[W.persistent_n(l) for l in range(L + 1)] for _ in pays]
+    fine = sum(N[0][l] * 4**l for l in range(L + 1)) * len(pays)
+    ctx.mlmc_levels_batch(gm, pays, 4, L, N, seed=1)          # capture + warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        ctx.mlmc_levels_batch(gm, pays, 4, L, N, seed=1 + r)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for r in range(reps):
+        for p in pays:
+            for l in range(L + 1):
+                ctx.mlmc_level(gm, p, l, 4, N[0][l], 1 + r)
+    torch.cuda.synchronize()
+    t_levels = (time.perf_counter() - t0) / reps
+    return {"workload": "GBM call/Asian/lookback/digital, M=4, levels 0..8, N_l = 2^26 4^-l",
+            "fine_path_steps": fine, "persistent_ms": 1e3 * t_batch,
+            "per_level_launches_ms": 1e3 * t_levels,
+            "persistent_fine_steps_per_s": fine / t_batch,
+            "per_level_fine_steps_per_s": fine / t_levels}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -96,6 +203,13 @@ def main():
     from paper_1505_00965_amd import mlmc, workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    if args.copy_calibration:
+        # a copy of known size: 256 MiB read + 256 MiB written
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = mlmc.Context(0)
     stream = torch.cuda.current_stream()
     ctx.set_stream(stream)
@@ -108,7 +222,7 @@ def main():
                             precision=32, persistent=bool(args.persistent))
 
     for i in range(args.warmup):
-        step(1000 + i)
+        step(1 + i % max(args.steps, 1))   # same seeds, hence launch sizes, as timed steps
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -145,11 +259,12 @@ def main():
             samples = s["fine_steps"] / M**lv
             ops_per_launch = algorithmic_ops(lv, s["fine_steps"], samples) / s["launches"]
             achieved = ops_per_launch / (avg_ms * 1e-3)
+            label = ("short_level_kernel<GBM,call,fp32,n_f=1>" if lv == 0
+                     else f"level_kernel<GBM,call,fp32,M=4> at level {lv}")
             roofline = {"bound": "alu", "achieved": achieved / 1e12,
                         "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
-                        "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                        "kernel": ("short_level_kernel<GBM,call,fp32,n_f=1> (level 0)" if lv == 0
-                                   else f"level_kernel<GBM,call,fp32,M=4> at level {lv}"),
+                        "frac": achieved / VALU_PEAK_OPS, "traffic": measured_traffic(label),
+                        "kernel": label,
                         "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_ms,
                         "launches": s["launches"],
                         "fine_steps_per_launch": s["fine_steps"] / s["launches"]}
@@ -167,16 +282,8 @@ def main():
             "roofline": roofline}
 
     if not args.no_tta:
-        tta = {}
-        for name, pd in (("gbm_call", W.CALL), ("gbm_asian", W.ASIAN)):
-            pp = mlmc.payoff(**pd)
-            ts = []
-            for seed in range(1, 6):
-                r = ctx.mlmc_run(gm, pp, 1e-3 * W.S0, M=M, seed=seed, precision=32)
-                ts.append(r["wall_s"])
-            ts.sort()
-            tta[f"plain_{name}"] = ts[len(ts) // 2]
-        line["seconds_to_rmse_1e-3_S0"] = tta
+        line["persistent_batch"] = persistent_batch(ctx, mlmc, W)
+        line["seconds_to_rmse"] = time_to_accuracy(ctx, mlmc, W, args)
 
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(runs[-1], M, args.cpu_seconds)

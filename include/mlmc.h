@@ -117,6 +117,20 @@ mlmc_status mlmc_set_timing(mlmc_ctx* ctx, int on);
 /* Copy MLMC_STAT_SLOTS statistics into out (host array). */
 mlmc_status mlmc_kernel_stats(mlmc_ctx* ctx, mlmc_kernel_stat* out);
 
+/* Autotuner: times every block size {64..1024} x samples-per-lane {1,2,4}
+ * (fp64: 1) of the level sampler on a device-filling sample count for three
+ * level classes (one-step levels, 2..16 fine steps, longer paths) and keeps
+ * the fastest for this (model, payoff, precision, M); later launches use it
+ * unless mlmc_set_launch fixed a shape.  Results are cached in the JSON file
+ * cache_path (or $MLMC_TUNE_CACHE; NULL/"" and no variable: no cache) under
+ * a key of GPU architecture, compute-unit count and HIP runtime version, and
+ * read back instead of measured when present.                             */
+mlmc_status mlmc_autotune(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff, int M,
+                          int precision, const char* cache_path);
+/* Shape the tuner chose for level l (block = ppt = 0 if none). */
+mlmc_status mlmc_tuned_shape(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                             int l, int M, int precision, int* block, int* ppt);
+
 /* Level estimator sums (eqs. (eq:mlmc:Yzero), (eq:Yldef)).
  *   l >= 0, M in {2, 4}, M^l <= 4^8 * 4 (262144 steps), N >= 0 paths
  *   seed: Philox key; path_offset: index of the first sample, so further

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlmc.so")
-SOURCES = ["capi.cpp", "level.hip", "driver.hip", "persistent.hip", "cv.hip"]
+SOURCES = ["capi.cpp", "level.hip", "driver.hip", "persistent.hip", "cv.hip", "autotune.cpp"]
 ARCH = "gfx950"
 
 

@@ -1,0 +1,234 @@
+// Launch-shape autotuner: picks block size and samples per lane for the
+// level sampler (per model, payoff, precision, M and level class) and block
+// size, samples per lane and resident blocks per compute unit for the
+// persistent kernel, by timing candidates with HIP events on the device
+// itself.  Results are results of measurement, so they are cached in a small
+// JSON file keyed by GPU architecture, compute-unit count and HIP runtime
+// version; a later context on the same machine reads them back instead of
+// measuring again.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+
+#include "context.hpp"
+
+namespace mlmc {
+
+// Level classes: one-step levels (shared generator blocks), short paths
+// (2..16 fine steps) and long paths.
+int level_class(int l, int M)
+{
+    int nf = 1;
+    for (int i = 0; i < l; ++i) nf *= M;
+    if (nf < 4) return 0;
+    if (nf <= 16) return 1;
+    return 2;
+}
+
+static std::string tune_key(int model, int payoff, int precision, int M, int cls)
+{
+    char b[64];
+    std::snprintf(b, sizeof b, "level:%d:%d:%d:%d:%d", model, payoff, precision, M, cls);
+    return b;
+}
+
+static std::string machine_key(const mlmc_ctx* ctx)
+{
+    hipDeviceProp_t prop;
+    hipGetDeviceProperties(&prop, ctx->device);
+    int rt = 0;
+    hipRuntimeGetVersion(&rt);
+    char b[160];
+    std::snprintf(b, sizeof b, "%s|cu%d|hip%d", prop.gcnArchName, prop.multiProcessorCount, rt);
+    return b;
+}
+
+// Minimal JSON of the form {"machine": {"key": [a, b, c], ...}, ...}.
+static std::map<std::string, std::map<std::string, std::vector<int>>> read_cache(const std::string& path)
+{
+    std::map<std::string, std::map<std::string, std::vector<int>>> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t i = 0;
+    auto skip = [&]() { while (i < s.size() && std::strchr(" \t\r\n,:", s[i])) ++i; };
+    auto str = [&](std::string& v) -> bool {
+        skip();
+        if (i >= s.size() || s[i] != '"') return false;
+        const size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) return false;
+        v = s.substr(i + 1, j - i - 1);
+        i = j + 1;
+        return true;
+    };
+    skip();
+    if (i >= s.size() || s[i] != '{') return out;
+    ++i;
+    for (;;) {
+        std::string mk;
+        if (!str(mk)) break;
+        skip();
+        if (i >= s.size() || s[i] != '{') break;
+        ++i;
+        for (;;) {
+            std::string k;
+            if (!str(k)) break;
+            skip();
+            if (i >= s.size() || s[i] != '[') break;
+            ++i;
+            std::vector<int> v;
+            for (;;) {
+                skip();
+                if (i < s.size() && s[i] == ']') { ++i; break; }
+                char* end = nullptr;
+                const long x = std::strtol(s.c_str() + i, &end, 10);
+                if (end == s.c_str() + i) return out;
+                v.push_back((int)x);
+                i = end - s.c_str();
+            }
+            out[mk][k] = v;
+        }
+        skip();
+        if (i < s.size() && s[i] == '}') ++i;
+    }
+    return out;
+}
+
+static bool write_cache(const std::string& path,
+                        const std::map<std::string, std::map<std::string, std::vector<int>>>& c)
+{
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    size_t a = 0;
+    for (const auto& m : c) {
+        std::fprintf(f, "  \"%s\": {\n", m.first.c_str());
+        size_t b = 0;
+        for (const auto& e : m.second) {
+            std::fprintf(f, "    \"%s\": [", e.first.c_str());
+            for (size_t k = 0; k < e.second.size(); ++k)
+                std::fprintf(f, "%s%d", k ? ", " : "", e.second[k]);
+            std::fprintf(f, "]%s\n", ++b < m.second.size() ? "," : "");
+        }
+        std::fprintf(f, "  }%s\n", ++a < c.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    return std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+bool tuned_shape(const mlmc_ctx* ctx, int model, int payoff, int precision, int M, int l,
+                 int* block, int* ppt)
+{
+    auto it = ctx->tuned.find(tune_key(model, payoff, precision, M, level_class(l, M)));
+    if (it == ctx->tuned.end() || it->second.size() < 2) return false;
+    *block = it->second[0];
+    *ppt = it->second[1];
+    return true;
+}
+
+// Time one level launch shape (median of 3 after a warm-up), milliseconds.
+static float time_shape(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
+                        uint64_t N, int precision, int block, int ppt, mlmc_status* st)
+{
+    const int saved_b = ctx->launch_block, saved_p = ctx->launch_ppt;
+    ctx->launch_block = block;
+    ctx->launch_ppt = ppt;
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    float best[3] = {1e30f, 1e30f, 1e30f};
+    for (int rep = 0; rep < 4 && !*st; ++rep) {
+        hipEventRecord(a, ctx->stream);
+        *st = enqueue_level(ctx, m, p, l, M, N, 12345, 0, precision, kStreamNormal, 1, ctx->d_acc,
+                            nullptr, nullptr, nullptr);
+        hipEventRecord(b, ctx->stream);
+        if (hipEventSynchronize(b) != hipSuccess) *st = MLMC_EDEVICE;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, a, b);
+        if (rep > 0) best[rep - 1] = ms;
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    ctx->launch_block = saved_b;
+    ctx->launch_ppt = saved_p;
+    std::sort(best, best + 3);
+    return best[1];
+}
+
+}  // namespace mlmc
+
+using namespace mlmc;
+
+extern "C" {
+
+mlmc_status mlmc_autotune(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff, int M,
+                          int precision, const char* cache_path)
+{
+    if (!ctx) return MLMC_EINVAL;
+    mlmc_status st = check_level_args(ctx, model, payoff, 0, M, precision);
+    if (st) return st;
+    ctx->err.clear();
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    std::string path;
+    if (cache_path && *cache_path) path = cache_path;
+    else if (const char* e = std::getenv("MLMC_TUNE_CACHE")) path = e;
+    const std::string mk = machine_key(ctx);
+    auto cache = path.empty() ? decltype(read_cache(path)){} : read_cache(path);
+    bool dirty = false;
+    const int blocks[] = {64, 128, 256, 512, 1024};
+    const int ppts32[] = {1, 2, 4};
+    // representative levels and sizes per class: saturate the device
+    const int reps[3] = {0, M == 4 ? 2 : 3, M == 4 ? 4 : 7};
+    for (int cls = 0; cls < 3; ++cls) {
+        const std::string key = tune_key(model->kind, payoff->kind, precision, M, cls);
+        auto mit = cache.find(mk);
+        if (mit != cache.end() && mit->second.count(key)) {
+            ctx->tuned[key] = mit->second[key];
+            continue;
+        }
+        const int l = reps[cls];
+        double nf = 1.0;
+        for (int i = 0; i < l; ++i) nf *= M;
+        const uint64_t N = (uint64_t)std::max(1.0, (double)(1ull << 27) / nf);
+        float best = 1e30f;
+        int bb = 256, bp = precision == 64 ? 1 : 2;
+        for (int b : blocks)
+            for (int p : ppts32) {
+                if (precision == 64 && p != 1) continue;
+                if (cls == 0 && p == 4) continue;
+                const float ms = time_shape(ctx, *model, *payoff, l, M, N, precision, b, p, &st);
+                if (st) return st;
+                if (ms < best) { best = ms; bb = b; bp = p; }
+            }
+        ctx->tuned[key] = {bb, bp};
+        cache[mk][key] = {bb, bp};
+        dirty = true;
+    }
+    if (dirty && !path.empty() && !write_cache(path, cache))
+        return fail(ctx, MLMC_EINVAL, "could not write the tuning cache " + path);
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_tuned_shape(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                             int l, int M, int precision, int* block, int* ppt)
+{
+    if (!ctx || !model || !payoff || !block || !ppt) return MLMC_EINVAL;
+    if (!tuned_shape(ctx, model->kind, payoff->kind, precision, M, l, block, ppt)) {
+        *block = 0;
+        *ppt = 0;
+    }
+    return MLMC_OK;
+}
+
+}  // extern "C"

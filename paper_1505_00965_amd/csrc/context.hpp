@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,8 @@ struct mlmc_ctx {
     std::vector<hipEvent_t> event_pool;
     std::vector<Timed> pending;
     mlmc_kernel_stat stats[MLMC_STAT_SLOTS] = {};
+    // tuned launch shapes (autotune.cpp), keyed by kernel and problem class
+    std::map<std::string, std::vector<int>> tuned;
 };
 
 namespace mlmc {
@@ -73,6 +76,11 @@ void timed_end(mlmc_ctx* ctx, int idx);
 void harvest_timing(mlmc_ctx* ctx);
 
 void free_persistent(mlmc_ctx* ctx);
+
+// Tuned shape of the level sampler for this problem, if the tuner ran.
+bool tuned_shape(const mlmc_ctx* ctx, int model, int payoff, int precision, int M, int l,
+                 int* block, int* ppt);
+int level_class(int l, int M);
 
 // Control variate (cv.hip).
 hipError_t cv_launch_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st);

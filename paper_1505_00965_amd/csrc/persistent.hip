@@ -52,54 +52,75 @@ struct BatchDesc {
     unsigned* count;                  // number of items
     unsigned resident_blocks;         // grid size of the sampler
     unsigned chunk;                   // blockDim * PPT of the sampler
+    unsigned block;                   // blockDim of the sampler
 };
 
-// One thread plans every item of the batch.
-__global__ void plan_kernel(const BatchDesc* d)
+// Plan: thread 0 sizes every (slot, level) pair's items and lays the pairs
+// out deepest level first; then the block writes the items in parallel.
+__global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int L = d->L, M = d->M;
-    double total = 0.0;
-    for (int s = 0; s < d->nslots; ++s)
-        for (int l = 0; l <= L; ++l) {
+    constexpr int kPairs = kMaxSlots * kMaxLevels;
+    __shared__ uint64_t s_first[kPairs], s_left[kPairs], s_per[kPairs];
+    __shared__ unsigned s_start[kPairs + 1];
+    __shared__ int s_slot[kPairs], s_level[kPairs];
+    __shared__ int s_npairs;
+    if (threadIdx.x == 0) {
+        const int L = d->L, M = d->M;
+        double total = 0.0;
+        for (int s = 0; s < d->nslots; ++s)
+            for (int l = 0; l <= L; ++l) {
+                const double nf = pow((double)M, (double)l);
+                total += d->dN[s * kMaxLevels + l] * (nf + (l ? nf / M : 0.0));
+            }
+        const double target = total / ((double)d->resident_blocks * kItemsPerBlock);
+        unsigned count = 0;
+        int np = 0;
+        for (int l = L; l >= 0; --l) {          // deepest (longest) items first
             const double nf = pow((double)M, (double)l);
-            total += d->dN[s * kMaxLevels + l] * (nf + (l ? nf / M : 0.0));
-        }
-    double target = total / ((double)d->resident_blocks * kItemsPerBlock);
-    unsigned count = 0;
-    // deepest (longest) items first
-    for (int l = L; l >= 0; --l) {
-        const double nf = pow((double)M, (double)l);
-        const double per = nf + (l ? nf / M : 0.0);
-        double want = target / per;
-        uint64_t paths = (uint64_t)want;
-        // whole chunks where possible; small items at least one wave
-        if (paths >= d->chunk) paths = (paths / d->chunk) * d->chunk;
-        else if (paths < 64) paths = 64;
-        if (paths > (1ull << 31)) paths = 1ull << 31;   // item counts fit 32 bits
-        for (int s = 0; s < d->nslots; ++s) {
-            uint64_t left = (uint64_t)d->dN[s * kMaxLevels + l];
-            uint64_t first = (uint64_t)d->offset[s * kMaxLevels + l];
-            // at most kItemsPerPair items per (slot, level), so the table
-            // (kMaxSlots * kMaxLevels * kItemsPerPair = kMaxItems) never fills
-            const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
-            const uint64_t per_item = paths > min_items ? paths : min_items;
-            while (left > 0) {
-                const uint64_t n = left < per_item ? left : per_item;
-                WorkItem w;
-                w.first = first;
-                w.n = (uint32_t)n;
-                w.level = (uint16_t)l;
-                w.slot = (uint8_t)s;
-                w.pad = 0;
-                d->items[count++] = w;
-                first += n;
-                left -= n;
+            const double per = nf + (l ? nf / M : 0.0);
+            uint64_t paths = (uint64_t)(target / per);
+            // whole chunks where possible; at least one sample per lane of a block
+            if (paths >= d->chunk) paths = (paths / d->chunk) * d->chunk;
+            else if (paths < d->block) paths = d->block;
+            if (paths > (1ull << 31)) paths = 1ull << 31;   // item counts fit 32 bits
+            for (int s = 0; s < d->nslots; ++s) {
+                const uint64_t left = (uint64_t)d->dN[s * kMaxLevels + l];
+                if (left == 0) continue;
+                // at most kItemsPerPair items per pair: the table never fills
+                const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
+                const uint64_t per_item = paths > min_items ? paths : min_items;
+                s_first[np] = (uint64_t)d->offset[s * kMaxLevels + l];
+                s_left[np] = left;
+                s_per[np] = per_item;
+                s_slot[np] = s;
+                s_level[np] = l;
+                s_start[np] = count;
+                count += (unsigned)((left + per_item - 1) / per_item);
+                ++np;
             }
         }
+        s_start[np] = count;
+        s_npairs = np;
+        *d->count = count;
+        *d->head = 0;
     }
-    *d->count = count;
-    *d->head = 0;
+    __syncthreads();
+    const int np = s_npairs;
+    const unsigned count = s_start[np];
+    for (unsigned k = threadIdx.x; k < count; k += blockDim.x) {
+        int q = 0;
+        while (q + 1 < np && s_start[q + 1] <= k) ++q;
+        const uint64_t i = k - s_start[q];
+        const uint64_t done = i * s_per[q];
+        const uint64_t n = s_left[q] - done < s_per[q] ? s_left[q] - done : s_per[q];
+        WorkItem w;
+        w.first = s_first[q] + done;
+        w.n = (uint32_t)n;
+        w.level = (uint16_t)s_level[q];
+        w.slot = (uint8_t)s_slot[q];
+        w.pad = 0;
+        d->items[k] = w;
+    }
 }
 
 template <int MODEL, int PAYOFF, int M, int PPT>
@@ -208,7 +229,7 @@ static PersistentShape persistent_shape(const mlmc_ctx* ctx)
 {
     PersistentShape s;
     s.block = ctx->persist_block ? ctx->persist_block : 256;
-    s.ppt = ctx->persist_ppt ? ctx->persist_ppt : 2;
+    s.ppt = ctx->persist_ppt ? ctx->persist_ppt : 1;
     s.blocks_per_cu = ctx->persist_bpc ? ctx->persist_bpc : 4;
     return s;
 }
@@ -271,6 +292,7 @@ static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const ml
     h->count = b->d_counters + 1;
     h->resident_blocks = (unsigned)(ctx->num_cu * s.blocks_per_cu);
     h->chunk = (unsigned)(s.block * s.ppt);
+    h->block = (unsigned)s.block;
 }
 
 // Capture [prologue?] -> plan -> persistent -> [epilogue] into a graph.
@@ -285,7 +307,7 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess && zero_batch) e = zero_records(b->d_acc, kMaxSlots * kMaxLevels, cs);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, cs, (const BatchDesc*)b->d_desc);
+        hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, cs, (const BatchDesc*)b->d_desc);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {

@@ -22,7 +22,8 @@ EXPORTED = [
     "mlmc_stdmc", "mlmc_optimal_n", "mlmc_run", "mlmc_set_timing", "mlmc_kernel_stats",
     "mlmc_levels_batch", "mlmc_set_persistent_launch",
     "mlmc_cv_create", "mlmc_cv_destroy", "mlmc_cv_nparams", "mlmc_cv_get_params",
-    "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train",
+    "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train", "mlmc_autotune",
+    "mlmc_tuned_shape",
 ]
 STAT_SLOTS = 20
 STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
@@ -124,6 +125,8 @@ def lib():
     L.mlmc_cv_loss_grad.argtypes = [vp, M_, P_, i32, i32, u64, u64, u64, C.POINTER(C.c_float),
                                     C.POINTER(d), C.POINTER(d)]
     L.mlmc_cv_train.argtypes = [vp, M_, P_, i32, i32, i32, u64, d, u64, C.POINTER(C.c_float)]
+    L.mlmc_autotune.argtypes = [vp, M_, P_, i32, i32, C.c_char_p]
+    L.mlmc_tuned_shape.argtypes = [vp, M_, P_, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.mlmc_set_timing.argtypes = [vp, i32]
     L.mlmc_kernel_stats.argtypes = [vp, C.POINTER(KernelStat)]
     for name in EXPORTED:
@@ -202,6 +205,16 @@ class Context:
         arr = (KernelStat * STAT_SLOTS)()
         self._check(self._lib.mlmc_kernel_stats(self.h, arr))
         return [{k: getattr(a, k) for k, _ in KernelStat._fields_} for a in arr]
+
+    def autotune(self, m, p, M=4, precision=32, cache_path=None):
+        self._check(self._lib.mlmc_autotune(self.h, C.byref(m), C.byref(p), M, precision,
+                                            cache_path.encode() if cache_path else None))
+
+    def tuned_shape(self, m, p, l, M=4, precision=32):
+        b, q = C.c_int(), C.c_int()
+        self._check(self._lib.mlmc_tuned_shape(self.h, C.byref(m), C.byref(p), l, M, precision,
+                                               C.byref(b), C.byref(q)))
+        return b.value, q.value
 
     def set_launch(self, block=0, ppt=0):
         self._check(self._lib.mlmc_set_launch(self.h, block, ppt))

@@ -1,0 +1,33 @@
+"""Autotuner: picks measured shapes, caches them, and never changes results."""
+import json
+import os
+
+import pytest
+
+from paper_1505_00965_amd import mlmc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_cache_and_invariance(tmp_path):
+    path = str(tmp_path / "tune.json")
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    with mlmc.Context(0) as ctx:
+        ref = [ctx.mlmc_level(gm, gp, l, 4, 50000, 3) for l in (0, 2, 5)]
+        ctx.autotune(gm, gp, M=4, precision=32, cache_path=path)
+        shapes = [ctx.tuned_shape(gm, gp, l) for l in (0, 2, 5)]
+        for b, p in shapes:
+            assert b in (64, 128, 256, 512, 1024) and p in (1, 2, 4)
+        assert shapes[0][1] in (1, 2)            # one-step levels take at most 2 blocks per lane
+        got = [ctx.mlmc_level(gm, gp, l, 4, 50000, 3) for l in (0, 2, 5)]
+        for a, b in zip(ref, got):
+            assert abs(a["sum_y"] - b["sum_y"]) <= 1e-12 * abs(a["sum_y"])
+    data = json.load(open(path))
+    (machine, entries), = data.items()
+    assert "gfx950" in machine and len(entries) == 3
+    # a new context reads the cache instead of measuring
+    with mlmc.Context(0) as ctx:
+        assert ctx.tuned_shape(gm, gp, 2) == (0, 0)
+        ctx.autotune(gm, gp, M=4, precision=32, cache_path=path)
+        assert [ctx.tuned_shape(gm, gp, l) for l in (0, 2, 5)] == shapes
+    assert os.path.getsize(path) > 0
