@@ -24,13 +24,13 @@ sys.path.insert(0, ROOT)
 METRIC = "seconds to RMSE 1e-3·S0 (learned-CV vs plain MLMC); fine path-steps/s"
 UNIT = "fine path-steps/s"
 
-# Algorithmic vector-ALU operations of the GBM call sampler, M = 4 (the
-# derivation is in the design doc): per fine step, a quarter Philox4x32-10 call
-# (10 rounds of 2 32x32->64 products and 2 three-input xors: 10), half a
-# Box-Muller pair (6.5), increment and Euler step (3), coarse increment sum
-# and a quarter coarse step (1.5); per sample, payoffs and fp64 sums.
-OPS_PER_FINE_STEP = 21.0
-OPS_PER_SAMPLE_L0 = 25.5      # level 0: the one step plus payoff and Y, Y^2 sums
+# Algorithmic vector-ALU operations of the GBM call sampler, M = 4: per fine
+# step, a quarter Philox4x32-10 call (10 rounds of 2 32x32->64 products and 2
+# three-input xors: 10), half a Box-Muller pair with sqrt(h) folded into its
+# radius (6.5), the Euler step (2 fma), coarse increment sum and a quarter
+# coarse step (1.5); per sample, payoffs and fp64 sums.
+OPS_PER_FINE_STEP = 20.0
+OPS_PER_SAMPLE_L0 = 24.5      # level 0: the one step plus payoff (3) and Y, Y^2 sums (3)
 OPS_PER_SAMPLE = 11.0         # levels >= 1: two payoffs, difference, sums
 
 
@@ -112,10 +112,10 @@ def cpu_baseline(ref_run, M, budget_s):
                       f"scaled by {scale:.3g} ({fine:.3g} fine path steps, {dt:.1f} s, fp64)"}
 
 
-def median_run(ctx, m, p, eps, M, cv, seeds):
+def median_run(ctx, m, p, eps, M, cv, seeds, cv_levels=0):
     """Median wall seconds (measured inside mlmc_run) and the median run."""
-    runs = sorted((ctx.mlmc_run(m, p, eps, M=M, seed=s, precision=32, cv=cv) for s in seeds),
-                  key=lambda r: r["wall_s"])
+    runs = sorted((ctx.mlmc_run(m, p, eps, M=M, seed=s, precision=32, cv=cv, cv_levels=cv_levels)
+                   for s in seeds), key=lambda r: r["wall_s"])
     mid = runs[len(runs) // 2]
     return mid["wall_s"], mid
 
@@ -146,7 +146,7 @@ def time_to_accuracy(ctx, mlmc, W, args):
             entry["train_s"] = time.perf_counter() - t0
             entry["train_steps"] = args.cv_steps
             entry["loss_first_last"] = [float(hist[0]), float(hist[-1])]
-        for eps in (1e-3, 5e-4):
+        for eps in (1e-3, 5e-4, 1e-4):
             key = f"eps_{eps:g}_S0"
             tp, rp = median_run(ctx, m, p, eps * W.S0, 4, None, seeds)
             e = {"plain_s": tp, "plain_cost": rp["cost"], "plain_N": rp["N"],
@@ -155,6 +155,10 @@ def time_to_accuracy(ctx, mlmc, W, args):
                 tc, rc = median_run(ctx, m, p, eps * W.S0, 4, cv, seeds)
                 e.update({"cv_s": tc, "cv_cost": rc["cost"], "cv_N": rc["N"],
                           "cv_V": [round(v, 6) for v in rc["V"]], "speedup": tp / tc})
+                # the network on level 0 only: one evaluation per launch
+                t0, r0 = median_run(ctx, m, p, eps * W.S0, 4, cv, seeds, cv_levels=1)
+                e.update({"cv_level0_s": t0, "cv_level0_cost": r0["cost"], "cv_level0_N": r0["N"],
+                          "speedup_level0": tp / t0})
             entry[key] = e
         if cv is not None:
             cv.close()
@@ -191,6 +195,23 @@ def persistent_batch(ctx, mlmc, W, reps=3):
             "per_level_launches_ms": 1e3 * t_levels,
             "persistent_fine_steps_per_s": fine / t_batch,
             "per_level_fine_steps_per_s": fine / t_levels}
+
+
+def fig3(ctx, mlmc, W):
+    """The paper's Sec. 6 experiment on the GPU: N_l per level and eps^2 x cost
+    and time for adaptive MLMC and standard Monte Carlo, call and digital."""
+    from paper_1505_00965_amd import complexity
+    out = {"workload": "GBM r=0.05 sigma=0.25 S0=100 T=1, K=100, M=2, fp32 paths, "
+                       "eps (absolute) " + ", ".join(f"{e:g}" for e in W.FIG3_EPS)}
+    for name, pay in (("call", W.FIG3_CALL), ("digital", W.FIG3_DIGITAL)):
+        recs = complexity.sweep(ctx, mlmc.model(**W.FIG3_MODEL), mlmc.payoff(**pay), W.FIG3_EPS,
+                                **W.FIG3_RUN)
+        keep = ("eps", "L", "N", "estimate", "eps2_mlmc_cost", "eps2_std_cost", "mlmc_s",
+                "std_s", "std_scaled")
+        out[name] = {"runs": [{k: r[k] for k in keep} for r in recs],
+                     "shape_checks": {what: ok for what, ok in
+                                      complexity.shape_checks(recs, pay["kind"])}}
+    return out
 
 
 def main():
@@ -284,6 +305,7 @@ def main():
     if not args.no_tta:
         line["persistent_batch"] = persistent_batch(ctx, mlmc, W)
         line["seconds_to_rmse"] = time_to_accuracy(ctx, mlmc, W, args)
+        line["fig3"] = fig3(ctx, mlmc, W)
 
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(runs[-1], M, args.cpu_seconds)

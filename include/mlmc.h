@@ -207,7 +207,13 @@ typedef struct {
                             persistent all-levels kernel; 0: one launch per
                             level                                             */
     double alpha, beta;  /* assumed weak and variance rates (<= 0: 1 and 1) */
-    const mlmc_cv* cv;   /* NULL: plain MLMC                                 */
+    const mlmc_cv* cv;   /* NULL: plain MLMC.  Needs precision 32 and
+                            persistent 0 (MLMC_EINVAL otherwise).             */
+    int cv_levels;       /* with cv: apply it on levels l < cv_levels only
+                            (0 = every level).  Each level estimator keeps its
+                            mean either way, so any split is unbiased; level 0
+                            costs one network evaluation per launch, deeper
+                            levels one per path step.                          */
 } mlmc_run_opts;
 
 #define MLMC_MAX_LEVELS 16

@@ -149,6 +149,23 @@ int timed_begin(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_steps)
     return (int)ctx->pending.size() - 1;
 }
 
+void timed_kernel(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_steps,
+                  hipEvent_t* start, hipEvent_t* stop)
+{
+    *start = *stop = nullptr;
+    if (!ctx->timing) return;
+    mlmc_ctx::Timed t;
+    t.start = pool_event(ctx);
+    t.stop = pool_event(ctx);
+    if (!t.start || !t.stop) return;
+    t.slot = slot;
+    t.fine_steps = fine_steps;
+    t.coarse_steps = coarse_steps;
+    ctx->pending.push_back(t);
+    *start = t.start;
+    *stop = t.stop;
+}
+
 void timed_end(mlmc_ctx* ctx, int idx)
 {
     if (idx < 0) return;
@@ -186,13 +203,13 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
         hipError_t e;
         if (l == 0) {
             // one step from (0, S0): phi is the single value phi(0, S0)
-            e = cv_launch_phi0(cv, m, ctx->stream);
+            e = cv_ensure_phi0(cv, m, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "phi(0, S0) launch");
             a.phi0 = cv_phi0_ptr(cv);
             LaunchShape shape = choose_shape(ctx, m, p, l, M, 32, N);
-            const int tix = timed_begin(ctx, 0, (double)N, 0.0);
-            e = launch_level(m, p, M, 32, &a, shape, ctx->stream);
-            timed_end(ctx, tix);
+            hipEvent_t t0, t1;
+            timed_kernel(ctx, 0, (double)N, 0.0, &t0, &t1);
+            e = launch_level(m, p, M, 32, &a, shape, ctx->stream, t0, t1);
         } else {
             const uint64_t chunks = (N + 255) / 256;
             const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, (uint64_t)ctx->num_cu * 8));
@@ -205,17 +222,17 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
     }
     const LaunchShape shape = choose_shape(ctx, m, p, l, M, precision, N);
     const double nf = (double)level_steps(l, M);
-    const int tix = timed_begin(ctx, l < 16 ? l : 15, (double)N * nf,
-                                (coupled && l > 0) ? (double)N * nf / M : 0.0);
+    hipEvent_t t0, t1;
+    timed_kernel(ctx, l < 16 ? l : 15, (double)N * nf, (coupled && l > 0) ? (double)N * nf / M : 0.0,
+                 &t0, &t1);
     hipError_t e;
     if (precision == 64) {
         auto a = make_args<double>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
-        e = launch_level(m, p, M, 64, &a, shape, ctx->stream);
+        e = launch_level(m, p, M, 64, &a, shape, ctx->stream, t0, t1);
     } else {
         auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
-        e = launch_level(m, p, M, 32, &a, shape, ctx->stream);
+        e = launch_level(m, p, M, 32, &a, shape, ctx->stream, t0, t1);
     }
-    timed_end(ctx, tix);
     if (e != hipSuccess) return hip_fail(ctx, e, "level kernel launch");
     return MLMC_OK;
 }

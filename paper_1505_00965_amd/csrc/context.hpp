@@ -23,7 +23,8 @@ struct mlmc_ctx {
     mlmc::LevelAcc* h_acc = nullptr;
     // Driver state on the device and its pinned host mirror (driver.hip).
     void* d_drv = nullptr;
-    void* h_drv = nullptr;
+    void* h_drv = nullptr;        // pinned host mirror of the driver state
+    void* h_drv_dev = nullptr;    // the same memory as the device sees it
     double* d_tmp = nullptr;                // small fp64 scratch (optimal_n)
     double* h_tmp = nullptr;
     // kernel timing (mlmc_set_timing)
@@ -72,6 +73,10 @@ hipError_t zero_records(LevelAcc* acc, int n, hipStream_t st);
 // timed_begin returns an index for timed_end, or -1.
 int timed_begin(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_steps);
 void timed_end(mlmc_ctx* ctx, int idx);
+// Event pair for a kernel launched with start/stop events (nullptr, nullptr
+// when timing is off); harvested like timed_begin's.
+void timed_kernel(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_steps,
+                  hipEvent_t* start, hipEvent_t* stop);
 // After the stream has been synchronised: fold finished events into stats.
 void harvest_timing(mlmc_ctx* ctx);
 
@@ -83,7 +88,7 @@ bool tuned_shape(const mlmc_ctx* ctx, int model, int payoff, int precision, int 
 int level_class(int l, int M);
 
 // Control variate (cv.hip).
-hipError_t cv_launch_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st);
+hipError_t cv_ensure_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st);
 hipError_t cv_launch_level(const mlmc_cv* cv, const mlmc_model& m, const mlmc_payoff& p, int M,
                            const LevelArgs<float>& a, int grid, hipStream_t st);
 const float* cv_phi0_ptr(const mlmc_cv* cv);

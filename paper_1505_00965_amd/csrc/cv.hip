@@ -28,8 +28,12 @@ struct mlmc_cv {
     float* d_m2 = nullptr;
     bf16x8* d_afwd = nullptr;     // bf16 W2 operands (forward), 8 x 64 entries
     bf16x8* d_abwd = nullptr;     // bf16 W2 operands (backward, permuted)
-    float* d_phi0 = nullptr;      // phi(0, S0) of the last model used
+    float* d_phi0 = nullptr;      // phi(0, S0), cached: see cv_ensure_phi0
     int adam_t = 0;
+    uint64_t version = 0;         // bumped by every parameter change
+    uint64_t phi0_version = ~0ull;
+    mlmc_model phi0_model{};
+    hipStream_t phi0_stream = nullptr;
     // training scratch
     float* d_gpart = nullptr;     // per-block gradient partials
     int gpart_blocks = 0;
@@ -137,18 +141,15 @@ __device__ __forceinline__ void fetch_group(const LevelArgs<float>& a, uint64_t 
     if (a.nf >= 4) {
         if (MODEL == kGBM) {
             const u32x4 w = path_block(key, g);
-            float z[4];
-            box_muller(w.x, w.y, z[0], z[1]);
-            box_muller(w.z, w.w, z[2], z[3]);
-            for (int k = 0; k < 4; ++k) { dw1[k] = P.sqh * z[k]; dwp[k] = 0.0f; }
+            brownian_pair(w.x, w.y, P, dw1[0], dw1[1]);
+            brownian_pair(w.z, w.w, P, dw1[2], dw1[3]);
+            for (int k = 0; k < 4; ++k) dwp[k] = 0.0f;
         } else {
             const u32x4 wa = path_block(key, 2 * g), wb = path_block(key, 2 * g + 1);
-            float z[8];
-            box_muller(wa.x, wa.y, z[0], z[1]);
-            box_muller(wa.z, wa.w, z[2], z[3]);
-            box_muller(wb.x, wb.y, z[4], z[5]);
-            box_muller(wb.z, wb.w, z[6], z[7]);
-            for (int k = 0; k < 4; ++k) { dw1[k] = P.sqh * z[2 * k]; dwp[k] = P.sqh * z[2 * k + 1]; }
+            brownian_pair(wa.x, wa.y, P, dw1[0], dwp[0]);
+            brownian_pair(wa.z, wa.w, P, dw1[1], dwp[1]);
+            brownian_pair(wb.x, wb.y, P, dw1[2], dwp[2]);
+            brownian_pair(wb.z, wb.w, P, dw1[3], dwp[3]);
         }
         if (PAYOFF == kLookback) {
             const u32x4 u = path_block(make_path_key(a.seed, a.l, s, a.stream + 1u), g);
@@ -162,15 +163,15 @@ __device__ __forceinline__ void fetch_group(const LevelArgs<float>& a, uint64_t 
     const int T = a.nf * D, q = 4 / T;
     const u32x4 w = path_block(make_path_key(a.seed, a.l, s / q, a.stream), 0);
     float z[4];
-    box_muller(w.x, w.y, z[0], z[1]);
-    box_muller(w.z, w.w, z[2], z[3]);
+    brownian_pair(w.x, w.y, P, z[0], z[1]);
+    brownian_pair(w.z, w.w, P, z[2], z[3]);
     const int base = (int)(s % q) * T;
     for (int k = 0; k < 4; ++k) {
         const int i1 = (base + k * D) & 3, i2 = (base + k * D + 1) & 3;
         const float z1 = i1 == 0 ? z[0] : i1 == 1 ? z[1] : i1 == 2 ? z[2] : z[3];
         const float z2 = i2 == 0 ? z[0] : i2 == 1 ? z[1] : i2 == 2 ? z[2] : z[3];
-        dw1[k] = P.sqh * z1;
-        dwp[k] = D == 2 ? P.sqh * z2 : 0.0f;
+        dw1[k] = z1;
+        dwp[k] = D == 2 ? z2 : 0.0f;
     }
     if (PAYOFF == kLookback) {
         const int qu = 4 / a.nf;
@@ -440,9 +441,21 @@ NetConsts net_consts(const mlmc_model& m)
     return c;
 }
 
-// phi(0, S0) for level 0 (written to cv->d_phi0 on the context's stream).
-hipError_t cv_launch_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st)
+static bool same_model(const mlmc_model& a, const mlmc_model& b)
 {
+    return a.kind == b.kind && a.S0 == b.S0 && a.r == b.r && a.sigma == b.sigma && a.T == b.T &&
+           a.kappa == b.kappa && a.theta == b.theta && a.xi == b.xi && a.rho == b.rho && a.v0 == b.v0;
+}
+
+// phi(0, S0) for level 0 in cv->d_phi0.  The value depends only on the
+// parameters and the model, so it is computed once per parameter change,
+// model and stream (a launch on another stream would not be ordered after
+// the write) and level-0 launches reuse it.
+hipError_t cv_ensure_phi0(const mlmc_cv* ccv, const mlmc_model& m, hipStream_t st)
+{
+    mlmc_cv* cv = const_cast<mlmc_cv*>(ccv);
+    if (cv->phi0_version == cv->version && cv->phi0_stream == st && same_model(cv->phi0_model, m))
+        return hipSuccess;
     CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
     if (cv->D == 2)
         hipLaunchKernelGGL(cv_phi0_kernel<2>, dim3(1), dim3(64), 0, st, c, (float)m.S0,
@@ -450,7 +463,13 @@ hipError_t cv_launch_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st
     else
         hipLaunchKernelGGL(cv_phi0_kernel<3>, dim3(1), dim3(64), 0, st, c, (float)m.S0,
                            (float)m.v0, cv->d_phi0);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        cv->phi0_version = cv->version;
+        cv->phi0_stream = st;
+        cv->phi0_model = m;
+    }
+    return e;
 }
 
 hipError_t cv_launch_level(const mlmc_cv* cv, const mlmc_model& m, const mlmc_payoff& p, int M,
@@ -563,6 +582,7 @@ int cv_in_dim(const mlmc_cv* cv) { return cv->D; }
 
 static hipError_t cv_prepare(mlmc_cv* cv, hipStream_t st)
 {
+    ++cv->version;
     hipLaunchKernelGGL(cv_prepare_kernel, dim3(1), dim3(256), 0, st, (const float*)cv->d_params,
                        cv->D, cv->d_afwd, cv->d_abwd);
     return hipGetLastError();

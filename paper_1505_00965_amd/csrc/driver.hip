@@ -12,7 +12,9 @@
 // estimated from weak order alpha (eq. (eq:emweak)).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 
@@ -135,14 +137,70 @@ __device__ void driver_update_dev(DriverState* st)
     }
 }
 
-__global__ void driver_update_kernel(DriverState* st)
+// The update is a serial chain of a few hundred dependent fp64 operations on
+// the state, so the state is staged in LDS (a global round trip per access
+// would dominate), updated by one lane, and written back.  The same words go
+// to the host's pinned mirror: everything but `seq` first, then a
+// system-scope fence, then `seq`, so a host that sees the new `seq` sees the
+// whole update (the host waits on it instead of a copy and a stream
+// synchronisation).
+__global__ void driver_update_kernel(DriverState* st, DriverState* mirror)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) driver_update_dev(st);
+    static_assert(sizeof(DriverState) % 8 == 0, "state is copied in 8-byte words");
+    static_assert(offsetof(DriverState, seq) % 8 == 0, "seq is one word");
+    constexpr int kWords = sizeof(DriverState) / 8;
+    constexpr int kSeq = offsetof(DriverState, seq) / 8;
+    __shared__ DriverState s;
+    const unsigned long long* src = (const unsigned long long*)st;
+    unsigned long long* w = (unsigned long long*)&s;
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        driver_update_dev(&s);
+        s.seq += 1;
+    }
+    __syncthreads();
+    unsigned long long* dst = (unsigned long long*)st;
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = w[i];
+    if (mirror) {
+        volatile unsigned long long* h = (volatile unsigned long long*)mirror;
+        for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+            if (i != kSeq) h[i] = w[i];
+        __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0) h[kSeq] = w[kSeq];
+    }
 }
 
-hipError_t launch_driver_update(DriverState* st, hipStream_t stream)
+// Wait until the host mirror shows update number `want`.  Spinning on the
+// mirror saves the completion signal and wake-up of a stream synchronisation;
+// the stream is polled as well, so a failed launch ends the wait with its
+// error.
+hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long long want)
 {
-    hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(64), 0, stream, st);
+    const volatile unsigned long long* seq = &h->seq;
+    auto next_poll = std::chrono::steady_clock::now() + std::chrono::milliseconds(1);
+    for (;;) {
+        if (*seq >= want) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return hipSuccess;
+        }
+        // querying the stream costs the runtime work; once a millisecond is enough
+        if (std::chrono::steady_clock::now() >= next_poll) {
+            next_poll += std::chrono::milliseconds(1);
+            const hipError_t e = hipStreamQuery(stream);
+            if (e == hipSuccess) {
+                std::atomic_thread_fence(std::memory_order_acquire);
+                return *seq >= want ? hipSuccess : hipErrorUnknown;
+            }
+            if (e != hipErrorNotReady) return e;
+        }
+    }
+}
+
+hipError_t launch_driver_update(DriverState* st, DriverState* mirror, hipStream_t stream)
+{
+    hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror);
     return hipGetLastError();
 }
 
@@ -151,6 +209,7 @@ static mlmc_status ensure_driver(mlmc_ctx* ctx)
     if (ctx->d_drv) return MLMC_OK;
     MLMC_HIP(ctx, hipMalloc(&ctx->d_drv, sizeof(DriverState)));
     MLMC_HIP(ctx, hipHostMalloc(&ctx->h_drv, sizeof(DriverState)));
+    MLMC_HIP(ctx, hipHostGetDevicePointer(&ctx->h_drv_dev, ctx->h_drv, 0));
     return MLMC_OK;
 }
 
@@ -169,7 +228,7 @@ mlmc_status mlmc_driver_free(mlmc_ctx* ctx)
     if (!ctx) return MLMC_OK;
     if (ctx->d_drv) hipFree(ctx->d_drv);
     if (ctx->h_drv) hipHostFree(ctx->h_drv);
-    ctx->d_drv = ctx->h_drv = nullptr;
+    ctx->d_drv = ctx->h_drv = ctx->h_drv_dev = nullptr;
     return MLMC_OK;
 }
 
@@ -214,6 +273,8 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     if (o.n_pilot < 2) return fail(ctx, MLMC_EINVAL, "n_pilot must be >= 2");
     if (o.cv && o.precision != 32)
         return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
+    if (o.cv && o.persistent)
+        return fail(ctx, MLMC_EINVAL, "the control variate runs with per-level launches only");
     ctx->err.clear();
     const auto t0 = std::chrono::steady_clock::now();
     MLMC_HIP(ctx, hipSetDevice(ctx->device));
@@ -236,23 +297,27 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
         st = run_persistent(ctx, *model, *payoff, o, d, h);
         if (st) return st;
     } else {
-        for (;;) {
+        for (int it = 0;; ++it) {
+            // the device stops at max_iterations; a host loop past that means
+            // the mirror is not being written
+            if (it > h->max_iterations + 1)
+                return fail(ctx, MLMC_EDEVICE, "driver state did not reach the host");
             for (int l = 0; l <= h->L; ++l) {
                 if (h->dN[l] <= 0) continue;
+                const mlmc_cv* cv = (o.cv && (o.cv_levels <= 0 || l < o.cv_levels)) ? o.cv : nullptr;
                 st = enqueue_level(ctx, *model, *payoff, l, o.M, (uint64_t)h->dN[l], o.seed,
                                    (uint64_t)h->n[l], o.precision, kStreamNormal, 1, &d->batch[l],
-                                   nullptr, nullptr, o.cv);
+                                   nullptr, nullptr, cv);
                 if (st) return st;
             }
             const int tix = timed_begin(ctx, 17, 0.0, 0.0);
-            MLMC_HIP(ctx, launch_driver_update(d, ctx->stream));
+            MLMC_HIP(ctx, launch_driver_update(d, (DriverState*)ctx->h_drv_dev, ctx->stream));
             timed_end(ctx, tix);
-            MLMC_HIP(ctx, hipMemcpyAsync(h, d, sizeof(DriverState), hipMemcpyDeviceToHost,
-                                         ctx->stream));
-            MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            harvest_timing(ctx);
+            MLMC_HIP(ctx, wait_update(ctx->stream, h, (unsigned long long)it + 1));
             if (h->done) break;
         }
+        MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        harvest_timing(ctx);
     }
     const auto t1 = std::chrono::steady_clock::now();
     std::memset(out, 0, sizeof(*out));

@@ -30,6 +30,8 @@ struct DriverState {
     // persistent form: work table bookkeeping (persistent.hip)
     unsigned int work_head, work_count;
     unsigned int pad0, pad1;
+    // number of updates published to the host mirror (written there last)
+    unsigned long long seq;
     LevelAcc batch[kMaxLevels];
 };
 

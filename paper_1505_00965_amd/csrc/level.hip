@@ -10,6 +10,8 @@
 // launch, so waves never diverge in the path loop.
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "level.hpp"
 #include "sampler_impl.hpp"
 
@@ -126,17 +128,18 @@ static KernelFn<Real> pick(int model, int payoff, int M, int ppt, int nf)
 }
 
 hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int precision,
-                        const void* args, LaunchShape shape, hipStream_t stream)
+                        const void* args, LaunchShape shape, hipStream_t stream, hipEvent_t start,
+                        hipEvent_t stop)
 {
     dim3 grid(shape.grid), block(shape.block);
     if (precision == 64) {
         const auto& a = *(const LevelArgs<double>*)args;
         auto fn = pick<double>(m.kind, p.kind, M, 1, a.nf);
-        hipLaunchKernelGGL(fn, grid, block, 0, stream, a);
+        hipExtLaunchKernelGGL(fn, grid, block, 0, stream, start, stop, 0, a);
     } else {
         const auto& a = *(const LevelArgs<float>*)args;
         auto fn = pick<float>(m.kind, p.kind, M, shape.ppt, a.nf);
-        hipLaunchKernelGGL(fn, grid, block, 0, stream, a);
+        hipExtLaunchKernelGGL(fn, grid, block, 0, stream, start, stop, 0, a);
     }
     return hipGetLastError();
 }

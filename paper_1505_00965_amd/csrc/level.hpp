@@ -37,8 +37,11 @@ struct LaunchShape {
 };
 
 // Enqueue one level's sampler on `stream` (accumulating into args.acc).
-// Returns hipSuccess or the launch error.  Shape chosen by the caller.
+// Returns hipSuccess or the launch error.  Shape chosen by the caller.  With
+// start/stop events the runtime stamps them when the kernel itself starts and
+// ends (hipExtLaunchKernelGGL), so they time the kernel, not the queue.
 hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int precision,
-                        const void* args, LaunchShape shape, hipStream_t stream);
+                        const void* args, LaunchShape shape, hipStream_t stream,
+                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 
 }  // namespace mlmc

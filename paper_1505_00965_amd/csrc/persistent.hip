@@ -204,7 +204,8 @@ static PersistentFn pick_persistent(int model, int M, int ppt)
     return M == 2 ? pick_ppt<kHeston, 2>(ppt) : pick_ppt<kHeston, 4>(ppt);
 }
 
-hipError_t launch_driver_update(DriverState* st, hipStream_t stream);
+hipError_t launch_driver_update(DriverState* st, DriverState* mirror, hipStream_t stream);
+hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long long want);
 
 // Device buffers of the persistent form, owned by the context.
 struct PersistentBufs {
@@ -217,6 +218,8 @@ struct PersistentBufs {
     double* h_req = nullptr;
     hipGraphExec_t graph = nullptr;   // cached batch graph
     int graph_key[5] = {-1, -1, -1, -1, -1};
+    hipGraphExec_t run_graph = nullptr;   // cached driver-iteration graph
+    int run_key[5] = {-1, -1, -1, -1, -1};
 };
 
 static PersistentBufs* bufs_of(mlmc_ctx* ctx);
@@ -257,6 +260,7 @@ void free_persistent(mlmc_ctx* ctx)
     auto* b = bufs_of(ctx);
     if (!b) return;
     if (b->graph) hipGraphExecDestroy(b->graph);
+    if (b->run_graph) hipGraphExecDestroy(b->run_graph);
     if (b->d_desc) hipFree(b->d_desc);
     if (b->h_desc) hipHostFree(b->h_desc);
     if (b->d_items) hipFree(b->d_items);
@@ -315,7 +319,8 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
                            dim3(s.block), 0, cs, (const BatchDesc*)b->d_desc);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && driver) e = launch_driver_update(driver, cs);
+    if (e == hipSuccess && driver)
+        e = launch_driver_update(driver, (DriverState*)ctx->h_drv_dev, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -337,10 +342,21 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, o.seed, d_st->dN, d_st->n, d_st->batch);
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
                                  ctx->stream));
-    hipGraphExec_t g = nullptr;
-    st = capture(ctx, m.kind, o.M, false, d_st, &g);
-    if (st) return st;
-    for (;;) {
+    // the graph reads the descriptor, the driver state and its mirror at
+    // replay, all fixed per context: one capture serves every run
+    const PersistentShape s = persistent_shape(ctx);
+    const int key[5] = {m.kind, o.M, s.block, s.ppt, s.blocks_per_cu};
+    if (!b->run_graph || std::memcmp(key, b->run_key, sizeof(key)) != 0) {
+        if (b->run_graph) hipGraphExecDestroy(b->run_graph);
+        b->run_graph = nullptr;
+        st = capture(ctx, m.kind, o.M, false, d_st, &b->run_graph);
+        if (st) return st;
+        std::memcpy(b->run_key, key, sizeof(key));
+    }
+    hipGraphExec_t g = b->run_graph;
+    for (int it = 0;; ++it) {
+        if (it > h_st->max_iterations + 1)
+            return fail(ctx, MLMC_EDEVICE, "driver state did not reach the host");
         // the host copy holds the batch this launch samples (for timing only)
         double fine = 0.0, coarse = 0.0;
         for (int l = 0; l <= h_st->L; ++l) {
@@ -351,17 +367,14 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
         const int tix = timed_begin(ctx, 16, fine, coarse);
         hipError_t e = hipGraphLaunch(g, ctx->stream);
         timed_end(ctx, tix);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h_st, d_st, sizeof(DriverState), hipMemcpyDeviceToHost, ctx->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) {
-            hipGraphExecDestroy(g);
-            return hip_fail(ctx, e, "persistent iteration");
-        }
-        harvest_timing(ctx);
+        // the update kernel inside the graph also writes the host mirror h_st
+        if (e == hipSuccess) e = wait_update(ctx->stream, h_st, (unsigned long long)it + 1);
+        if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
         if (h_st->done) break;
     }
-    hipGraphExecDestroy(g);
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    harvest_timing(ctx);
+    if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
     return MLMC_OK;
 }
 
@@ -388,8 +401,9 @@ mlmc_status mlmc_set_persistent_launch(mlmc_ctx* ctx, int block, int ppt, int bl
     }
     if (auto* b = bufs_of(ctx)) {
         if (b->graph) hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-        b->graph_key[0] = -1;
+        if (b->run_graph) hipGraphExecDestroy(b->run_graph);
+        b->graph = b->run_graph = nullptr;
+        b->graph_key[0] = b->run_key[0] = -1;
     }
     return MLMC_OK;
 }

@@ -50,11 +50,40 @@ template <>
 __device__ __forceinline__ double flog2<double>(double x) { return log2(x); }
 
 template <typename Real>
+__device__ __forceinline__ Real fmaxT(Real a, Real b);
+template <>
+__device__ __forceinline__ float fmaxT<float>(float a, float b) { return __builtin_fmaxf(a, b); }
+template <>
+__device__ __forceinline__ double fmaxT<double>(double a, double b) { return __builtin_fmax(a, b); }
+
+template <typename Real>
 __device__ __forceinline__ Real uniform01(uint32_t x);
 template <>
 __device__ __forceinline__ float uniform01<float>(uint32_t x) { return u01f(x); }
 template <>
 __device__ __forceinline__ double uniform01<double>(uint32_t x) { return u01d(x); }
+
+// Brownian increments sqrt(h) z0, sqrt(h) z1 of one Box--Muller pair.  In
+// fp32 the step size goes into the radius, sqrt(-2 h ln u1) =
+// sqrt(lnu_scale log2 u1), which saves the two products by sqrt(h); fp64
+// scales the standard normals.
+__device__ __forceinline__ void brownian_pair(uint32_t a, uint32_t b, const StepParams<float>& P,
+                                              float& d0, float& d1)
+{
+    const float u1 = u01f(a), u2 = u01f(b);
+    const float rho = __builtin_amdgcn_sqrtf(P.lnu_scale * __builtin_amdgcn_logf(u1));
+    d0 = rho * __builtin_amdgcn_cosf(u2);
+    d1 = rho * __builtin_amdgcn_sinf(u2);
+}
+
+__device__ __forceinline__ void brownian_pair(uint32_t a, uint32_t b, const StepParams<double>& P,
+                                              double& d0, double& d1)
+{
+    double z0, z1;
+    box_muller(a, b, z0, z1);
+    d0 = P.sqh * z0;
+    d1 = P.sqh * z1;
+}
 
 // Compensated (Neumaier) accumulation for the Asian average: the sum of up
 // to 65536 terms keeps ~1e-7 relative accuracy in fp32.
@@ -121,15 +150,18 @@ __device__ __forceinline__ void fine_step(PathPair<Real>& q, const StepParams<Re
         q.mn = m < q.mn ? m : q.mn;
     }
     if (!coupled) return;
-    q.dw1c += dw1;
-    if (MODEL == kHeston) q.dwpc += dwp;
+    // k == 0 opens a coarse step: assign rather than add to the zero the
+    // previous coarse step left (same value; with k known at compile time it
+    // saves the addition)
+    q.dw1c = k == 0 ? dw1 : q.dw1c + dw1;
+    if (MODEL == kHeston) q.dwpc = k == 0 ? dwp : q.dwpc + dwp;
     if (PAYOFF == kLookback) {
         // coarse path refined at the fine times with frozen coefficients:
         // X(tau) = Sc + Sc (r tau + vol_c W(tau)), W from the coarse step start
         const Real volc = (MODEL == kGBM) ? P.sigma
                                          : fsqrt<Real>(q.vc > Real(0) ? q.vc : Real(0));
-        const Real x0 = fmaT(q.Sc, fmaT(volc, q.wpart, P.rh * Real(k)), q.Sc);
-        q.wpart += dw1;
+        const Real x0 = k == 0 ? q.Sc : fmaT(q.Sc, fmaT(volc, q.wpart, P.rh * Real(k)), q.Sc);
+        q.wpart = k == 0 ? dw1 : q.wpart + dw1;
         const Real x1 = fmaT(q.Sc, fmaT(volc, q.wpart, P.rh * Real(k + 1)), q.Sc);
         const Real m = bridge_min(x0, x1, volc * q.Sc, e);
         q.mnc = m < q.mnc ? m : q.mnc;
@@ -160,16 +192,20 @@ template <typename Real, int PAYOFF>
 __device__ __forceinline__ Real payoff_value(const StepParams<Real>& P, Real S, Real sum,
                                              Real comp, Real mn, Real dt)
 {
-    // a path that overflowed stays visible as a non-finite payoff
-    if (!isfinite(S)) return S - S;
-    if (PAYOFF == kCall) return P.disc * (S > P.K ? S - P.K : Real(0));
-    if (PAYOFF == kDigital)
-        return S > P.K ? P.disc * P.payout : (S == P.K ? P.disc * Real(0.5) * P.payout : Real(0));
-    if (PAYOFF == kAsian) {
+    Real v;
+    if (PAYOFF == kCall) {
+        v = P.disc * fmaxT<Real>(S - P.K, Real(0));
+    } else if (PAYOFF == kDigital) {
+        v = S > P.K ? P.disc * P.payout : (S == P.K ? P.disc * Real(0.5) * P.payout : Real(0));
+    } else if (PAYOFF == kAsian) {
         const Real A = (sum + comp) * (dt * Real(0.5)) * P.inv_T;
-        return P.disc * (A > P.K ? A - P.K : Real(0));
+        v = P.disc * fmaxT<Real>(A - P.K, Real(0));
+    } else {
+        v = P.disc * (S - mn);   // floating-strike lookback
     }
-    return P.disc * (S - mn);   // floating-strike lookback
+    // a path that overflowed stays visible as a non-finite payoff: S - S is
+    // +0 for finite S and NaN otherwise (two lane operations, no branch)
+    return v + (S - S);
 }
 
 }  // namespace mlmc

@@ -4,16 +4,12 @@
 
 namespace mlmc {
 
-// Add one sample's payoffs into the lane sums (and the optional dump).
+// Add one sample's payoffs into the lane sums.
 template <typename Real>
-__device__ __forceinline__ void accumulate(const LevelArgs<Real>& a, uint64_t idx, Real pf, Real pc,
-                                           double (&sums)[kNumSums], unsigned& nonfinite)
+__device__ __forceinline__ void add_sample(Real pf, Real pc, double (&sums)[kNumSums],
+                                           unsigned& nonfinite)
 {
     const double df = (double)pf, dc = (double)pc;
-    if (a.pf_out) {
-        a.pf_out[idx] = df;
-        a.pc_out[idx] = dc;
-    }
     const double y = df - dc;
     if (!isfinite(y)) {
         ++nonfinite;
@@ -25,6 +21,18 @@ __device__ __forceinline__ void accumulate(const LevelArgs<Real>& a, uint64_t id
     sums[3] = __builtin_fma(df, df, sums[3]);
     sums[4] += dc;
     sums[5] = __builtin_fma(dc, dc, sums[5]);
+}
+
+// add_sample plus the optional per-sample dump.
+template <typename Real>
+__device__ __forceinline__ void accumulate(const LevelArgs<Real>& a, uint64_t idx, Real pf, Real pc,
+                                           double (&sums)[kNumSums], unsigned& nonfinite)
+{
+    if (a.pf_out) {
+        a.pf_out[idx] = (double)pf;
+        a.pc_out[idx] = (double)pc;
+    }
+    add_sample(pf, pc, sums, nonfinite);
 }
 
 // Advance PPT coupled pairs through all n_f >= 4 fine steps of the level.
@@ -40,32 +48,26 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
         bkey[p] = make_path_key(a.seed, a.l, s[p], a.stream + 1u);
         init_pair<Real, MODEL, PAYOFF>(q[p], P);
     }
-    const bool coupled = a.coupled && a.l > 0;
-    // n_f >= 4 here (a multiple of 4): every group holds four fine steps
+    // n_f >= 4 here (a multiple of 4): every group holds four fine steps.
+    // The coarse path is advanced even when the caller drops it (standard
+    // Monte Carlo at one level): a per-step choice would cost more lane
+    // operations on the coupled levels than the coarse steps cost there.
     for (uint32_t g = 0; g < a.ngroups; ++g) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             Real dw1[4], dwp[4], e[4];
             if (MODEL == kGBM) {
                 const u32x4 w = path_block(key[p], g);
-                Real z0, z1, z2, z3;
-                box_muller(w.x, w.y, z0, z1);
-                box_muller(w.z, w.w, z2, z3);
-                dw1[0] = P.sqh * z0; dw1[1] = P.sqh * z1;
-                dw1[2] = P.sqh * z2; dw1[3] = P.sqh * z3;
+                brownian_pair(w.x, w.y, P, dw1[0], dw1[1]);
+                brownian_pair(w.z, w.w, P, dw1[2], dw1[3]);
                 dwp[0] = dwp[1] = dwp[2] = dwp[3] = Real(0);
             } else {
                 const u32x4 wa = path_block(key[p], 2 * g);
                 const u32x4 wb = path_block(key[p], 2 * g + 1);
-                Real z0, z1, z2, z3, z4, z5, z6, z7;
-                box_muller(wa.x, wa.y, z0, z1);
-                box_muller(wa.z, wa.w, z2, z3);
-                box_muller(wb.x, wb.y, z4, z5);
-                box_muller(wb.z, wb.w, z6, z7);
-                dw1[0] = P.sqh * z0; dwp[0] = P.sqh * z1;
-                dw1[1] = P.sqh * z2; dwp[1] = P.sqh * z3;
-                dw1[2] = P.sqh * z4; dwp[2] = P.sqh * z5;
-                dw1[3] = P.sqh * z6; dwp[3] = P.sqh * z7;
+                brownian_pair(wa.x, wa.y, P, dw1[0], dwp[0]);
+                brownian_pair(wa.z, wa.w, P, dw1[1], dwp[1]);
+                brownian_pair(wb.x, wb.y, P, dw1[2], dwp[2]);
+                brownian_pair(wb.z, wb.w, P, dw1[3], dwp[3]);
             }
             if (PAYOFF == kLookback) {
                 const u32x4 u = path_block(bkey[p], g);
@@ -78,8 +80,8 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                fine_step<Real, MODEL, PAYOFF>(q[p], P, dw1[k], dwp[k], e[k], k % M, coupled);
-                if (coupled && ((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(q[p], P);
+                fine_step<Real, MODEL, PAYOFF>(q[p], P, dw1[k], dwp[k], e[k], k % M, true);
+                if (((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(q[p], P);
             }
         }
     }
@@ -120,6 +122,15 @@ __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t
 // the level covers samples Q B .. Q B + Q - 1 (those outside
 // [offset, offset + N) are computed and dropped).  blk_base indexes blocks
 // from B0 = offset / Q.
+//
+// Level 0 (NF = 1, no coarse path) is the busiest launch of an adaptive run
+// and costs ~25 lane operations per sample, so its bookkeeping is per lane
+// chunk rather than per sample: the chunk's sums of y and y^2 go into the
+// lane sums at once when every sample of the chunk lies in the range and the
+// fp64 sum of squares is finite (y^2 of an fp32 value cannot overflow fp64,
+// so that sum is finite exactly when every y is); otherwise the chunk is
+// added sample by sample with the range and finiteness checks.  y = P_f
+// there, so the sums of P_f repeat those of y and the P_c sums stay zero.
 template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT>
 __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t blk_base,
                                               double (&sums)[kNumSums], unsigned& nonfinite)
@@ -131,17 +142,19 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
     const StepParams<Real>& P = a.P;
     const bool coupled = a.coupled && a.l > 0;   // NF == 2 with M == 2 only
     const uint64_t B0 = a.offset / Q;
+    uint64_t B[PPT];
+    Real pf[PPT][Q], pc[PPT][Q], dwf[PPT][Q];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        const uint64_t B = B0 + blk_base + (uint64_t)p * blockDim.x + threadIdx.x;
-        const u32x4 w = path_block(make_path_key(a.seed, a.l, B, a.stream), 0);
-        Real z[4];
-        box_muller(w.x, w.y, z[0], z[1]);
-        box_muller(w.z, w.w, z[2], z[3]);
+        B[p] = B0 + blk_base + (uint64_t)p * blockDim.x + threadIdx.x;
+        const u32x4 w = path_block(make_path_key(a.seed, a.l, B[p], a.stream), 0);
+        Real dw[4];
+        brownian_pair(w.x, w.y, P, dw[0], dw[1]);
+        brownian_pair(w.z, w.w, P, dw[2], dw[3]);
         Real e[4] = {Real(0), Real(0), Real(0), Real(0)};
         if (PAYOFF == kLookback) {
             // every sample of this generator block reads bridge block B / D
-            const u32x4 u = path_block(make_path_key(a.seed, a.l, B / D, a.stream + 1u), 0);
+            const u32x4 u = path_block(make_path_key(a.seed, a.l, B[p] / D, a.stream + 1u), 0);
             e[0] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.x));
             e[1] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.y));
             e[2] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.z));
@@ -149,26 +162,73 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
         }
 #pragma unroll
         for (int r = 0; r < Q; ++r) {
-            const uint64_t s = B * Q + r;
+            const uint64_t s = B[p] * Q + r;
             PathPair<Real> q;
             init_pair<Real, MODEL, PAYOFF>(q, P);
             const int ub = (int)(s % QU) * NF;   // first bridge word of the sample
 #pragma unroll
             for (int k = 0; k < NF; ++k) {
-                const Real dw1 = P.sqh * z[r * T + k * D];
-                const Real dwp = (D == 2) ? P.sqh * z[r * T + k * D + 1] : Real(0);
+                const Real dw1 = dw[r * T + k * D];
+                const Real dwp = (D == 2) ? dw[r * T + k * D + 1] : Real(0);
                 fine_step<Real, MODEL, PAYOFF>(q, P, dw1, dwp, e[(ub + k) & 3], k % M, coupled);
             }
             if (NF == 2 && coupled) coarse_step<Real, MODEL, PAYOFF>(q, P);
-            Real pf = payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
-            // level 0 with the control variate: every sample starts at (0, S0)
-            if (NF == 1 && a.phi0) pf -= (Real)(*a.phi0) * (P.sqh * z[r * T]);
-            const Real pc = coupled ? payoff_value<Real, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H)
-                                    : Real(0);
-            if (s < a.offset || s - a.offset >= a.N) continue;
-            accumulate(a, s - a.offset, pf, pc, sums, nonfinite);
+            pf[p][r] = payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
+            pc[p][r] = coupled ? payoff_value<Real, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H)
+                               : Real(0);
+            dwf[p][r] = dw[r * T];
         }
     }
+    // level 0 with the control variate: every sample starts at (0, S0), so
+    // the martingale term is the one value phi(0, S0) times the increment
+    if (NF == 1 && a.phi0) {
+        const Real c = (Real)*a.phi0;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p)
+#pragma unroll
+            for (int r = 0; r < Q; ++r) pf[p][r] = fmaT(-c, dwf[p][r], pf[p][r]);
+    }
+    if (a.pf_out) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p)
+#pragma unroll
+            for (int r = 0; r < Q; ++r) {
+                const uint64_t s = B[p] * Q + r;
+                if (s < a.offset || s - a.offset >= a.N) continue;
+                a.pf_out[s - a.offset] = (double)pf[p][r];
+                a.pc_out[s - a.offset] = (double)pc[p][r];
+            }
+    }
+    if (NF == 1) {
+        double cy = (double)pf[0][0];
+        double cy2 = cy * cy;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p)
+#pragma unroll
+            for (int r = 0; r < Q; ++r) {
+                if (p == 0 && r == 0) continue;
+                const double y = (double)pf[p][r];
+                cy += y;
+                cy2 = __builtin_fma(y, y, cy2);
+            }
+        const uint64_t first = B[0] * Q, last = B[PPT - 1] * Q + (Q - 1);
+        const bool inside = first >= a.offset && last - a.offset < a.N;
+        if (inside && isfinite(cy2)) {
+            sums[0] += cy;
+            sums[1] += cy2;
+            sums[2] += cy;
+            sums[3] += cy2;
+            return;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p)
+#pragma unroll
+        for (int r = 0; r < Q; ++r) {
+            const uint64_t s = B[p] * Q + r;
+            if (s < a.offset || s - a.offset >= a.N) continue;
+            add_sample(pf[p][r], pc[p][r], sums, nonfinite);
+        }
 }
 
 // Number of generator blocks a short level's range [offset, offset + N) touches.

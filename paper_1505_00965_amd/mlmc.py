@@ -64,7 +64,7 @@ class RunOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("M", C.c_int), ("L_min", C.c_int), ("L_max", C.c_int),
                 ("n_pilot", C.c_uint64), ("seed", C.c_uint64), ("precision", C.c_int),
                 ("persistent", C.c_int), ("alpha", C.c_double), ("beta", C.c_double),
-                ("cv", C.c_void_p)]
+                ("cv", C.c_void_p), ("cv_levels", C.c_int)]
 
 
 class RunResult(C.Structure):
@@ -97,6 +97,15 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one.  Loading torch first makes the library bind to that copy, so the
+    # process has one HIP runtime and torch's device pointers and stream
+    # handles are valid in the library; loaded the other way round the two
+    # runtimes coexist and torch no longer sees the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, u64, i32, d, u32 = C.c_void_p, C.c_uint64, C.c_int, C.c_double, C.c_uint32
     M_, P_ = C.POINTER(Model), C.POINTER(Payoff)
@@ -278,9 +287,10 @@ class Context:
         return list(Na)
 
     def mlmc_run(self, m, p, eps, M=4, L_min=2, L_max=8, n_pilot=10000, seed=1, precision=32,
-                 persistent=False, alpha=0.0, beta=0.0, cv=None, allow_notconv=False):
+                 persistent=False, alpha=0.0, beta=0.0, cv=None, cv_levels=0,
+                 allow_notconv=False):
         o = RunOpts(eps, M, L_min, L_max, n_pilot, seed, precision, int(persistent), alpha, beta,
-                    _cvh(cv))
+                    _cvh(cv), cv_levels)
         r = RunResult()
         allow = (MLMC_OK, MLMC_ENOTCONV) if allow_notconv else (MLMC_OK,)
         self._check(self._lib.mlmc_run(self.h, C.byref(m), C.byref(p), C.byref(o), C.byref(r)),

@@ -20,6 +20,16 @@ LOOKBACK = dict(kind=2, K=100.0, payout=1.0)
 DIGITAL = dict(kind=3, K=100.0, payout=1.0)
 PAYOFFS = {"call": CALL, "asian": ASIAN, "lookback": LOOKBACK, "digital": DIGITAL}
 
+# Sec. 6 experiment (Fig. 3): GBM with sigma = 0.25, European call and digital
+# call (payout 100, h(100) = half the payout), K = 100, T = 1; the accuracy
+# requests eps (absolute) and the refinement factor M = 2 the paper suggests
+# thinking of; n_pilot = 1000 and L_min = 2 are readings (not stated).
+FIG3_MODEL = PAPER_GBM_MODEL
+FIG3_CALL = dict(kind=0, K=100.0, payout=1.0)
+FIG3_DIGITAL = dict(kind=3, K=100.0, payout=100.0)
+FIG3_EPS = [0.1, 0.05, 0.02, 0.01, 0.005]
+FIG3_RUN = dict(M=2, L_min=2, L_max=12, n_pilot=1000)
+
 # Parity set: GBM call, M=2, levels 0..5, 20000 samples per level, seed 1, fp64.
 PARITY_SET = dict(M=2, levels=list(range(6)), N=20000, seed=1, precision=64)
 # Adaptive driver: GBM call, M=4, eps in units of S0.

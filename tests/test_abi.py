@@ -44,3 +44,19 @@ def test_oracle_and_library_share_no_source():
     for f in glob.glob(os.path.join(ROOT, "oracle", "*")):
         if f.endswith((".c", ".h", ".py")):
             assert "paper_1505_00965_amd" not in open(f).read(), f
+
+
+def test_one_hip_runtime_per_process():
+    """torch carries its own HIP runtime: the library must bind to that copy
+    (two runtimes in one process leave torch without the device)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1505_00965_amd import mlmc\n"
+            "mlmc.lib()\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "paths = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "print(len(paths))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

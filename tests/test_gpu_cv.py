@@ -122,8 +122,14 @@ def test_run_with_control_variate(gctx, orc):
     errs = [gctx.mlmc_run(gm, gp, eps, M=4, seed=s, cv=cv)["estimate"] - orc.bs_call()
             for s in range(1, 17)]
     assert np.sqrt(np.mean(np.square(errs))) < 1.35 * eps
+    # the network on level 0 only: still unbiased
+    errs = [gctx.mlmc_run(gm, gp, eps, M=4, seed=s, cv=cv, cv_levels=1)["estimate"] - orc.bs_call()
+            for s in range(1, 17)]
+    assert np.sqrt(np.mean(np.square(errs))) < 1.35 * eps
     with pytest.raises(mlmc.MLMCError):
         gctx.mlmc_run(gm, gp, eps, cv=cv, precision=64)
+    with pytest.raises(mlmc.MLMCError):
+        gctx.mlmc_run(gm, gp, eps, cv=cv, persistent=True)
     with pytest.raises(mlmc.MLMCError):     # Heston needs a 3-input network
         gctx.mlmc_level(mlmc.model(**W.HESTON_MODEL), gp, 1, 4, 100, 1, cv=cv)
     cv.close()

@@ -142,6 +142,32 @@ def test_nonfinite_samples_are_counted(gctx):
     assert e.value.status == mlmc.MLMC_ENONFINITE
 
 
+@pytest.mark.parametrize("pname", ["call", "digital"])
+def test_level0_nonfinite_and_ragged(gctx, pname):
+    # one fp32 step with sigma = 2e36 overflows where |z| > ~1.7: those
+    # samples are counted and left out of the sums, chunk by chunk
+    gm = mlmc.model(**dict(W.GBM_MODEL, sigma=2e36))
+    gp = mlmc.payoff(**W.PAYOFFS[pname])
+    for N, off in ((5000, 3), (777, 1 << 33)):
+        pf, pc, res = None, None, None
+        import torch
+        tpf = torch.empty(N, dtype=torch.float64, device="cuda")
+        tpc = torch.empty(N, dtype=torch.float64, device="cuda")
+        res = gctx.mlmc_level_paths(gm, gp, 0, 4, N, 9, tpf, tpc, path_offset=off,
+                                    allow_nonfinite=True)
+        pf = tpf.cpu().numpy()
+        bad = ~np.isfinite(pf)
+        assert 0.02 * N < bad.sum() < 0.3 * N, bad.sum()
+        assert res["n_nonfinite"] == bad.sum() and res["n"] == N
+        y = pf[~bad]
+        assert abs(res["sum_y"] - y.sum()) <= 1e-12 * max(1.0, np.abs(y).sum())
+        assert abs(res["sum_y2"] - (y * y).sum()) <= 1e-12 * (y * y).sum()
+        assert res["sum_pf"] == res["sum_y"] and res["sum_pc"] == 0
+        r = gctx.mlmc_level(gm, gp, 0, 4, N, 9, path_offset=off, allow_nonfinite=True)
+        assert r["n_nonfinite"] == res["n_nonfinite"]
+        assert abs(r["sum_y"] - res["sum_y"]) <= 1e-12 * max(1.0, np.abs(y).sum())
+
+
 def test_stdmc_matches_oracle(gctx, orc):
     gm, om = models(orc, 0)
     gp, op = pays(orc, "call")
