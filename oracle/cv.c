@@ -233,6 +233,7 @@ double orc_cv_loss_grad(const orc_model *m, const orc_payoff *p, int M, int lmax
                         uint64_t B, uint64_t seed, uint64_t step, const orc_cv *cv,
                         int nthreads, double *grad, double *var_out)
 {
+    if (m->scheme != ORC_EULER || m->antithetic) return NAN;   /* Euler paths only */
     size_t np = orc_cv_nparams(cv->in_dim, cv->hidden);
     if (grad) memset(grad, 0, sizeof(double) * np);
     double *Y = malloc(sizeof(double) * B);
@@ -251,7 +252,7 @@ double orc_cv_loss_grad(const orc_model *m, const orc_payoff *p, int M, int lmax
         for (uint64_t i = 0; i < B; ++i) var += (Y[i] - mean) * (Y[i] - mean);
         var /= (double)(B - 1);
         if (var_out) var_out[l] = var;
-        double C = orc_level_cost(l, M);
+        double C = orc_level_cost(l, M, 0);
         loss += sqrt(C * var);
         if (!grad) continue;
         double scale = (var > 0) ? sqrt(C / var) / (double)(B - 1) : 0.0;

@@ -80,7 +80,7 @@ int orc_mlmc_run(const orc_model *m, const orc_payoff *p, const orc_run_opts *o,
             out->cost += r.cost;
         }
         for (int l = 0; l <= L; ++l) {
-            C[l] = orc_level_cost(l, M);
+            C[l] = orc_level_cost(l, M, m->antithetic);
             E[l] = fabs(s1[l] / n[l]);
             V[l] = s2[l] / n[l] - (s1[l] / n[l]) * (s1[l] / n[l]);
             if (V[l] < 0) V[l] = 0;
@@ -102,7 +102,7 @@ int orc_mlmc_run(const orc_model *m, const orc_payoff *p, const orc_run_opts *o,
         if (L == o->L_max) break;
         ++L;
         V[L] = V[L - 1] / Mb;
-        C[L] = orc_level_cost(L, M);
+        C[L] = orc_level_cost(L, M, m->antithetic);
         n[L] = 0; s1[L] = 0; s2[L] = 0;
         orc_optimal_n(L, V, C, o->eps, Nopt);
         for (int l = 0; l <= L; ++l) {
@@ -121,7 +121,7 @@ int orc_mlmc_run(const orc_model *m, const orc_payoff *p, const orc_run_opts *o,
         out->sum_y2[l] = s2[l];
         out->E[l] = s1[l] / n[l];
         out->V[l] = s2[l] / n[l] - out->E[l] * out->E[l];
-        out->C[l] = orc_level_cost(l, M);
+        out->C[l] = orc_level_cost(l, M, m->antithetic);
     }
     double absE[16], Vr[16];
     for (int l = 0; l <= L; ++l) { absE[l] = fabs(out->E[l]); Vr[l] = out->V[l]; }

@@ -47,10 +47,15 @@ enum { ORC_STREAM_NORMAL = 0, ORC_STREAM_BRIDGE = 1, ORC_STREAM_TRAIN_NORMAL = 2
        ORC_STREAM_TRAIN_BRIDGE = 3, ORC_STREAM_STDMC = 4, ORC_STREAM_STDMC_BRIDGE = 5,
        ORC_STREAM_INIT = 6 };
 
+enum { ORC_EULER = 0, ORC_MILSTEIN = 1 };
+
 typedef struct {
     int kind;             /* ORC_GBM or ORC_HESTON */
     double S0, r, sigma, T;               /* GBM: dS = r S dt + sigma S dW   */
     double kappa, theta, xi, rho, v0;     /* Heston variance parameters      */
+    int scheme;           /* ORC_EULER, or ORC_MILSTEIN (GBM only)          */
+    int antithetic;       /* 1: levels l >= 1 average the fine path with its
+                             antithetic twin                                */
 } orc_model;
 
 typedef struct {
@@ -132,7 +137,7 @@ int orc_stdmc(const orc_model *m, const orc_payoff *p, int L, int M, uint64_t N,
  * l = 0..L.                                                                  */
 void orc_optimal_n(int L, const double *V, const double *C, double eps, double *N);
 /* Level cost in path steps: 1 at l = 0, M^l + M^(l-1) above. */
-double orc_level_cost(int l, int M);
+double orc_level_cost(int l, int M, int antithetic);
 
 typedef struct {
     double eps; int M, L_min, L_max; uint64_t n_pilot; uint64_t seed;

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 GBM, HESTON = 0, 1
+EULER, MILSTEIN = 0, 1
 CALL, ASIAN, LOOKBACK, DIGITAL = 0, 1, 2, 3
 STREAM_NORMAL, STREAM_BRIDGE, STREAM_TRAIN_NORMAL, STREAM_TRAIN_BRIDGE = 0, 1, 2, 3
 STREAM_STDMC, STREAM_STDMC_BRIDGE, STREAM_INIT = 4, 5, 6
@@ -22,7 +23,7 @@ class Model(C.Structure):
     _fields_ = [("kind", C.c_int), ("S0", C.c_double), ("r", C.c_double),
                 ("sigma", C.c_double), ("T", C.c_double), ("kappa", C.c_double),
                 ("theta", C.c_double), ("xi", C.c_double), ("rho", C.c_double),
-                ("v0", C.c_double)]
+                ("v0", C.c_double), ("scheme", C.c_int), ("antithetic", C.c_int)]
 
 
 class Payoff(C.Structure):
@@ -88,7 +89,7 @@ def lib():
         L.orc_stdmc.argtypes = [C.POINTER(Model), C.POINTER(Payoff), i32, i32, u64, u64, u64,
                                 i32, C.POINTER(LevelResult)]
         L.orc_optimal_n.argtypes = [i32, dp, dp, d, dp]
-        L.orc_level_cost.argtypes = [i32, i32]
+        L.orc_level_cost.argtypes = [i32, i32, i32]
         L.orc_level_cost.restype = d
         L.orc_mlmc_run.argtypes = [C.POINTER(Model), C.POINTER(Payoff), C.POINTER(RunOpts),
                                    C.POINTER(RunResult)]
@@ -128,8 +129,8 @@ def _u32p(a):
 
 
 def model(kind=GBM, S0=100.0, r=0.05, sigma=0.2, T=1.0, kappa=2.0, theta=0.04, xi=0.3,
-          rho=-0.7, v0=0.04):
-    return Model(kind, S0, r, sigma, T, kappa, theta, xi, rho, v0)
+          rho=-0.7, v0=0.04, scheme=0, antithetic=0):
+    return Model(kind, S0, r, sigma, T, kappa, theta, xi, rho, v0, scheme, antithetic)
 
 
 def payoff(kind=CALL, K=100.0, payout=1.0):
@@ -240,8 +241,8 @@ def optimal_n(V, Cl, eps):
     return N
 
 
-def level_cost(l, M):
-    return lib().orc_level_cost(l, M)
+def level_cost(l, M, antithetic=0):
+    return lib().orc_level_cost(l, M, antithetic)
 
 
 def fit_rate(y, M):

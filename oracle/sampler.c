@@ -21,6 +21,26 @@
  *          the paper has no Heston model.
  * The S update is written in increment form S + S (r dt + vol dW).
  *
+ * Milstein (GBM only; the scheme the complexity discussion of Sec. 5 and the
+ * Sec. 3 remark on higher strong order refer to): the scalar Milstein step
+ * for dX = f dt + g dW adds (1/2) g g' (dW^2 - dt) to the Euler step, which
+ * for g(S) = sigma S is (1/2) sigma^2 S (dW^2 - dt).  The coarse path uses the
+ * same step with the summed increment and step M h.
+ *
+ * Antithetic estimator (Sec. 7, "Further Developments": antithetic variables
+ * embedded in the multilevel estimator; a reading, as the paper gives no
+ * formula): on levels l >= 1 the fine path has an antithetic twin driven by
+ * the same increments in reverse order inside every coarse step
+ * (n = cM + k -> cM + M-1-k; for M = 2 the two halves swap), with the bridge
+ * uniforms and the second factor permuted alike, so the twin has the fine
+ * path's law and the coarse increments are unchanged.  The twin pair is the
+ * twin fine path with the coarse path built from the twin's increments; the
+ * coarse step values are the same up to summation order, but the lookback's
+ * refinement of each coarse step follows the twin's fine path.  The level
+ * sample averages the pair and its twin pair:
+ * Y = (P_f + P_f^a)/2 - (P_c + P_c^a)/2, reported as P_f := (P_f + P_f^a)/2
+ * and P_c := (P_c + P_c^a)/2.
+ *
  * Payoffs, all discounted by exp(-rT):
  *   call     max(S_N - K, 0)                               (Sec. 5)
  *   digital  payout 1{S_N > K}, payout/2 when S_N = K       (Sec. 6)
@@ -56,13 +76,20 @@ static double vol_of(const orc_model *m, double v)
     return sqrt(v > 0.0 ? v : 0.0);
 }
 
-/* One Euler--Maruyama step, eq. (eq:em).  dw1 drives S; dwp is the second,
- * uncorrelated factor, combined into dW2 = rho dW1 + sqrt(1-rho^2) dwp.    */
+/* One Euler--Maruyama step, eq. (eq:em), or for GBM with the Milstein
+ * scheme the Euler step plus (1/2) g g' (dW^2 - dt).  dw1 drives S; dwp is
+ * the second, uncorrelated factor, combined into
+ * dW2 = rho dW1 + sqrt(1-rho^2) dwp.                                       */
 static void em_step(const orc_model *m, double *S, double *v, double dt,
                     double dw1, double dwp)
 {
     if (m->kind == ORC_GBM) {
-        *S = *S + *S * (m->r * dt + m->sigma * dw1);
+        double S0 = *S;
+        *S = S0 + S0 * (m->r * dt + m->sigma * dw1);
+        if (m->scheme == ORC_MILSTEIN) {
+            double g = m->sigma * S0, dg = m->sigma;
+            *S += 0.5 * g * dg * (dw1 * dw1 - dt);
+        }
         return;
     }
     double vp = *v > 0.0 ? *v : 0.0;
@@ -153,6 +180,8 @@ static double coarse_path(const orc_model *m, const orc_payoff *p, int M, int nc
                 w_part += dw1[c * M + k];
                 double tau = (k + 1) * h;
                 double x_next = S_start + S_start * (m->r * tau + vol * w_part);
+                if (m->scheme == ORC_MILSTEIN)   /* the coarse Milstein step to tau */
+                    x_next += 0.5 * vol * vol * S_start * (w_part * w_part - tau);
                 double mk = bridge_min(x_prev, x_next, vol * S_start, h, u[c * M + k]);
                 if (mk < mn) mn = mk;
                 x_prev = x_next;
@@ -169,6 +198,9 @@ static int check_args(const orc_model *m, const orc_payoff *p, int l, int M)
 {
     if (!m || !p) return -1;
     if (m->kind != ORC_GBM && m->kind != ORC_HESTON) return -1;
+    if (m->scheme != ORC_EULER && m->scheme != ORC_MILSTEIN) return -1;
+    if (m->scheme == ORC_MILSTEIN && m->kind != ORC_GBM) return -1;
+    if (m->antithetic != 0 && m->antithetic != 1) return -1;
     if (p->kind < ORC_CALL || p->kind > ORC_DIGITAL) return -1;
     if (l < 0 || l > 20 || M < 2 || M > 16) return -1;
     double nf = pow((double)M, (double)l);
@@ -178,6 +210,7 @@ static int check_args(const orc_model *m, const orc_payoff *p, int l, int M)
 
 typedef struct {
     double *dw1, *dwp, *u, *z;
+    double *dw1a, *dwpa, *ua;     /* antithetic twin's increments, uniforms */
     int cap;
 } workspace;
 
@@ -188,11 +221,15 @@ static void ws_init(workspace *w, int nf)
     w->dwp = malloc(sizeof(double) * nf);
     w->u = malloc(sizeof(double) * nf);
     w->z = malloc(sizeof(double) * 2 * nf);
+    w->dw1a = malloc(sizeof(double) * nf);
+    w->dwpa = malloc(sizeof(double) * nf);
+    w->ua = malloc(sizeof(double) * nf);
 }
 
 static void ws_free(workspace *w)
 {
     free(w->dw1); free(w->dwp); free(w->u); free(w->z);
+    free(w->dw1a); free(w->dwpa); free(w->ua);
 }
 
 /* One coupled sample using a caller workspace. */
@@ -219,6 +256,22 @@ static void sample_ws(const orc_model *m, const orc_payoff *p, int l, int M,
     if (l > 0)
         Pc = coarse_path(m, p, M, nf / M, h, w->dw1, dim == 2 ? w->dwp : NULL, w->u, cv, &cc,
                          gw, grad);
+    if (m->antithetic && l > 0) {
+        /* the twin: increments reversed inside each coarse step */
+        for (int c = 0; c < nf / M; ++c)
+            for (int k = 0; k < M; ++k) {
+                int from = c * M + (M - 1 - k);
+                w->dw1a[c * M + k] = w->dw1[from];
+                w->dwpa[c * M + k] = w->dwp[from];
+                w->ua[c * M + k] = w->u[from];
+            }
+        double Pa = fine_path(m, p, nf, h, w->dw1a, dim == 2 ? w->dwpa : NULL, w->ua, NULL, NULL,
+                              0.0, NULL);
+        double Pca = coarse_path(m, p, M, nf / M, h, w->dw1a, dim == 2 ? w->dwpa : NULL, w->ua,
+                                 NULL, NULL, 0.0, NULL);
+        Pf = 0.5 * (Pf + Pa);
+        Pc = 0.5 * (Pc + Pca);
+    }
     *pf = Pf - cf;
     *pc = (l > 0) ? Pc - cc : 0.0;
     if (cvf) *cvf = cf;
@@ -230,6 +283,7 @@ int orc_level_sample(const orc_model *m, const orc_payoff *p, int l, int M,
                      double *pf, double *pc, double *cvf, double *cvc)
 {
     if (check_args(m, p, l, M)) return -1;
+    if (cv && (m->antithetic || m->scheme != ORC_EULER)) return -1;
     int nf = 1;
     for (int i = 0; i < l; ++i) nf *= M;
     workspace w;
@@ -364,11 +418,12 @@ int orc_level(const orc_model *m, const orc_payoff *p, int l, int M, uint64_t N,
               orc_level_result *out)
 {
     if (check_args(m, p, l, M) || !out) return -1;
+    if (cv && (m->antithetic || m->scheme != ORC_EULER)) return -1;
     job proto = {0};
     proto.m = m; proto.p = p; proto.cv = cv; proto.l = l; proto.M = M;
     proto.stream = ORC_STREAM_NORMAL; proto.mode = 0; proto.seed = seed;
     run_jobs(&proto, N, offset, nthreads, out);
-    out->cost = (double)N * orc_level_cost(l, M);
+    out->cost = (double)N * orc_level_cost(l, M, m->antithetic);
     return 0;
 }
 
@@ -377,6 +432,7 @@ int orc_level_paths(const orc_model *m, const orc_payoff *p, int l, int M,
                     int nthreads, double *pf, double *pc)
 {
     if (check_args(m, p, l, M) || !pf || !pc) return -1;
+    if (cv && (m->antithetic || m->scheme != ORC_EULER)) return -1;
     job proto = {0};
     proto.m = m; proto.p = p; proto.cv = cv; proto.l = l; proto.M = M;
     proto.stream = ORC_STREAM_NORMAL; proto.mode = 1; proto.seed = seed;
@@ -389,6 +445,7 @@ int orc_stdmc(const orc_model *m, const orc_payoff *p, int L, int M, uint64_t N,
               uint64_t seed, uint64_t offset, int nthreads, orc_level_result *out)
 {
     if (check_args(m, p, L, M) || !out) return -1;
+    if (m->antithetic) return -1;    /* the twin belongs to level differences */
     job proto = {0};
     proto.m = m; proto.p = p; proto.l = L; proto.M = M;
     proto.mode = 2; proto.seed = seed;
@@ -399,8 +456,10 @@ int orc_stdmc(const orc_model *m, const orc_payoff *p, int L, int M, uint64_t N,
     return 0;
 }
 
-double orc_level_cost(int l, int M)
+/* Path steps per sample: n_f + n_c, with the antithetic twin 2 n_f + n_c. */
+double orc_level_cost(int l, int M, int antithetic)
 {
     if (l == 0) return 1.0;
-    return pow((double)M, (double)l) + pow((double)M, (double)(l - 1));
+    double nf = pow((double)M, (double)l);
+    return (antithetic ? 2.0 : 1.0) * nf + pow((double)M, (double)(l - 1));
 }
