@@ -49,6 +49,7 @@ typedef enum {
 
 /* Models (eq. (eq:sde)); GBM is the model of Sec. 6. */
 typedef enum { MLMC_GBM = 0, MLMC_HESTON = 1 } mlmc_model_kind;
+typedef enum { MLMC_EULER = 0, MLMC_MILSTEIN = 1 } mlmc_scheme;
 /* Payoffs: European call (Sec. 5), arithmetic Asian and floating-strike
  * lookback (named in Sec. 7.1), digital with the tie rule of Sec. 6. */
 typedef enum { MLMC_CALL = 0, MLMC_ASIAN = 1, MLMC_LOOKBACK = 2, MLMC_DIGITAL = 3 } mlmc_payoff_kind;
@@ -60,6 +61,21 @@ typedef struct {
     /* Heston: dS = r S dt + sqrt(v) S dW1, dv = kappa (theta - v) dt +
      * xi sqrt(v) dW2, corr(dW1, dW2) = rho, v(0) = v0; stepped by
      * full-truncation Euler (sigma unused).                               */
+    int scheme;      /* mlmc_scheme.  MLMC_EULER: Euler--Maruyama, eq. (eq:em).
+                        MLMC_MILSTEIN (GBM only): the Euler step plus
+                        sigma^2 S (dW^2 - dt) / 2 -- the higher strong order
+                        scheme of Sec. 3 and the remark after the complexity
+                        theorem of Sec. 5 (beta = 2 > gamma = 1).            */
+    int antithetic;  /* 1: on levels l >= 1 the fine path has an antithetic
+                        twin driven by the same increments in reverse order
+                        inside every coarse step (Sec. 7, antithetic
+                        variables in the multilevel estimator), and
+                        Y = (P_f + P_f^a)/2 - (P_c + P_c^a)/2, where the twin
+                        coarse path differs from the coarse path only in the
+                        lookback's refined minimum.  Cost per sample
+                        2 n_f + n_c.  Not with the standard Monte Carlo
+                        comparator, the control variate or the persistent
+                        kernel (MLMC_EINVAL).                                 */
 } mlmc_model;
 
 typedef struct {

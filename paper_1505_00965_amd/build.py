@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlmc.so")
-SOURCES = ["capi.cpp", "level.hip", "driver.hip", "persistent.hip", "cv.hip", "autotune.cpp"]
+SOURCES = ["capi.cpp", "level.hip", "level_gbm.hip", "level_gbm_mil.hip", "level_heston.hip",
+           "driver.hip", "persistent.hip", "cv.hip", "autotune.cpp"]
 ARCH = "gfx950"
 
 

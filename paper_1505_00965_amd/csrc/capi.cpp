@@ -49,7 +49,21 @@ mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payo
     if (m->kind == MLMC_HESTON &&
         (!(m->rho >= -1 && m->rho <= 1) || !(m->xi >= 0) || !(m->theta >= 0) || !(m->v0 >= 0)))
         return fail(ctx, MLMC_EINVAL, "Heston needs |rho| <= 1 and xi, theta, v0 >= 0");
+    if (m->scheme != MLMC_EULER && m->scheme != MLMC_MILSTEIN)
+        return fail(ctx, MLMC_EINVAL, "unknown scheme");
+    if (m->scheme == MLMC_MILSTEIN && m->kind != MLMC_GBM)
+        return fail(ctx, MLMC_EINVAL, "the Milstein scheme is implemented for GBM only");
+    if (m->antithetic != 0 && m->antithetic != 1)
+        return fail(ctx, MLMC_EINVAL, "antithetic must be 0 or 1");
     return MLMC_OK;
+}
+
+// Path steps per sample of level l: n_f + n_c (2 n_f + n_c with the twin).
+static double level_cost(const mlmc_model& m, int l, int M)
+{
+    if (l == 0) return 1.0;
+    const double nf = std::pow((double)M, (double)l);
+    return (m.antithetic ? 2.0 : 1.0) * nf + nf / M;
 }
 
 LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
@@ -75,6 +89,7 @@ LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_pa
         units = (N + q - 1) / q + 1;
         if (s.ppt > 2) s.ppt = 2;
     }
+    if (m.antithetic && l > 0 && s.ppt > 2) s.ppt = 2;   // the twin doubles the path state
     const uint64_t chunk = (uint64_t)s.block * s.ppt;
     const uint64_t chunks = (units + chunk - 1) / chunk;
     const uint64_t cap = (uint64_t)ctx->num_cu * (2048 / s.block);
@@ -196,6 +211,8 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
     if (N == 0) return MLMC_OK;
     if (cv) {
         if (precision != 32) return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
+        if (m.scheme != MLMC_EULER || m.antithetic)
+            return fail(ctx, MLMC_EINVAL, "the control variate runs with plain Euler paths");
         if (cv_in_dim(cv) != (m.kind == MLMC_HESTON ? 3 : 2))
             return fail(ctx, MLMC_EINVAL, "network inputs do not match the model (2: GBM, 3: Heston)");
         const double nf = (double)level_steps(l, M);
@@ -222,9 +239,10 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
     }
     const LaunchShape shape = choose_shape(ctx, m, p, l, M, precision, N);
     const double nf = (double)level_steps(l, M);
+    const double twins = (m.antithetic && l > 0) ? 2.0 : 1.0;   // fine paths per sample
     hipEvent_t t0, t1;
-    timed_kernel(ctx, l < 16 ? l : 15, (double)N * nf, (coupled && l > 0) ? (double)N * nf / M : 0.0,
-                 &t0, &t1);
+    timed_kernel(ctx, l < 16 ? l : 15, (double)N * nf * twins,
+                 (coupled && l > 0) ? (double)N * nf / M : 0.0, &t0, &t1);
     hipError_t e;
     if (precision == 64) {
         auto a = make_args<double>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
@@ -237,8 +255,8 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
     return MLMC_OK;
 }
 
-static mlmc_status finish_level(mlmc_ctx* ctx, uint64_t N, int l, int M, int coupled,
-                                mlmc_level_result* out)
+static mlmc_status finish_level(mlmc_ctx* ctx, const mlmc_model& m, uint64_t N, int l, int M,
+                                int coupled, mlmc_level_result* out)
 {
     MLMC_HIP(ctx, hipMemcpyAsync(ctx->h_acc, ctx->d_acc, sizeof(LevelAcc), hipMemcpyDeviceToHost,
                                  ctx->stream));
@@ -252,8 +270,7 @@ static mlmc_status finish_level(mlmc_ctx* ctx, uint64_t N, int l, int M, int cou
         out->sum_pf2 = r.sum[3];
         out->sum_pc = r.sum[4];
         out->sum_pc2 = r.sum[5];
-        const double nf = std::pow((double)M, (double)l);
-        out->cost = (double)N * ((coupled && l > 0) ? nf + nf / M : nf);
+        out->cost = (double)N * (coupled ? level_cost(m, l, M) : std::pow((double)M, (double)l));
         out->n = N;
         out->n_nonfinite = r.n_nonfinite;
     }
@@ -377,6 +394,8 @@ static mlmc_status level_common(mlmc_ctx* ctx, const mlmc_model* model, const ml
     if (st) return st;
     if (cv && precision != 32)
         return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
+    if (!coupled && model->antithetic)
+        return fail(ctx, MLMC_EINVAL, "the antithetic twin belongs to level differences");
     if (N > (1ull << 40)) return fail(ctx, MLMC_EINVAL, "N too large (max 2^40 per call)");
     if ((path_offset + N) >> 56) return fail(ctx, MLMC_EINVAL, "path index beyond 2^56");
     ctx->err.clear();
@@ -385,7 +404,7 @@ static mlmc_status level_common(mlmc_ctx* ctx, const mlmc_model* model, const ml
     st = enqueue_level(ctx, *model, *payoff, l, M, N, seed, path_offset, precision, stream, coupled,
                        ctx->d_acc, d_pf, d_pc, cv);
     if (st) return st;
-    return finish_level(ctx, N, l, M, coupled, out);
+    return finish_level(ctx, *model, N, l, M, coupled, out);
 }
 
 mlmc_status mlmc_level(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff, int l,

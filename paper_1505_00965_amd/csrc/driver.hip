@@ -23,12 +23,12 @@
 
 namespace mlmc {
 
-__device__ double level_cost_dev(int l, int M)
+__device__ double level_cost_dev(int l, int M, int antithetic)
 {
     if (l == 0) return 1.0;
     double a = 1.0;
     for (int i = 0; i < l - 1; ++i) a *= M;
-    return a * M + a;
+    return (antithetic ? 2.0 : 1.0) * a * M + a;
 }
 
 __device__ void optimal_n_dev(int L, const double* V, const double* C, double eps, double* N)
@@ -75,7 +75,7 @@ __device__ void driver_update_dev(DriverState* st)
     }
     st->iterations += 1;
     for (int l = 0; l <= L; ++l) {
-        st->C[l] = level_cost_dev(l, M);
+        st->C[l] = level_cost_dev(l, M, st->antithetic);
         const double m = st->sum1[l] / st->n[l];
         st->E[l] = fabs(m);
         st->V[l] = st->sum2[l] / st->n[l] - m * m;
@@ -104,7 +104,7 @@ __device__ void driver_update_dev(DriverState* st)
             ++L;
             st->V[L] = st->V[L - 1] / Mb;
             st->E[L] = st->E[L - 1] / Ma;
-            st->C[L] = level_cost_dev(L, M);
+            st->C[L] = level_cost_dev(L, M, st->antithetic);
             st->n[L] = 0;
             st->sum1[L] = 0;
             st->sum2[L] = 0;
@@ -275,6 +275,8 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
         return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
     if (o.cv && o.persistent)
         return fail(ctx, MLMC_EINVAL, "the control variate runs with per-level launches only");
+    if (model->antithetic && o.persistent)
+        return fail(ctx, MLMC_EINVAL, "the antithetic estimator runs with per-level launches only");
     ctx->err.clear();
     const auto t0 = std::chrono::steady_clock::now();
     MLMC_HIP(ctx, hipSetDevice(ctx->device));
@@ -287,6 +289,7 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     h->alpha = o.alpha > 0 ? o.alpha : 1.0;
     h->beta = o.beta > 0 ? o.beta : 1.0;
     h->M = o.M;
+    h->antithetic = model->antithetic;
     h->L_min = o.L_min;
     h->L_max = o.L_max;
     h->max_iterations = 1000;

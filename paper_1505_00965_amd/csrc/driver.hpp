@@ -18,6 +18,7 @@ struct DriverState {
     // configuration
     double eps, alpha, beta;
     int M, L_min, L_max, max_iterations;
+    int antithetic, pad_cfg;       // the twin doubles the fine steps of l >= 1
     // progress
     int L, done, converged, iterations;
     double n[kMaxLevels];          // samples absorbed so far

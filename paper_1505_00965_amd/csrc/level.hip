@@ -1,19 +1,10 @@
-// Coupled level-sampler kernels (one (model, payoff, precision, M, PPT)
-// instantiation each) and their launcher.
-//
-// One lane owns PPT samples of level l at a time (indices i0 + p * blockDim,
-// so dumps are coalesced), advances each coupled fine/coarse pair through
-// n_f = M^l fine steps in registers, forms Y = P_l - P_{l-1}
-// (eq. (eq:Yldef)) and adds Y, Y^2, P_l, P_l^2, P_{l-1}, P_{l-1}^2 into fp64
-// lane sums; blocks walk the sample range with a grid stride, then reduce
-// once (reduce.hpp).  The loop trip count is the same for every lane of a
-// launch, so waves never diverge in the path loop.
+// Level-sampler launcher: parameter block, dispatch to the per-variant
+// kernel tables, and the generator probes.
 #include <cmath>
 
 #include <hip/hip_ext.h>
 
-#include "level.hpp"
-#include "sampler_impl.hpp"
+#include "level_kernels.hpp"
 
 namespace mlmc {
 
@@ -38,6 +29,9 @@ StepParams<Real> make_step_params(const mlmc_model& m, const mlmc_payoff& p, int
     P.H = (Real)H;
     P.rh = (Real)(m.r * h);
     P.rH = (Real)(m.r * H);
+    P.c2 = (Real)(0.5 * m.sigma * m.sigma);
+    P.rh_m = (Real)((m.r - 0.5 * m.sigma * m.sigma) * h);
+    P.rH_m = (Real)((m.r - 0.5 * m.sigma * m.sigma) * H);
     P.K = (Real)p.K;
     P.payout = (Real)p.payout;
     P.disc = (Real)std::exp(-m.r * m.T);
@@ -49,82 +43,30 @@ StepParams<Real> make_step_params(const mlmc_model& m, const mlmc_payoff& p, int
 template StepParams<float> make_step_params<float>(const mlmc_model&, const mlmc_payoff&, int, int);
 template StepParams<double> make_step_params<double>(const mlmc_model&, const mlmc_payoff&, int, int);
 
-template <int MODEL, int PAYOFF, typename Real, int M, int PPT>
-__global__ __launch_bounds__(1024) void level_kernel(LevelArgs<Real> a)
-{
-    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
-    unsigned nonfinite = 0;
-    const uint64_t chunk = (uint64_t)blockDim.x * PPT;
-    const uint64_t nchunks = (a.N + chunk - 1) / chunk;
-    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x)
-        process_chunk<MODEL, PAYOFF, Real, M, PPT>(a, c * chunk, sums, nonfinite);
-    block_reduce_add(sums, nonfinite, a.acc);
-}
-
-// Levels with one or two fine steps: samples share generator blocks.
-template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT>
-__global__ __launch_bounds__(1024) void short_level_kernel(LevelArgs<Real> a)
-{
-    constexpr int Q = 4 / (NF * (MODEL == kGBM ? 1 : 2));
-    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
-    unsigned nonfinite = 0;
-    const uint64_t nblk = short_blocks(a.offset, a.N, Q);
-    const uint64_t chunk = (uint64_t)blockDim.x * PPT;
-    const uint64_t nchunks = (nblk + chunk - 1) / chunk;
-    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x)
-        process_short<MODEL, PAYOFF, Real, NF, M, PPT>(a, c * chunk, sums, nonfinite);
-    block_reduce_add(sums, nonfinite, a.acc);
-}
-
 // ------------------------------------------------------------ dispatch
-template <typename Real>
-using KernelFn = void (*)(LevelArgs<Real>);
+// Instantiated in the per-variant translation units.
+extern template KernelFn<float> pick_variant<kGBM, float>(int, int, int, int, bool);
+extern template KernelFn<double> pick_variant<kGBM, double>(int, int, int, int, bool);
+extern template KernelFn<float> pick_variant<kGBMMil, float>(int, int, int, int, bool);
+extern template KernelFn<double> pick_variant<kGBMMil, double>(int, int, int, int, bool);
+extern template KernelFn<float> pick_variant<kHeston, float>(int, int, int, int, bool);
+extern template KernelFn<double> pick_variant<kHeston, double>(int, int, int, int, bool);
 
-// nf: 1 or 2 selects the short-level kernel, anything else the general one.
-template <int MODEL, int PAYOFF, typename Real, int M>
-static KernelFn<Real> pick_ppt(int ppt, int nf)
+int sampler_variant(const mlmc_model& m)
 {
-    if constexpr (sizeof(Real) == 8) {
-        (void)ppt;   // fp64 paths: one per lane (register budget)
-        if (nf == 1) return short_level_kernel<MODEL, PAYOFF, Real, 1, M, 1>;
-        if (nf == 2) return short_level_kernel<MODEL, PAYOFF, Real, 2, M, 1>;
-        return level_kernel<MODEL, PAYOFF, Real, M, 1>;
-    } else {
-        if (nf == 1) return ppt == 1 ? short_level_kernel<MODEL, PAYOFF, Real, 1, M, 1>
-                                     : short_level_kernel<MODEL, PAYOFF, Real, 1, M, 2>;
-        if (nf == 2) return ppt == 1 ? short_level_kernel<MODEL, PAYOFF, Real, 2, M, 1>
-                                     : short_level_kernel<MODEL, PAYOFF, Real, 2, M, 2>;
-        switch (ppt) {
-        case 1: return level_kernel<MODEL, PAYOFF, Real, M, 1>;
-        case 2: return level_kernel<MODEL, PAYOFF, Real, M, 2>;
-        default: return level_kernel<MODEL, PAYOFF, Real, M, 4>;
-        }
-    }
-}
-
-template <int MODEL, int PAYOFF, typename Real>
-static KernelFn<Real> pick_m(int M, int ppt, int nf)
-{
-    return M == 2 ? pick_ppt<MODEL, PAYOFF, Real, 2>(ppt, nf)
-                  : pick_ppt<MODEL, PAYOFF, Real, 4>(ppt, nf);
-}
-
-template <int MODEL, typename Real>
-static KernelFn<Real> pick_payoff(int payoff, int M, int ppt, int nf)
-{
-    switch (payoff) {
-    case kCall: return pick_m<MODEL, kCall, Real>(M, ppt, nf);
-    case kAsian: return pick_m<MODEL, kAsian, Real>(M, ppt, nf);
-    case kLookback: return pick_m<MODEL, kLookback, Real>(M, ppt, nf);
-    default: return pick_m<MODEL, kDigital, Real>(M, ppt, nf);
-    }
+    if (m.kind == MLMC_HESTON) return kHeston;
+    return m.scheme == MLMC_MILSTEIN ? kGBMMil : kGBM;
 }
 
 template <typename Real>
-static KernelFn<Real> pick(int model, int payoff, int M, int ppt, int nf)
+static KernelFn<Real> pick(const mlmc_model& m, int payoff, int M, int ppt, int nf)
 {
-    return model == kGBM ? pick_payoff<kGBM, Real>(payoff, M, ppt, nf)
-                         : pick_payoff<kHeston, Real>(payoff, M, ppt, nf);
+    const bool anti = m.antithetic != 0 && nf > 1;
+    switch (sampler_variant(m)) {
+    case kGBMMil: return pick_variant<kGBMMil, Real>(payoff, M, ppt, nf, anti);
+    case kHeston: return pick_variant<kHeston, Real>(payoff, M, ppt, nf, anti);
+    default: return pick_variant<kGBM, Real>(payoff, M, ppt, nf, anti);
+    }
 }
 
 hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int precision,
@@ -134,11 +76,11 @@ hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int pr
     dim3 grid(shape.grid), block(shape.block);
     if (precision == 64) {
         const auto& a = *(const LevelArgs<double>*)args;
-        auto fn = pick<double>(m.kind, p.kind, M, 1, a.nf);
+        auto fn = pick<double>(m, p.kind, M, 1, a.nf);
         hipExtLaunchKernelGGL(fn, grid, block, 0, stream, start, stop, 0, a);
     } else {
         const auto& a = *(const LevelArgs<float>*)args;
-        auto fn = pick<float>(m.kind, p.kind, M, shape.ppt, a.nf);
+        auto fn = pick<float>(m, p.kind, M, shape.ppt, a.nf);
         hipExtLaunchKernelGGL(fn, grid, block, 0, stream, start, stop, 0, a);
     }
     return hipGetLastError();

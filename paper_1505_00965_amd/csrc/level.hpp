@@ -31,6 +31,10 @@ struct LevelArgs {
 template <typename Real>
 StepParams<Real> make_step_params(const mlmc_model& m, const mlmc_payoff& p, int l, int M);
 
+// Kernel variant of a model: kGBM, kGBMMil (GBM with the Milstein scheme)
+// or kHeston.
+int sampler_variant(const mlmc_model& m);
+
 // Launch shape actually used.
 struct LaunchShape {
     int block, ppt, grid;

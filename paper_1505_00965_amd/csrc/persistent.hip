@@ -144,21 +144,21 @@ __device__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[k
     a.phi0 = nullptr;
     if (nf < 4) {
         // one or two steps: samples share generator blocks
-        constexpr int D = (MODEL == kGBM) ? 1 : 2;
+        constexpr int D = one_factor(MODEL) ? 1 : 2;
         const int q = 4 / (nf * D);
         const uint64_t nblk = short_blocks(w.first, w.n, q);
         const uint64_t chunk = (uint64_t)blockDim.x * PPT;
         for (uint64_t base = 0; base < nblk; base += chunk) {
-            if (nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT>(a, base, sums, nonfinite);
-            else process_short<MODEL, PAYOFF, float, 2, M, PPT>(a, base, sums, nonfinite);
+            if (nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT, false>(a, base, sums, nonfinite);
+            else process_short<MODEL, PAYOFF, float, 2, M, PPT, false>(a, base, sums, nonfinite);
         }
     } else if (w.n <= blockDim.x) {
         // fewer samples than lanes: one per lane
-        process_chunk<MODEL, PAYOFF, float, M, 1>(a, 0, sums, nonfinite);
+        process_chunk<MODEL, PAYOFF, float, M, 1, false>(a, 0, sums, nonfinite);
     } else {
         const uint64_t chunk = (uint64_t)blockDim.x * PPT;
         for (uint64_t base = 0; base < w.n; base += chunk)
-            process_chunk<MODEL, PAYOFF, float, M, PPT>(a, base, sums, nonfinite);
+            process_chunk<MODEL, PAYOFF, float, M, PPT, false>(a, base, sums, nonfinite);
     }
 }
 
@@ -198,9 +198,11 @@ static PersistentFn pick_ppt(int ppt)
     }
 }
 
-static PersistentFn pick_persistent(int model, int M, int ppt)
+// variant: sampler_variant() of the model (GBM Euler, GBM Milstein, Heston)
+static PersistentFn pick_persistent(int variant, int M, int ppt)
 {
-    if (model == kGBM) return M == 2 ? pick_ppt<kGBM, 2>(ppt) : pick_ppt<kGBM, 4>(ppt);
+    if (variant == kGBM) return M == 2 ? pick_ppt<kGBM, 2>(ppt) : pick_ppt<kGBM, 4>(ppt);
+    if (variant == kGBMMil) return M == 2 ? pick_ppt<kGBMMil, 2>(ppt) : pick_ppt<kGBMMil, 4>(ppt);
     return M == 2 ? pick_ppt<kHeston, 2>(ppt) : pick_ppt<kHeston, 4>(ppt);
 }
 
@@ -345,11 +347,11 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     // the graph reads the descriptor, the driver state and its mirror at
     // replay, all fixed per context: one capture serves every run
     const PersistentShape s = persistent_shape(ctx);
-    const int key[5] = {m.kind, o.M, s.block, s.ppt, s.blocks_per_cu};
+    const int key[5] = {sampler_variant(m), o.M, s.block, s.ppt, s.blocks_per_cu};
     if (!b->run_graph || std::memcmp(key, b->run_key, sizeof(key)) != 0) {
         if (b->run_graph) hipGraphExecDestroy(b->run_graph);
         b->run_graph = nullptr;
-        st = capture(ctx, m.kind, o.M, false, d_st, &b->run_graph);
+        st = capture(ctx, sampler_variant(m), o.M, false, d_st, &b->run_graph);
         if (st) return st;
         std::memcpy(b->run_key, key, sizeof(key));
     }
@@ -419,6 +421,8 @@ mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc
     mlmc_status st = MLMC_OK;
     for (int k = 0; k < npayoffs && !st; ++k) st = check_level_args(ctx, model, &payoffs[k], L, M, 32);
     if (st) return st;
+    if (model->antithetic)
+        return fail(ctx, MLMC_EINVAL, "the antithetic estimator runs with per-level launches only");
     if (L >= kMaxLevels) return fail(ctx, MLMC_EINVAL, "L must be < 16");
     for (int i = 0; i < npayoffs * (L + 1); ++i) {
         if (N[i] > (1ull << 40)) return fail(ctx, MLMC_EINVAL, "N too large (max 2^40 per level)");
@@ -445,11 +449,11 @@ mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
                                  ctx->stream));
     const PersistentShape s = persistent_shape(ctx);
-    const int key[5] = {model->kind, M, s.block, s.ppt, s.blocks_per_cu};
+    const int key[5] = {sampler_variant(*model), M, s.block, s.ppt, s.blocks_per_cu};
     if (!b->graph || std::memcmp(key, b->graph_key, sizeof(key)) != 0) {
         if (b->graph) hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
-        st = capture(ctx, model->kind, M, true, nullptr, &b->graph);
+        st = capture(ctx, sampler_variant(*model), M, true, nullptr, &b->graph);
         if (st) return st;
         std::memcpy(b->graph_key, key, sizeof(key));
     }

@@ -18,7 +18,12 @@
 
 namespace mlmc {
 
-enum ModelKind : int { kGBM = 0, kHeston = 1 };
+// Sampler variants: the SDE and its time stepping.  GBM steps by
+// Euler--Maruyama (kGBM) or by the Milstein scheme (kGBMMil); Heston by
+// full-truncation Euler.
+enum ModelKind : int { kGBM = 0, kHeston = 1, kGBMMil = 2 };
+// One Brownian factor and a constant volatility sigma (both GBM variants).
+__host__ __device__ constexpr bool one_factor(int model) { return model != kHeston; }
 enum PayoffKind : int { kCall = 0, kAsian = 1, kLookback = 2, kDigital = 3 };
 
 // Model and payoff parameters converted once on the host.
@@ -26,6 +31,7 @@ template <typename Real>
 struct StepParams {
     Real S0, r, sigma, kappa, theta, xi, rho, rho_c, v0;
     Real h, sqh, H, rh, rH;          // fine/coarse step sizes and r*dt
+    Real c2, rh_m, rH_m;             // Milstein: sigma^2/2, (r - sigma^2/2) dt
     Real K, payout, disc, inv_T;     // payoff
     Real lnu_scale;                  // -2 h ln(2): bridge term e = lnu_scale * log2(U)
     Real asian_scale;                // h / (2T)
@@ -126,6 +132,17 @@ __device__ __forceinline__ void init_pair(PathPair<Real>& q, const StepParams<Re
     q.wpart = 0; q.cvf = 0; q.cvc = 0;
 }
 
+// Relative move of the frozen-coefficient coarse step after j fine times
+// with Brownian increment w: r tau + vol w (+ sigma^2/2 (w^2 - tau) for
+// Milstein), tau = j h; at j = M it is the coarse step itself.
+template <typename Real, int MODEL>
+__device__ __forceinline__ Real refine(const StepParams<Real>& P, Real vol, Real w, int j)
+{
+    const Real lin = fmaT(vol, w, P.rh * Real(j));
+    if (MODEL == kGBMMil) return fmaT(P.c2, fmaT(w, w, -P.h * Real(j)), lin);
+    return lin;
+}
+
 // One fine step with increments (dw1, dwp), bridge exponent e (lookback only)
 // and position k = n mod M inside the current coarse step.
 template <typename Real, int MODEL, int PAYOFF>
@@ -137,6 +154,10 @@ __device__ __forceinline__ void fine_step(PathPair<Real>& q, const StepParams<Re
     if (MODEL == kGBM) {
         vol = P.sigma;
         q.S = fmaT(q.S, fmaT(P.sigma, dw1, P.rh), q.S);
+    } else if (MODEL == kGBMMil) {
+        // S + S (r h + sigma dW + sigma^2/2 (dW^2 - h))
+        vol = P.sigma;
+        q.S = fmaT(q.S, fmaT(P.c2, dw1 * dw1, fmaT(P.sigma, dw1, P.rh_m)), q.S);
     } else {
         const Real vp = q.v > Real(0) ? q.v : Real(0);
         vol = fsqrt<Real>(vp);
@@ -158,11 +179,11 @@ __device__ __forceinline__ void fine_step(PathPair<Real>& q, const StepParams<Re
     if (PAYOFF == kLookback) {
         // coarse path refined at the fine times with frozen coefficients:
         // X(tau) = Sc + Sc (r tau + vol_c W(tau)), W from the coarse step start
-        const Real volc = (MODEL == kGBM) ? P.sigma
-                                         : fsqrt<Real>(q.vc > Real(0) ? q.vc : Real(0));
-        const Real x0 = k == 0 ? q.Sc : fmaT(q.Sc, fmaT(volc, q.wpart, P.rh * Real(k)), q.Sc);
+        const Real volc = one_factor(MODEL) ? P.sigma
+                                            : fsqrt<Real>(q.vc > Real(0) ? q.vc : Real(0));
+        const Real x0 = k == 0 ? q.Sc : fmaT(q.Sc, refine<Real, MODEL>(P, volc, q.wpart, k), q.Sc);
         q.wpart = k == 0 ? dw1 : q.wpart + dw1;
-        const Real x1 = fmaT(q.Sc, fmaT(volc, q.wpart, P.rh * Real(k + 1)), q.Sc);
+        const Real x1 = fmaT(q.Sc, refine<Real, MODEL>(P, volc, q.wpart, k + 1), q.Sc);
         const Real m = bridge_min(x0, x1, volc * q.Sc, e);
         q.mnc = m < q.mnc ? m : q.mnc;
     }
@@ -175,6 +196,8 @@ __device__ __forceinline__ void coarse_step(PathPair<Real>& q, const StepParams<
     const Real S0c = q.Sc;
     if (MODEL == kGBM) {
         q.Sc = fmaT(q.Sc, fmaT(P.sigma, q.dw1c, P.rH), q.Sc);
+    } else if (MODEL == kGBMMil) {
+        q.Sc = fmaT(q.Sc, fmaT(P.c2, q.dw1c * q.dw1c, fmaT(P.sigma, q.dw1c, P.rH_m)), q.Sc);
     } else {
         const Real vp = q.vc > Real(0) ? q.vc : Real(0);
         const Real sv = fsqrt<Real>(vp);

@@ -35,10 +35,23 @@ __device__ __forceinline__ void accumulate(const LevelArgs<Real>& a, uint64_t id
     add_sample(pf, pc, sums, nonfinite);
 }
 
-// Advance PPT coupled pairs through all n_f >= 4 fine steps of the level.
-template <int MODEL, int PAYOFF, typename Real, int M, int PPT>
+// Position of the antithetic twin's k-th increment inside a group of four:
+// the increments of every coarse step (M of them) in reverse order.
+template <int M>
+__host__ __device__ constexpr int twin_index(int k) { return (k / M) * M + (M - 1 - k % M); }
+
+// The twin runs its own coarse path only where the coarse payoff depends on
+// the fine increments' order (the lookback's refined minimum); elsewhere the
+// twin's coarse path equals the coupled one up to summation order.
+template <int PAYOFF>
+__host__ __device__ constexpr bool twin_coarse() { return PAYOFF == kLookback; }
+
+// Advance PPT coupled pairs through all n_f >= 4 fine steps of the level;
+// with ANTI also each pair's antithetic twin qa (same generator words, the
+// increments reversed inside every coarse step).
+template <int MODEL, int PAYOFF, typename Real, int M, int PPT, bool ANTI>
 __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_t (&s)[PPT],
-                                         PathPair<Real> (&q)[PPT])
+                                         PathPair<Real> (&q)[PPT], PathPair<Real> (&qa)[PPT])
 {
     const StepParams<Real>& P = a.P;
     PathKey key[PPT], bkey[PPT];
@@ -47,6 +60,7 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
         key[p] = make_path_key(a.seed, a.l, s[p], a.stream);
         bkey[p] = make_path_key(a.seed, a.l, s[p], a.stream + 1u);
         init_pair<Real, MODEL, PAYOFF>(q[p], P);
+        if (ANTI) init_pair<Real, MODEL, PAYOFF>(qa[p], P);
     }
     // n_f >= 4 here (a multiple of 4): every group holds four fine steps.
     // The coarse path is advanced even when the caller drops it (standard
@@ -56,7 +70,7 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             Real dw1[4], dwp[4], e[4];
-            if (MODEL == kGBM) {
+            if (one_factor(MODEL)) {
                 const u32x4 w = path_block(key[p], g);
                 brownian_pair(w.x, w.y, P, dw1[0], dw1[1]);
                 brownian_pair(w.z, w.w, P, dw1[2], dw1[3]);
@@ -83,36 +97,57 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
                 fine_step<Real, MODEL, PAYOFF>(q[p], P, dw1[k], dwp[k], e[k], k % M, true);
                 if (((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(q[p], P);
             }
+            if (ANTI) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    constexpr bool tc = twin_coarse<PAYOFF>();
+                    const int j = twin_index<M>(k);
+                    fine_step<Real, MODEL, PAYOFF>(qa[p], P, dw1[j], dwp[j], e[j], k % M, tc);
+                    if (tc && ((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(qa[p], P);
+                }
+            }
         }
+    }
+}
+
+// Fine and coarse payoffs of a pair; with ANTI the averages over the pair
+// and its twin pair (the twin's coarse payoff is the pair's own unless the
+// twin runs a coarse path of its own).
+template <int PAYOFF, typename Real, bool ANTI>
+__device__ __forceinline__ void pair_payoffs(const StepParams<Real>& P, const PathPair<Real>& q,
+                                             const PathPair<Real>& qa, bool coupled, Real& pf,
+                                             Real& pc)
+{
+    pf = payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
+    pc = coupled ? payoff_value<Real, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H) : Real(0);
+    if (ANTI) {
+        pf = Real(0.5) * (pf + payoff_value<Real, PAYOFF>(P, qa.S, qa.asum, qa.acomp, qa.mn, P.h));
+        if (twin_coarse<PAYOFF>())
+            pc = Real(0.5) * (pc + payoff_value<Real, PAYOFF>(P, qa.Sc, qa.csum, qa.ccomp, qa.mnc, P.H));
     }
 }
 
 // Samples base + p * blockDim + threadIdx (p < PPT) of the range described
 // by a (a.offset + index, index < a.N): simulate, then add into the lane sums.
-template <int MODEL, int PAYOFF, typename Real, int M, int PPT>
+template <int MODEL, int PAYOFF, typename Real, int M, int PPT, bool ANTI>
 __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t base,
                                               double (&sums)[kNumSums], unsigned& nonfinite)
 {
     const bool coupled = a.coupled && a.l > 0;
-    const Real dtf = a.P.h, dtc = a.P.H;
-    {
-        uint64_t idx[PPT], s[PPT];
+    uint64_t idx[PPT], s[PPT];
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            idx[p] = base + (uint64_t)p * blockDim.x + threadIdx.x;
-            s[p] = a.offset + idx[p];
-        }
-        PathPair<Real> q[PPT];
-        simulate<MODEL, PAYOFF, Real, M, PPT>(a, s, q);
+    for (int p = 0; p < PPT; ++p) {
+        idx[p] = base + (uint64_t)p * blockDim.x + threadIdx.x;
+        s[p] = a.offset + idx[p];
+    }
+    PathPair<Real> q[PPT], qa[PPT];
+    simulate<MODEL, PAYOFF, Real, M, PPT, ANTI>(a, s, q, qa);
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            const Real pf = payoff_value<Real, PAYOFF>(a.P, q[p].S, q[p].asum, q[p].acomp, q[p].mn, dtf);
-            const Real pc = coupled ? payoff_value<Real, PAYOFF>(a.P, q[p].Sc, q[p].csum, q[p].ccomp,
-                                                                q[p].mnc, dtc)
-                                    : Real(0);
-            if (idx[p] >= a.N) continue;
-            accumulate(a, idx[p], pf, pc, sums, nonfinite);
-        }
+    for (int p = 0; p < PPT; ++p) {
+        Real pf, pc;
+        pair_payoffs<PAYOFF, Real, ANTI>(a.P, q[p], qa[p], coupled, pf, pc);
+        if (idx[p] >= a.N) continue;
+        accumulate(a, idx[p], pf, pc, sums, nonfinite);
     }
 }
 
@@ -131,11 +166,12 @@ __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t
 // so that sum is finite exactly when every y is); otherwise the chunk is
 // added sample by sample with the range and finiteness checks.  y = P_f
 // there, so the sums of P_f repeat those of y and the P_c sums stay zero.
-template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT>
+template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT, bool ANTI>
 __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t blk_base,
                                               double (&sums)[kNumSums], unsigned& nonfinite)
 {
-    constexpr int D = (MODEL == kGBM) ? 1 : 2;
+    static_assert(!ANTI || (NF == 2 && M == 2), "the twin exists on coupled levels only");
+    constexpr int D = one_factor(MODEL) ? 1 : 2;
     constexpr int T = NF * D;             // normals per sample: 1, 2 or 4
     constexpr int Q = 4 / T;              // samples per generator block
     constexpr int QU = 4 / NF;            // samples per bridge block
@@ -173,9 +209,21 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
                 fine_step<Real, MODEL, PAYOFF>(q, P, dw1, dwp, e[(ub + k) & 3], k % M, coupled);
             }
             if (NF == 2 && coupled) coarse_step<Real, MODEL, PAYOFF>(q, P);
-            pf[p][r] = payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
-            pc[p][r] = coupled ? payoff_value<Real, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H)
-                               : Real(0);
+            PathPair<Real> qa;
+            if (ANTI) {
+                // the twin takes the two increments (and bridge words) swapped
+                constexpr bool tc = twin_coarse<PAYOFF>();
+                init_pair<Real, MODEL, PAYOFF>(qa, P);
+#pragma unroll
+                for (int k = 0; k < NF; ++k) {
+                    const int j = NF - 1 - k;
+                    const Real dw1 = dw[r * T + j * D];
+                    const Real dwp = (D == 2) ? dw[r * T + j * D + 1] : Real(0);
+                    fine_step<Real, MODEL, PAYOFF>(qa, P, dw1, dwp, e[(ub + j) & 3], k % M, tc);
+                }
+                if (tc) coarse_step<Real, MODEL, PAYOFF>(qa, P);
+            }
+            pair_payoffs<PAYOFF, Real, ANTI>(P, q, qa, coupled, pf[p][r], pc[p][r]);
             dwf[p][r] = dw[r * T];
         }
     }

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libmlmc.so")
 
 MLMC_OK, MLMC_ENOTCONV, MLMC_EINVAL, MLMC_ENOMEM, MLMC_EDEVICE, MLMC_ENONFINITE = 0, 1, -1, -2, -3, -4
 GBM, HESTON = 0, 1
+EULER, MILSTEIN = 0, 1
 CALL, ASIAN, LOOKBACK, DIGITAL = 0, 1, 2, 3
 STREAM_NORMAL, STREAM_BRIDGE, STREAM_TRAIN_NORMAL = 0, 1, 2
 MAX_LEVELS = 16
@@ -39,7 +40,7 @@ class Model(C.Structure):
     _fields_ = [("kind", C.c_int), ("S0", C.c_double), ("r", C.c_double),
                 ("sigma", C.c_double), ("T", C.c_double), ("kappa", C.c_double),
                 ("theta", C.c_double), ("xi", C.c_double), ("rho", C.c_double),
-                ("v0", C.c_double)]
+                ("v0", C.c_double), ("scheme", C.c_int), ("antithetic", C.c_int)]
 
 
 class Payoff(C.Structure):
@@ -147,8 +148,8 @@ def lib():
 
 
 def model(kind=GBM, S0=100.0, r=0.05, sigma=0.2, T=1.0, kappa=2.0, theta=0.04, xi=0.3,
-          rho=-0.7, v0=0.04):
-    return Model(kind, S0, r, sigma, T, kappa, theta, xi, rho, v0)
+          rho=-0.7, v0=0.04, scheme=0, antithetic=0):
+    return Model(kind, S0, r, sigma, T, kappa, theta, xi, rho, v0, scheme, antithetic)
 
 
 def payoff(kind=CALL, K=100.0, payout=1.0):
