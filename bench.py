@@ -49,7 +49,7 @@ def measured_traffic(kernel_label):
     import hashlib
     h = hashlib.sha256()
     for f in ("philox.hpp", "sampler.hpp", "sampler_impl.hpp", "reduce.hpp", "level.hip",
-              "level.hpp"):
+              "level.hpp", "level_kernels.hpp", "level_gbm.hip"):
         with open(os.path.join(ROOT, "paper_1505_00965_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     digest = h.hexdigest()[:16]
@@ -211,6 +211,17 @@ def fig3(ctx, mlmc, W):
         out[name] = {"runs": [{k: r[k] for k in keep} for r in recs],
                      "shape_checks": {what: ok for what, ok in
                                       complexity.shape_checks(recs, pay["kind"])}}
+    # the same sweep with the Milstein scheme (Sec. 5's remark: beta = 2 >
+    # gamma = 1, so eps^2 x cost stays bounded) and with its antithetic twin
+    for name, extra in (("call_milstein", dict(scheme=1)),
+                        ("call_milstein_antithetic", dict(scheme=1, antithetic=1))):
+        m = mlmc.model(**dict(W.FIG3_MODEL, **extra))
+        recs = complexity.sweep(ctx, m, mlmc.payoff(**W.FIG3_CALL), W.FIG3_EPS, run_stdmc=False,
+                                **W.FIG3_RUN)
+        e2 = [r["eps2_mlmc_cost"] for r in recs]
+        out[name] = {"runs": [{k: r[k] for k in ("eps", "L", "N", "estimate", "eps2_mlmc_cost",
+                                                  "mlmc_s")} for r in recs],
+                     "eps2_cost_max_over_min": max(e2) / min(e2)}
     return out
 
 

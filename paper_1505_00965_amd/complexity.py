@@ -24,14 +24,21 @@ def _level_cost(l, M):
 
 
 def sweep(ctx, model, payoff, eps_list, M=2, L_min=2, L_max=12, n_pilot=10000, seed=1,
-          precision=32, var_pilot=1 << 16, run_stdmc=True, max_std_steps=2e11):
+          precision=32, var_pilot=1 << 16, run_stdmc=True, std_cost=True, max_std_steps=2e11):
     """One record per eps (largest first, as in Fig. 3).
 
     model / payoff: ``mlmc.model(...)`` / ``mlmc.payoff(...)`` structures.
-    max_std_steps caps the standard Monte Carlo run (path steps); a capped
-    comparator is timed on the cap and its time scaled up, which the record
-    states (``std_scaled``).
+    std_cost: estimate the comparator's cost from a variance pilot;
+    run_stdmc: also run and time the comparator.  max_std_steps caps the
+    standard Monte Carlo run (path steps); a capped comparator is timed on
+    the cap and its time scaled up, which the record states
+    (``std_scaled``).  With an antithetic model there is no comparator.
     """
+    if model.antithetic:
+        run_stdmc = std_cost = False
+    # one untimed run first: the first launch of a kernel variant loads its code
+    ctx.mlmc_run(model, payoff, max(eps_list), M=M, L_min=L_min, L_max=L_max, n_pilot=n_pilot,
+                 seed=seed + 999, precision=precision)
     out = []
     for i, eps in enumerate(sorted(eps_list, reverse=True)):
         run_seed = seed + 1000 * i
@@ -42,6 +49,9 @@ def sweep(ctx, model, payoff, eps_list, M=2, L_min=2, L_max=12, n_pilot=10000, s
         rec = {"eps": eps, "L": L, "N": list(r["N"][:L + 1]), "V": list(r["V"][:L + 1]),
                "estimate": r["estimate"], "mlmc_cost": cost, "mlmc_s": r["wall_s"],
                "eps2_mlmc_cost": eps * eps * cost, "eps2_mlmc_s": eps * eps * r["wall_s"]}
+        if not run_stdmc and not std_cost:
+            out.append(rec)
+            continue
         # variance of the finest-grid payoff, from an independent pilot
         p = ctx.mlmc_stdmc(model, payoff, L, M, var_pilot, run_seed, precision=precision)
         mean = p["sum_pf"] / p["n"]
