@@ -41,7 +41,7 @@ extern "C" {
 
 /* ---------------------------------------------------------------- models */
 enum { ORC_GBM = 0, ORC_HESTON = 1 };
-enum { ORC_CALL = 0, ORC_ASIAN = 1, ORC_LOOKBACK = 2, ORC_DIGITAL = 3 };
+enum { ORC_CALL = 0, ORC_ASIAN = 1, ORC_LOOKBACK = 2, ORC_DIGITAL = 3, ORC_DIGITAL_COND = 4 };
 /* Philox stream ids (counter word 3). */
 enum { ORC_STREAM_NORMAL = 0, ORC_STREAM_BRIDGE = 1, ORC_STREAM_TRAIN_NORMAL = 2,
        ORC_STREAM_TRAIN_BRIDGE = 3, ORC_STREAM_STDMC = 4, ORC_STREAM_STDMC_BRIDGE = 5,
@@ -59,7 +59,8 @@ typedef struct {
 } orc_model;
 
 typedef struct {
-    int kind;             /* ORC_CALL, ORC_ASIAN, ORC_LOOKBACK, ORC_DIGITAL */
+    int kind;             /* ORC_CALL, ORC_ASIAN, ORC_LOOKBACK, ORC_DIGITAL,
+                             ORC_DIGITAL_COND                              */
     double K;             /* strike (unused by the floating lookback)       */
     double payout;        /* digital cash amount                            */
 } orc_payoff;

@@ -14,7 +14,7 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 GBM, HESTON = 0, 1
 EULER, MILSTEIN = 0, 1
-CALL, ASIAN, LOOKBACK, DIGITAL = 0, 1, 2, 3
+CALL, ASIAN, LOOKBACK, DIGITAL, DIGITAL_COND = 0, 1, 2, 3, 4
 STREAM_NORMAL, STREAM_BRIDGE, STREAM_TRAIN_NORMAL, STREAM_TRAIN_BRIDGE = 0, 1, 2, 3
 STREAM_STDMC, STREAM_STDMC_BRIDGE, STREAM_INIT = 4, 5, 6
 

@@ -59,6 +59,26 @@
  *            coarse step, so its law is the level-(l-1) fine construction's.
  *            (a reading of Sec. 7.1's "lookback")
  *
+ * Conditional digital (Sec. 7: a conditional Monte Carlo approach inside
+ * the multilevel estimator; a reading, as no formula is given): the digital
+ * payoff is replaced by its expectation given every Brownian increment of
+ * the sample except the last fine one, x = dW_last ~ N(0, h).  Both paths of
+ * a sample condition on the same information.  Given that information the
+ * last step of either path is a polynomial S_N = A + B x + C x^2 in x:
+ *   fine, Euler:      A = S (1 + r h),  B = vol S,  C = 0;
+ *   fine, Milstein:   A = S (1 + r h - sigma^2 h / 2),  B = sigma S,
+ *                     C = sigma^2 S / 2;
+ *   coarse, Euler:    A = S (1 + r H + vol w),  B = vol S,  C = 0;
+ *   coarse, Milstein: A = S (1 + r H + sigma w + sigma^2 (w^2 - H) / 2),
+ *                     B = sigma S (1 + sigma w),  C = sigma^2 S / 2,
+ * with S the state at the start of the last step and w the sum of the other
+ * M - 1 fine increments of the last coarse step.  P(S_N > K) is then
+ * Phi((A - K)/(|B| sqrt h)) for C = 0, and for C > 0 the Gaussian mass
+ * outside the roots x1 < x2 of C x^2 + B x + A - K (all of it when there
+ * are none); Phi(z) = erfc(-z / sqrt 2) / 2, the digital's tie rule when
+ * B = C = 0.  By the tower property each path's expectation is the plain
+ * digital's, so the levels still telescope.
+ *
  * Control variate: if cv is given, P is replaced by
  *   P - sum_n phi(t_n, X_n) dW1_n
  * on each path's own grid, fine with fine increments, coarse with coarse
@@ -107,6 +127,26 @@ static double bridge_min(double x0, double x1, double b, double dt, double u)
     return 0.5 * (x0 + x1 - sqrt(d * d - 2.0 * b * b * dt * log(u)));
 }
 
+static double norm_cdf(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+/* payout P(A + B x + C x^2 > K), x ~ N(0, h), C >= 0. */
+static double digital_given(const orc_payoff *p, double A, double B, double C, double h)
+{
+    double sd = sqrt(h);
+    if (C > 0.0) {
+        double c0 = A - p->K;
+        double disc = B * B - 4.0 * C * c0;
+        if (disc <= 0.0) return p->payout;            /* no real root: always above */
+        double x1 = (-B - sqrt(disc)) / (2.0 * C);
+        double x2 = (-B + sqrt(disc)) / (2.0 * C);
+        return p->payout * (norm_cdf(x1 / sd) + norm_cdf(-x2 / sd));
+    }
+    if (B != 0.0) return p->payout * norm_cdf((A - p->K) / (fabs(B) * sd));
+    if (A > p->K) return p->payout;
+    if (A == p->K) return 0.5 * p->payout;
+    return 0.0;
+}
+
 static double final_payoff(const orc_model *m, const orc_payoff *p, double S,
                            double asian_sum, double mn)
 {
@@ -136,6 +176,7 @@ static double fine_path(const orc_model *m, const orc_payoff *p, int nsteps, dou
                         const orc_cv *cv, double *cv_sum, double gw, double *grad)
 {
     double S = m->S0, v = m->v0, asian = 0.0, mn = INFINITY, cvs = 0.0;
+    double S_last = S, vol_last = 0.0;
     for (int n = 0; n < nsteps; ++n) {
         double t = n * dt;
         if (cv) cvs += orc_cv_phi(m, cv, t, S, v) * dw1[n];
@@ -143,6 +184,8 @@ static double fine_path(const orc_model *m, const orc_payoff *p, int nsteps, dou
         if (cv && grad) orc_cv_phi_grad(m, cv, t, S, v, -gw * dw1[n], grad);
         double S_start = S;
         double vol = vol_of(m, v);
+        S_last = S_start;
+        vol_last = vol;
         em_step(m, &S, &v, dt, dw1[n], dwp ? dwp[n] : 0.0);
         asian += 0.5 * (S_start + S) * dt;
         if (p->kind == ORC_LOOKBACK) {
@@ -151,6 +194,15 @@ static double fine_path(const orc_model *m, const orc_payoff *p, int nsteps, dou
         }
     }
     if (cv_sum) *cv_sum = cvs;
+    if (p->kind == ORC_DIGITAL_COND) {
+        if (!isfinite(S)) return NAN;
+        double A = S_last + S_last * m->r * dt, B = vol_last * S_last, C = 0.0;
+        if (m->scheme == ORC_MILSTEIN) {
+            A -= 0.5 * m->sigma * m->sigma * S_last * dt;
+            C = 0.5 * m->sigma * m->sigma * S_last;
+        }
+        return exp(-m->r * m->T) * digital_given(p, A, B, C, dt);
+    }
     return final_payoff(m, p, S, asian, mn);
 }
 
@@ -187,6 +239,22 @@ static double coarse_path(const orc_model *m, const orc_payoff *p, int M, int nc
                 x_prev = x_next;
             }
         }
+        if (p->kind == ORC_DIGITAL_COND && c == nc - 1) {
+            /* condition on all but the last fine increment of this step */
+            double w = 0.0;
+            for (int k = 0; k < M - 1; ++k) w += dw1[c * M + k];
+            em_step(m, &S, &v, H, dw1c, dwpc);
+            if (!isfinite(S)) return NAN;
+            double A = S_start + S_start * (m->r * H + vol * w), B = vol * S_start, C = 0.0;
+            if (m->scheme == ORC_MILSTEIN) {
+                double s2 = m->sigma * m->sigma;
+                A += 0.5 * s2 * S_start * (w * w - H);
+                B = m->sigma * S_start * (1.0 + m->sigma * w);
+                C = 0.5 * s2 * S_start;
+            }
+            if (cv_sum) *cv_sum = cvs;
+            return exp(-m->r * m->T) * digital_given(p, A, B, C, h);
+        }
         em_step(m, &S, &v, H, dw1c, dwpc);
         asian += 0.5 * (S_start + S) * H;
     }
@@ -201,7 +269,7 @@ static int check_args(const orc_model *m, const orc_payoff *p, int l, int M)
     if (m->scheme != ORC_EULER && m->scheme != ORC_MILSTEIN) return -1;
     if (m->scheme == ORC_MILSTEIN && m->kind != ORC_GBM) return -1;
     if (m->antithetic != 0 && m->antithetic != 1) return -1;
-    if (p->kind < ORC_CALL || p->kind > ORC_DIGITAL) return -1;
+    if (p->kind < ORC_CALL || p->kind > ORC_DIGITAL_COND) return -1;
     if (l < 0 || l > 20 || M < 2 || M > 16) return -1;
     double nf = pow((double)M, (double)l);
     if (nf > (double)(1 << 24)) return -1;
