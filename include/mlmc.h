@@ -52,7 +52,9 @@ typedef enum { MLMC_GBM = 0, MLMC_HESTON = 1 } mlmc_model_kind;
 typedef enum { MLMC_EULER = 0, MLMC_MILSTEIN = 1 } mlmc_scheme;
 /* Payoffs: European call (Sec. 5), arithmetic Asian and floating-strike
  * lookback (named in Sec. 7.1), digital with the tie rule of Sec. 6. */
-typedef enum { MLMC_CALL = 0, MLMC_ASIAN = 1, MLMC_LOOKBACK = 2, MLMC_DIGITAL = 3 } mlmc_payoff_kind;
+typedef enum {
+    MLMC_CALL = 0, MLMC_ASIAN = 1, MLMC_LOOKBACK = 2, MLMC_DIGITAL = 3, MLMC_DIGITAL_COND = 4
+} mlmc_payoff_kind;
 
 typedef struct {
     int kind;                       /* mlmc_model_kind */
@@ -86,7 +88,14 @@ typedef struct {
      *   call     max(S_N - K, 0)
      *   Asian    max(A - K, 0), A the trapezoid average over the path's grid
      *   lookback S_N - min S with a Brownian-bridge minimum on every step
-     *   digital  payout if S_N > K, payout/2 if S_N == K, else 0          */
+     *   digital  payout if S_N > K, payout/2 if S_N == K, else 0
+     *   conditional digital (Sec. 7, conditional Monte Carlo inside the
+     *            multilevel estimator): the digital's expectation given every
+     *            increment of the sample but the last fine one, computed
+     *            exactly from the last step (Gaussian for Euler, a quadratic
+     *            in the increment for Milstein); same mean as the digital on
+     *            every level, far smaller level variances.  Not with the
+     *            control variate.                                          */
 } mlmc_payoff;
 
 /* Sums of one level's samples, eq. (eq:Yldef): Y = P_l - P_{l-1}

@@ -35,7 +35,7 @@ mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payo
     if (!m || !p) return fail(ctx, MLMC_EINVAL, "model and payoff must not be NULL");
     if (m->kind != MLMC_GBM && m->kind != MLMC_HESTON)
         return fail(ctx, MLMC_EINVAL, "unknown model kind");
-    if (p->kind < MLMC_CALL || p->kind > MLMC_DIGITAL)
+    if (p->kind < MLMC_CALL || p->kind > MLMC_DIGITAL_COND)
         return fail(ctx, MLMC_EINVAL, "unknown payoff kind");
     if (M != 2 && M != 4) return fail(ctx, MLMC_EINVAL, "M must be 2 or 4");
     if (l < 0) return fail(ctx, MLMC_EINVAL, "level must be >= 0");
@@ -213,6 +213,8 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
         if (precision != 32) return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
         if (m.scheme != MLMC_EULER || m.antithetic)
             return fail(ctx, MLMC_EINVAL, "the control variate runs with plain Euler paths");
+        if (p.kind == MLMC_DIGITAL_COND)
+            return fail(ctx, MLMC_EINVAL, "the control variate takes the four plain payoffs");
         if (cv_in_dim(cv) != (m.kind == MLMC_HESTON ? 3 : 2))
             return fail(ctx, MLMC_EINVAL, "network inputs do not match the model (2: GBM, 3: Heston)");
         const double nf = (double)level_steps(l, M);

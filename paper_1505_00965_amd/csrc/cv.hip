@@ -574,6 +574,8 @@ static mlmc_status check_train_args(mlmc_cv* cv, const mlmc_model* m, const mlmc
     if (B < 2 || B > (1ull << 24)) return fail(ctx, MLMC_EINVAL, "batch must be in 2..2^24 per level");
     if (cv->D != (m->kind == MLMC_HESTON ? 3 : 2))
         return fail(ctx, MLMC_EINVAL, "network inputs do not match the model (2: GBM, 3: Heston)");
+    if (m->scheme != MLMC_EULER || m->antithetic || p->kind == MLMC_DIGITAL_COND)
+        return fail(ctx, MLMC_EINVAL, "the control variate trains on plain Euler paths and payoffs");
     return MLMC_OK;
 }
 

@@ -99,6 +99,7 @@ KernelFn<Real> pick_variant(int payoff, int M, int ppt, int nf, bool anti)
     case kCall: return pick_m<MODEL, kCall, Real>(M, ppt, nf, anti);
     case kAsian: return pick_m<MODEL, kAsian, Real>(M, ppt, nf, anti);
     case kLookback: return pick_m<MODEL, kLookback, Real>(M, ppt, nf, anti);
+    case kDigitalCond: return pick_m<MODEL, kDigitalCond, Real>(M, ppt, nf, anti);
     default: return pick_m<MODEL, kDigital, Real>(M, ppt, nf, anti);
     }
 }

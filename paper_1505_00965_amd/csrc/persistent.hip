@@ -180,6 +180,7 @@ __global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
         case kCall: run_item<MODEL, kCall, M, PPT>(d, w, sums, nonfinite); break;
         case kAsian: run_item<MODEL, kAsian, M, PPT>(d, w, sums, nonfinite); break;
         case kLookback: run_item<MODEL, kLookback, M, PPT>(d, w, sums, nonfinite); break;
+        case kDigitalCond: run_item<MODEL, kDigitalCond, M, PPT>(d, w, sums, nonfinite); break;
         default: run_item<MODEL, kDigital, M, PPT>(d, w, sums, nonfinite); break;
         }
         block_reduce_add(sums, nonfinite, &d->acc[w.slot * kMaxLevels + w.level]);

@@ -24,7 +24,7 @@ namespace mlmc {
 enum ModelKind : int { kGBM = 0, kHeston = 1, kGBMMil = 2 };
 // One Brownian factor and a constant volatility sigma (both GBM variants).
 __host__ __device__ constexpr bool one_factor(int model) { return model != kHeston; }
-enum PayoffKind : int { kCall = 0, kAsian = 1, kLookback = 2, kDigital = 3 };
+enum PayoffKind : int { kCall = 0, kAsian = 1, kLookback = 2, kDigital = 3, kDigitalCond = 4 };
 
 // Model and payoff parameters converted once on the host.
 template <typename Real>
@@ -120,6 +120,9 @@ struct PathPair {
     Real mn, mnc;              // bridge minima
     Real wpart;                // coarse lookback: fine Brownian path since the coarse step start
     Real cvf, cvc;             // control-variate sums (unused without a network)
+    // conditional digital: state, volatility and increment of the last step
+    Real Sl, vl, dwl;          // fine path
+    Real Scl, vcl, wcl;        // coarse path (wcl: its whole last increment)
 };
 
 template <typename Real, int MODEL, int PAYOFF>
@@ -130,6 +133,7 @@ __device__ __forceinline__ void init_pair(PathPair<Real>& q, const StepParams<Re
     q.asum = 0; q.acomp = 0; q.csum = 0; q.ccomp = 0;
     q.mn = Real(INFINITY); q.mnc = Real(INFINITY);
     q.wpart = 0; q.cvf = 0; q.cvc = 0;
+    q.Sl = q.vl = q.dwl = 0; q.Scl = q.vcl = q.wcl = 0;
 }
 
 // Relative move of the frozen-coefficient coarse step after j fine times
@@ -166,6 +170,11 @@ __device__ __forceinline__ void fine_step(PathPair<Real>& q, const StepParams<Re
         q.v = fmaT(P.xi * vol, dw2, fmaT(P.kappa * P.h, P.theta - vp, q.v));
     }
     if (PAYOFF == kAsian) comp_add(q.asum, q.acomp, S0n + q.S);
+    if (PAYOFF == kDigitalCond) {
+        q.Sl = S0n;
+        q.vl = vol;
+        q.dwl = dw1;
+    }
     if (PAYOFF == kLookback) {
         const Real m = bridge_min(S0n, q.S, vol * S0n, e);
         q.mn = m < q.mn ? m : q.mn;
@@ -194,16 +203,25 @@ template <typename Real, int MODEL, int PAYOFF>
 __device__ __forceinline__ void coarse_step(PathPair<Real>& q, const StepParams<Real>& P)
 {
     const Real S0c = q.Sc;
+    Real volc;
     if (MODEL == kGBM) {
+        volc = P.sigma;
         q.Sc = fmaT(q.Sc, fmaT(P.sigma, q.dw1c, P.rH), q.Sc);
     } else if (MODEL == kGBMMil) {
+        volc = P.sigma;
         q.Sc = fmaT(q.Sc, fmaT(P.c2, q.dw1c * q.dw1c, fmaT(P.sigma, q.dw1c, P.rH_m)), q.Sc);
     } else {
         const Real vp = q.vc > Real(0) ? q.vc : Real(0);
         const Real sv = fsqrt<Real>(vp);
+        volc = sv;
         const Real dw2 = fmaT(P.rho, q.dw1c, P.rho_c * q.dwpc);
         q.Sc = fmaT(q.Sc, fmaT(sv, q.dw1c, P.rH), q.Sc);
         q.vc = fmaT(P.xi * sv, dw2, fmaT(P.kappa * P.H, P.theta - vp, q.vc));
+    }
+    if (PAYOFF == kDigitalCond) {
+        q.Scl = S0c;
+        q.vcl = volc;
+        q.wcl = q.dw1c;
     }
     if (PAYOFF == kAsian) comp_add(q.csum, q.ccomp, S0c + q.Sc);
     q.dw1c = 0;
@@ -229,6 +247,66 @@ __device__ __forceinline__ Real payoff_value(const StepParams<Real>& P, Real S, 
     // a path that overflowed stays visible as a non-finite payoff: S - S is
     // +0 for finite S and NaN otherwise (two lane operations, no branch)
     return v + (S - S);
+}
+
+// Standard normal distribution function, erfc(-z / sqrt 2) / 2.
+__device__ __forceinline__ float norm_cdf(float z) { return 0.5f * erfcf(-0.70710678118654752f * z); }
+__device__ __forceinline__ double norm_cdf(double z) { return 0.5 * erfc(-0.70710678118654752 * z); }
+
+// payout P(A + B x + C x^2 > K) for x ~ N(0, h), C >= 0 (roots in the stable
+// form q = -(B + sign(B) sqrt(disc))/2, x = q/C and (A - K)/q).
+template <typename Real>
+__device__ __forceinline__ Real digital_given(const StepParams<Real>& P, Real A, Real B, Real C)
+{
+    const Real c0 = A - P.K;
+    if (C > Real(0)) {
+        const Real disc = fmaT(B, B, Real(-4) * C * c0);
+        if (disc <= Real(0)) return P.payout;
+        const Real q = Real(-0.5) * (B + copysign(fsqrt<Real>(disc), B));
+        Real x1 = q / C, x2 = c0 / q;
+        if (x1 > x2) { const Real t = x1; x1 = x2; x2 = t; }
+        return P.payout * (norm_cdf(x1 / P.sqh) + norm_cdf(-x2 / P.sqh));
+    }
+    if (B != Real(0)) return P.payout * norm_cdf(c0 / (fabs(B) * P.sqh));
+    return c0 > Real(0) ? P.payout : (c0 == Real(0) ? Real(0.5) * P.payout : Real(0));
+}
+
+// The conditional digital of a path pair: expectation of the digital given
+// every increment but the last fine one.  Given it, the last fine step is
+// A + B x + C x^2 with x the last increment: Euler A = S (1 + r h),
+// B = vol S, C = 0; Milstein A = S (1 + (r - sigma^2/2) h), B = sigma S,
+// C = sigma^2 S / 2.  The coarse path's last step has the known part
+// w = (its increment) - x: Euler A = S (1 + r H + vol w), B = vol S;
+// Milstein A = S (1 + (r - sigma^2/2) H + sigma w + sigma^2 w^2 / 2),
+// B = sigma S (1 + sigma w), C = sigma^2 S / 2.  Discounted; NaN when the
+// path overflowed.
+template <typename Real, int MODEL>
+__device__ __forceinline__ Real cond_digital_fine(const StepParams<Real>& P, const PathPair<Real>& q)
+{
+    Real A, B = q.vl * q.Sl, C = Real(0);
+    if (MODEL == kGBMMil) {
+        A = fmaT(q.Sl, P.rh_m, q.Sl);
+        C = P.c2 * q.Sl;
+    } else {
+        A = fmaT(q.Sl, P.rh, q.Sl);
+    }
+    return P.disc * digital_given(P, A, B, C) + (q.S - q.S);
+}
+
+template <typename Real, int MODEL>
+__device__ __forceinline__ Real cond_digital_coarse(const StepParams<Real>& P, const PathPair<Real>& q)
+{
+    const Real w = q.wcl - q.dwl;
+    Real A, B, C = Real(0);
+    if (MODEL == kGBMMil) {
+        A = fmaT(q.Scl, fmaT(P.c2, w * w, fmaT(P.sigma, w, P.rH_m)), q.Scl);
+        B = P.sigma * q.Scl * fmaT(P.sigma, w, Real(1));
+        C = P.c2 * q.Scl;
+    } else {
+        A = fmaT(q.Scl, fmaT(q.vcl, w, P.rH), q.Scl);
+        B = q.vcl * q.Scl;
+    }
+    return P.disc * digital_given(P, A, B, C) + (q.Sc - q.Sc);
 }
 
 }  // namespace mlmc

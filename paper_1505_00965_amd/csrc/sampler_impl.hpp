@@ -44,7 +44,10 @@ __host__ __device__ constexpr int twin_index(int k) { return (k / M) * M + (M - 
 // the fine increments' order (the lookback's refined minimum); elsewhere the
 // twin's coarse path equals the coupled one up to summation order.
 template <int PAYOFF>
-__host__ __device__ constexpr bool twin_coarse() { return PAYOFF == kLookback; }
+__host__ __device__ constexpr bool twin_coarse()
+{
+    return PAYOFF == kLookback || PAYOFF == kDigitalCond;
+}
 
 // Advance PPT coupled pairs through all n_f >= 4 fine steps of the level;
 // with ANTI also each pair's antithetic twin qa (same generator words, the
@@ -113,17 +116,30 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
 // Fine and coarse payoffs of a pair; with ANTI the averages over the pair
 // and its twin pair (the twin's coarse payoff is the pair's own unless the
 // twin runs a coarse path of its own).
-template <int PAYOFF, typename Real, bool ANTI>
+template <int MODEL, int PAYOFF, typename Real>
+__device__ __forceinline__ Real fine_payoff(const StepParams<Real>& P, const PathPair<Real>& q)
+{
+    if constexpr (PAYOFF == kDigitalCond) return cond_digital_fine<Real, MODEL>(P, q);
+    else return payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
+}
+
+template <int MODEL, int PAYOFF, typename Real>
+__device__ __forceinline__ Real coarse_payoff(const StepParams<Real>& P, const PathPair<Real>& q)
+{
+    if constexpr (PAYOFF == kDigitalCond) return cond_digital_coarse<Real, MODEL>(P, q);
+    else return payoff_value<Real, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H);
+}
+
+template <int MODEL, int PAYOFF, typename Real, bool ANTI>
 __device__ __forceinline__ void pair_payoffs(const StepParams<Real>& P, const PathPair<Real>& q,
                                              const PathPair<Real>& qa, bool coupled, Real& pf,
                                              Real& pc)
 {
-    pf = payoff_value<Real, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
-    pc = coupled ? payoff_value<Real, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H) : Real(0);
+    pf = fine_payoff<MODEL, PAYOFF>(P, q);
+    pc = coupled ? coarse_payoff<MODEL, PAYOFF>(P, q) : Real(0);
     if (ANTI) {
-        pf = Real(0.5) * (pf + payoff_value<Real, PAYOFF>(P, qa.S, qa.asum, qa.acomp, qa.mn, P.h));
-        if (twin_coarse<PAYOFF>())
-            pc = Real(0.5) * (pc + payoff_value<Real, PAYOFF>(P, qa.Sc, qa.csum, qa.ccomp, qa.mnc, P.H));
+        pf = Real(0.5) * (pf + fine_payoff<MODEL, PAYOFF>(P, qa));
+        if (twin_coarse<PAYOFF>()) pc = Real(0.5) * (pc + coarse_payoff<MODEL, PAYOFF>(P, qa));
     }
 }
 
@@ -145,7 +161,7 @@ __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         Real pf, pc;
-        pair_payoffs<PAYOFF, Real, ANTI>(a.P, q[p], qa[p], coupled, pf, pc);
+        pair_payoffs<MODEL, PAYOFF, Real, ANTI>(a.P, q[p], qa[p], coupled, pf, pc);
         if (idx[p] >= a.N) continue;
         accumulate(a, idx[p], pf, pc, sums, nonfinite);
     }
@@ -223,7 +239,7 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
                 }
                 if (tc) coarse_step<Real, MODEL, PAYOFF>(qa, P);
             }
-            pair_payoffs<PAYOFF, Real, ANTI>(P, q, qa, coupled, pf[p][r], pc[p][r]);
+            pair_payoffs<MODEL, PAYOFF, Real, ANTI>(P, q, qa, coupled, pf[p][r], pc[p][r]);
             dwf[p][r] = dw[r * T];
         }
     }

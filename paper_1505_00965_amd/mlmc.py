@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libmlmc.so")
 MLMC_OK, MLMC_ENOTCONV, MLMC_EINVAL, MLMC_ENOMEM, MLMC_EDEVICE, MLMC_ENONFINITE = 0, 1, -1, -2, -3, -4
 GBM, HESTON = 0, 1
 EULER, MILSTEIN = 0, 1
-CALL, ASIAN, LOOKBACK, DIGITAL = 0, 1, 2, 3
+CALL, ASIAN, LOOKBACK, DIGITAL, DIGITAL_COND = 0, 1, 2, 3, 4
 STREAM_NORMAL, STREAM_BRIDGE, STREAM_TRAIN_NORMAL = 0, 1, 2
 MAX_LEVELS = 16
 

@@ -18,6 +18,7 @@ CALL = dict(kind=0, K=100.0, payout=1.0)
 ASIAN = dict(kind=1, K=100.0, payout=1.0)
 LOOKBACK = dict(kind=2, K=100.0, payout=1.0)
 DIGITAL = dict(kind=3, K=100.0, payout=1.0)
+DIGITAL_COND = dict(kind=4, K=100.0, payout=1.0)
 PAYOFFS = {"call": CALL, "asian": ASIAN, "lookback": LOOKBACK, "digital": DIGITAL}
 
 # Sec. 6 experiment (Fig. 3): GBM with sigma = 0.25, European call and digital
