@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["rng.c", "sampler.c", "driver.c", "closed_form.c", "cv.c"]
+SOURCES = ["rng.c", "sampler.c", "driver.c", "closed_form.c", "cv.c", "rhee_glynn.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -45,7 +45,7 @@ enum { ORC_CALL = 0, ORC_ASIAN = 1, ORC_LOOKBACK = 2, ORC_DIGITAL = 3, ORC_DIGIT
 /* Philox stream ids (counter word 3). */
 enum { ORC_STREAM_NORMAL = 0, ORC_STREAM_BRIDGE = 1, ORC_STREAM_TRAIN_NORMAL = 2,
        ORC_STREAM_TRAIN_BRIDGE = 3, ORC_STREAM_STDMC = 4, ORC_STREAM_STDMC_BRIDGE = 5,
-       ORC_STREAM_INIT = 6 };
+       ORC_STREAM_INIT = 6, ORC_STREAM_LEVEL_DRAW = 7 };
 
 enum { ORC_EULER = 0, ORC_MILSTEIN = 1 };
 
@@ -157,6 +157,22 @@ typedef struct {
 
 int orc_mlmc_run(const orc_model *m, const orc_payoff *p, const orc_run_opts *o,
                  orc_run_result *out);
+/* Randomised single-term estimator (rhee_glynn.c). */
+typedef struct {
+    double estimate;      /* (1/N) sum_l S1_l / p_l                          */
+    double variance;      /* per-sample variance of Z = Y_L / p_L            */
+    double cost;          /* path steps                                      */
+    int Lc;
+    uint64_t N[16];       /* samples that drew each level                    */
+    double p[16], sum_y[16], sum_y2[16];
+    uint64_t n_nonfinite;
+} orc_rg_result;
+
+void orc_rg_probabilities(double q, int Lc, double *p, double *F);
+int orc_rg_level_counts(uint64_t seed, uint64_t N, double q, int Lc, uint64_t *counts);
+int orc_rhee_glynn(const orc_model *m, const orc_payoff *p, int M, int Lc, double q, uint64_t N,
+                   uint64_t seed, int nthreads, orc_rg_result *out);
+
 /* Least-squares slope of log_M |y_l| against l over l = 1..L (y_l > 0). */
 double orc_fit_rate(int L, const double *y, int M);
 

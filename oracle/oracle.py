@@ -16,7 +16,7 @@ GBM, HESTON = 0, 1
 EULER, MILSTEIN = 0, 1
 CALL, ASIAN, LOOKBACK, DIGITAL, DIGITAL_COND = 0, 1, 2, 3, 4
 STREAM_NORMAL, STREAM_BRIDGE, STREAM_TRAIN_NORMAL, STREAM_TRAIN_BRIDGE = 0, 1, 2, 3
-STREAM_STDMC, STREAM_STDMC_BRIDGE, STREAM_INIT = 4, 5, 6
+STREAM_STDMC, STREAM_STDMC_BRIDGE, STREAM_INIT, STREAM_LEVEL_DRAW = 4, 5, 6, 7
 
 
 class Model(C.Structure):
@@ -48,6 +48,13 @@ class RunOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("M", C.c_int), ("L_min", C.c_int), ("L_max", C.c_int),
                 ("n_pilot", C.c_uint64), ("seed", C.c_uint64), ("alpha", C.c_double),
                 ("beta", C.c_double), ("nthreads", C.c_int), ("cv", C.POINTER(CV))]
+
+
+class RGResult(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("variance", C.c_double), ("cost", C.c_double),
+                ("Lc", C.c_int), ("N", C.c_uint64 * 16), ("p", C.c_double * 16),
+                ("sum_y", C.c_double * 16), ("sum_y2", C.c_double * 16),
+                ("n_nonfinite", C.c_uint64)]
 
 
 class RunResult(C.Structure):
@@ -116,6 +123,10 @@ def lib():
                                        u64, C.POINTER(CV), i32, dp, dp]
         L.orc_cv_loss_grad.restype = d
         L.orc_adam.argtypes = [C.c_size_t, dp, dp, dp, dp, d, d, d, d, i32]
+        L.orc_rg_probabilities.argtypes = [d, i32, dp, dp]
+        L.orc_rg_level_counts.argtypes = [u64, u64, d, i32, C.POINTER(C.c_uint64)]
+        L.orc_rhee_glynn.argtypes = [C.POINTER(Model), C.POINTER(Payoff), i32, i32, d, u64, u64,
+                                     i32, C.POINTER(RGResult)]
         _lib = L
     return _lib
 
@@ -345,3 +356,26 @@ def adam(theta, m1, m2, g, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, t=1):
     """In-place Adam step on FP64 numpy arrays."""
     lib().orc_adam(theta.size, _dp(theta), _dp(m1), _dp(m2),
                    _dp(np.ascontiguousarray(g, dtype=np.float64)), lr, b1, b2, eps, t)
+
+
+def rg_probabilities(q, Lc):
+    p, F = np.zeros(Lc + 1), np.zeros(Lc + 1)
+    lib().orc_rg_probabilities(q, Lc, _dp(p), _dp(F))
+    return p, F
+
+
+def rg_level_counts(seed, N, q, Lc):
+    c = np.zeros(Lc + 1, np.uint64)
+    if lib().orc_rg_level_counts(seed, N, q, Lc, c.ctypes.data_as(C.POINTER(C.c_uint64))):
+        raise ValueError("orc_rg_level_counts: bad arguments")
+    return c
+
+
+def rhee_glynn(m, p, M, Lc, q, N, seed, nthreads=1):
+    r = RGResult()
+    if lib().orc_rhee_glynn(C.byref(m), C.byref(p), M, Lc, q, N, seed, nthreads, C.byref(r)):
+        raise ValueError("orc_rhee_glynn: bad arguments")
+    n = Lc + 1
+    return {"estimate": r.estimate, "variance": r.variance, "cost": r.cost, "Lc": r.Lc,
+            "N": list(r.N)[:n], "p": list(r.p)[:n], "sum_y": list(r.sum_y)[:n],
+            "sum_y2": list(r.sum_y2)[:n], "n_nonfinite": r.n_nonfinite}
