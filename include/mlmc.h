@@ -268,6 +268,36 @@ typedef struct {
 mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
                      const mlmc_run_opts* opts, mlmc_run_result* out);
 
+/* ----------------------------------------------- randomised estimator
+ * Rhee and Glynn's randomised multilevel estimator (cited in Sec. 7): each
+ * of the N samples draws its level L with probability
+ * p_l = (1 - q) q^l / (1 - q^(L_cap+1)), l = 0..L_cap, and contributes
+ * Z = Y_L / p_L (eqs. (eq:mlmc:Yzero), (eq:Yldef)), so E[Z] = E[P_L_cap]
+ * (eq. (eq:mlmc:ident)) without a bias test.  The variance is finite when
+ * q > M^-beta and the expected cost when q < M^-1: use it with a scheme of
+ * beta > 1 (MLMC_MILSTEIN), e.g. q = M^-1.5.  Level draws: word i mod 4 of
+ * the generator block at counter (0, i / 4, 0, stream 7), u = ((x >> 8) +
+ * 1/2) 2^-24, L = the first l with u < sum_{k <= l} p_k.  Level l then runs
+ * on its samples 0 .. N_l - 1 of the ordinary sampler (stream 0).
+ * L_cap <= 15 and within the level limits of M; 0 < q < 1; 1 <= N <= 2^40.
+ * Host output; MLMC_ENONFINITE as for mlmc_level.                          */
+typedef struct {
+    double estimate;     /* (1/N) sum_l S1_l / p_l                          */
+    double variance;     /* per-sample variance of Z                        */
+    double rmse_est;     /* sqrt(variance / N)                              */
+    double cost;         /* path steps                                      */
+    double wall_s;
+    int L_cap;
+    uint64_t N[MLMC_MAX_LEVELS];       /* samples that drew each level     */
+    double p[MLMC_MAX_LEVELS];
+    double sum_y[MLMC_MAX_LEVELS], sum_y2[MLMC_MAX_LEVELS];
+    uint64_t n_nonfinite;
+} mlmc_rg_result;
+
+mlmc_status mlmc_rhee_glynn(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                            int M, int L_cap, double q, uint64_t N, uint64_t seed, int precision,
+                            mlmc_rg_result* out);
+
 /* ------------------------------------------------------- control variate
  * Learned martingale control variate (Sec. 5, "Exploiting Structure": a
  * control variate with known mean).  Each payoff P of a level sample is

@@ -59,7 +59,7 @@ mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payo
 }
 
 // Path steps per sample of level l: n_f + n_c (2 n_f + n_c with the twin).
-static double level_cost(const mlmc_model& m, int l, int M)
+double level_cost(const mlmc_model& m, int l, int M)
 {
     if (l == 0) return 1.0;
     const double nf = std::pow((double)M, (double)l);

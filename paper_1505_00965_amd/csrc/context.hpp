@@ -56,6 +56,8 @@ mlmc_status hip_fail(mlmc_ctx* ctx, hipError_t e, const char* what);
     } while (0)
 
 // Argument validation shared by the level entry points.
+// Path steps per sample of level l (n_f + n_c; 2 n_f + n_c with the twin).
+double level_cost(const mlmc_model& m, int l, int M);
 mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payoff* p, int l, int M,
                              int precision);
 // Launch shape for N samples at level l (honours mlmc_set_launch).

@@ -30,6 +30,7 @@ enum Stream : uint32_t {
     kStreamStdMC = 4,
     kStreamStdMCBridge = 5,
     kStreamInit = 6,
+    kStreamLevelDraw = 7,   // levels drawn by the randomised estimator
 };
 
 struct u32x4 {

@@ -24,7 +24,7 @@ EXPORTED = [
     "mlmc_levels_batch", "mlmc_set_persistent_launch",
     "mlmc_cv_create", "mlmc_cv_destroy", "mlmc_cv_nparams", "mlmc_cv_get_params",
     "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train", "mlmc_autotune",
-    "mlmc_tuned_shape",
+    "mlmc_tuned_shape", "mlmc_rhee_glynn",
 ]
 STAT_SLOTS = 20
 STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
@@ -66,6 +66,14 @@ class RunOpts(C.Structure):
                 ("n_pilot", C.c_uint64), ("seed", C.c_uint64), ("precision", C.c_int),
                 ("persistent", C.c_int), ("alpha", C.c_double), ("beta", C.c_double),
                 ("cv", C.c_void_p), ("cv_levels", C.c_int)]
+
+
+class RGResult(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("variance", C.c_double), ("rmse_est", C.c_double),
+                ("cost", C.c_double), ("wall_s", C.c_double), ("L_cap", C.c_int),
+                ("N", C.c_uint64 * MAX_LEVELS), ("p", C.c_double * MAX_LEVELS),
+                ("sum_y", C.c_double * MAX_LEVELS), ("sum_y2", C.c_double * MAX_LEVELS),
+                ("n_nonfinite", C.c_uint64)]
 
 
 class RunResult(C.Structure):
@@ -122,6 +130,7 @@ def lib():
     L.mlmc_philox_words.argtypes = [vp, u64, i32, u64, u32, u32, u64, vp]
     L.mlmc_normals.argtypes = [vp, u64, i32, u64, u32, i32, i32, u64, i32, vp]
     L.mlmc_stdmc.argtypes = [vp, M_, P_, i32, i32, u64, u64, u64, i32, C.POINTER(LevelResult)]
+    L.mlmc_rhee_glynn.argtypes = [vp, M_, P_, i32, i32, d, u64, u64, i32, C.POINTER(RGResult)]
     L.mlmc_optimal_n.argtypes = [vp, i32, C.POINTER(d), C.POINTER(d), d, C.POINTER(d)]
     L.mlmc_run.argtypes = [vp, M_, P_, C.POINTER(RunOpts), C.POINTER(RunResult)]
     L.mlmc_levels_batch.argtypes = [vp, M_, P_, i32, i32, i32, C.POINTER(u64), C.POINTER(u64),
@@ -253,6 +262,16 @@ class Context:
     def mlmc_normals(self, seed, level, s0, stream, dim, nsteps, npaths, precision, d_out):
         self._check(self._lib.mlmc_normals(self.h, seed, level, s0, stream, dim, nsteps, npaths,
                                            precision, _ptr(d_out)))
+
+    def mlmc_rhee_glynn(self, m, p, M, L_cap, q, N, seed, precision=32):
+        r = RGResult()
+        self._check(self._lib.mlmc_rhee_glynn(self.h, C.byref(m), C.byref(p), M, L_cap, q, N, seed,
+                                              precision, C.byref(r)))
+        n = L_cap + 1
+        return {"estimate": r.estimate, "variance": r.variance, "rmse_est": r.rmse_est,
+                "cost": r.cost, "wall_s": r.wall_s, "L_cap": r.L_cap, "N": list(r.N)[:n],
+                "p": list(r.p)[:n], "sum_y": list(r.sum_y)[:n], "sum_y2": list(r.sum_y2)[:n],
+                "n_nonfinite": r.n_nonfinite}
 
     def mlmc_stdmc(self, m, p, L, M, N, seed, path_offset=0, precision=32):
         r = LevelResult()
