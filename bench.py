@@ -313,6 +313,22 @@ def main():
                        "estimate": runs[-1]["estimate"]},
             "roofline": roofline}
 
+    if not args.persistent and not args.no_tta:
+        # the same estimates with every driver iteration as one graph launch
+        # (plan, persistent all-levels sampler, driver update)
+        for i in range(args.warmup):
+            ctx.mlmc_run(gm, gp, eps, M=M, L_min=2, L_max=9, n_pilot=10000,
+                         seed=1 + i % max(args.steps, 1), precision=32, persistent=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gr = [ctx.mlmc_run(gm, gp, eps, M=M, L_min=2, L_max=9, n_pilot=10000, seed=1 + i,
+                           precision=32, persistent=True) for i in range(args.steps)]
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
+        line["adaptive_graph_form"] = {
+            "ms_per_step": 1e3 * dtg / args.steps,
+            "fine_path_steps_per_s": sum(fine_steps_of(r, M) for r in gr) / dtg,
+            "same_N_l": all(a["N"] == b["N"] for a, b in zip(runs, gr))}
     if not args.no_tta:
         line["persistent_batch"] = persistent_batch(ctx, mlmc, W)
         line["seconds_to_rmse"] = time_to_accuracy(ctx, mlmc, W, args)

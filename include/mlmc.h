@@ -228,9 +228,9 @@ typedef struct {
     uint64_t n_pilot;    /* initial samples on each of levels 0..L_min      */
     uint64_t seed;
     int precision;       /* 32 or 64                                         */
-    int persistent;      /* 1: every iteration is one graph launch of the
-                            persistent all-levels kernel; 0: one launch per
-                            level                                             */
+    int persistent;      /* 0: one launch per level and iteration; 1: every
+                            iteration is one graph launch of the persistent
+                            all-levels kernel (plan, sampler, update)        */
     double alpha, beta;  /* assumed weak and variance rates (<= 0: 1 and 1) */
     const mlmc_cv* cv;   /* NULL: plain MLMC.  Needs precision 32 and
                             persistent 0 (MLMC_EINVAL otherwise).             */

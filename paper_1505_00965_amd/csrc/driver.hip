@@ -1,15 +1,5 @@
-// Adaptive MLMC driver: the fp64 update kernel and the host loop.
-//
-// The paper fixes the estimator Y = sum_l Yhat_l (eq. (eq:mlmc:ident)), that
-// level variances add (Sec. 5), the cost measure (Sec. 3), and leaves N_l to
-// an optimisation over estimated variances (Sec. 5, "Constructive Upper
-// Bound"); the complexity theorem sets the target E[(Y - E P)^2] < eps^2.
-// Reading used: eps is an RMSE split evenly into bias^2 and variance;
-// minimising sum N_l C_l under sum V_l/N_l = eps^2/2 gives
-// N_l = ceil(2 eps^-2 sqrt(V_l/C_l) sum_k sqrt(V_k C_k)); costs
-// C_0 = 1, C_l = M^l + M^(l-1); estimates floored by the assumed rates from
-// l = 2; a level is resampled when its shortfall exceeds 1%; the bias is
-// estimated from weak order alpha (eq. (eq:emweak)).
+// Adaptive MLMC driver: the fp64 update kernel and the host loops (the
+// arithmetic itself is in driver_dev.hpp).
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -20,156 +10,43 @@
 
 #include "context.hpp"
 #include "driver.hpp"
+#include "driver_dev.hpp"
 
 namespace mlmc {
-
-__device__ double level_cost_dev(int l, int M, int antithetic)
-{
-    if (l == 0) return 1.0;
-    double a = 1.0;
-    for (int i = 0; i < l - 1; ++i) a *= M;
-    return (antithetic ? 2.0 : 1.0) * a * M + a;
-}
-
-__device__ void optimal_n_dev(int L, const double* V, const double* C, double eps, double* N)
-{
-    double total = 0.0;
-    for (int k = 0; k <= L; ++k) total += sqrt(V[k] * C[k]);
-    for (int l = 0; l <= L; ++l) N[l] = ceil(2.0 / (eps * eps) * sqrt(V[l] / C[l]) * total);
-}
 
 __global__ void optimal_n_kernel(int L, const double* V, const double* C, double eps, double* N)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) optimal_n_dev(L, V, C, eps, N);
 }
 
-__device__ double fit_rate_dev(int L, const double* y, int M)
+// A fresh state: zeros, the configuration, n_pilot outstanding samples on
+// levels 0..L_min (the host mirror is filled the same way on the host).
+__global__ void driver_init_kernel(DriverState* st, double eps, double alpha, double beta, int M,
+                                   int antithetic, int L_min, int L_max, int max_iterations,
+                                   double n_pilot)
 {
-    double sx = 0, sy = 0, sxx = 0, sxy = 0;
-    int n = 0;
-    for (int l = 1; l <= L; ++l) {
-        if (!(y[l] > 0)) continue;
-        const double x = l, v = log(y[l]) / log((double)M);
-        sx += x; sy += v; sxx += x * x; sxy += x * v; ++n;
-    }
-    if (n < 2) return nan("");
-    return (n * sxy - sx * sy) / (n * sxx - sx * sx);
-}
-
-// Absorb the batch, re-plan.  One thread; a handful of fp64 operations.
-__device__ void driver_update_dev(DriverState* st)
-{
-    const int M = st->M;
-    const double Ma = pow((double)M, st->alpha), Mb = pow((double)M, st->beta);
-    int L = st->L;
-    for (int l = 0; l <= L; ++l) {
-        if (st->dN[l] > 0) {
-            st->sum1[l] += st->batch[l].sum[0];
-            st->sum2[l] += st->batch[l].sum[1];
-            st->n[l] += st->dN[l];
-            st->n_nonfinite += st->batch[l].n_nonfinite;
-        }
-        for (int k = 0; k < kNumSums; ++k) st->batch[l].sum[k] = 0.0;
-        st->batch[l].n_nonfinite = 0;
-        st->dN[l] = 0.0;
-    }
-    st->iterations += 1;
-    for (int l = 0; l <= L; ++l) {
-        st->C[l] = level_cost_dev(l, M, st->antithetic);
-        const double m = st->sum1[l] / st->n[l];
-        st->E[l] = fabs(m);
-        st->V[l] = st->sum2[l] / st->n[l] - m * m;
-        if (st->V[l] < 0) st->V[l] = 0;
-    }
-    for (int l = 2; l <= L; ++l) {
-        if (st->E[l] < st->E[l - 1] / Ma) st->E[l] = st->E[l - 1] / Ma;
-        if (st->V[l] < st->V[l - 1] / Mb) st->V[l] = st->V[l - 1] / Mb;
-    }
-    optimal_n_dev(L, st->V, st->C, st->eps, st->Nopt);
-    int more = 0;
-    for (int l = 0; l <= L; ++l) {
-        const double d = st->Nopt[l] - st->n[l];
-        st->dN[l] = (d > 0.01 * st->n[l]) ? d : 0.0;
-        if (st->dN[l] > 0) more = 1;
-    }
-    if (!more) {
-        const double rem = fmax(st->E[L], st->E[L - 1] / Ma) / (Ma - 1.0);
-        st->bias_est = rem;
-        if (rem <= st->eps / sqrt(2.0)) {
-            st->converged = 1;
-            st->done = 1;
-        } else if (L == st->L_max) {
-            st->done = 1;
-        } else {
-            ++L;
-            st->V[L] = st->V[L - 1] / Mb;
-            st->E[L] = st->E[L - 1] / Ma;
-            st->C[L] = level_cost_dev(L, M, st->antithetic);
-            st->n[L] = 0;
-            st->sum1[L] = 0;
-            st->sum2[L] = 0;
-            optimal_n_dev(L, st->V, st->C, st->eps, st->Nopt);
-            for (int l = 0; l <= L; ++l) {
-                const double d = st->Nopt[l] - st->n[l];
-                st->dN[l] = (l == L) ? (st->Nopt[l] > 1 ? st->Nopt[l] : 1.0)
-                                     : ((d > 0.01 * st->n[l]) ? d : 0.0);
-            }
-            st->L = L;
-        }
-    }
-    if (st->iterations >= st->max_iterations) st->done = 1;
-    if (st->done) {
-        double est = 0.0, var = 0.0;
-        double absE[kMaxLevels], Vr[kMaxLevels];
-        for (int l = 0; l <= st->L; ++l) {
-            const double m = st->sum1[l] / st->n[l];
-            est += m;
-            const double v = st->sum2[l] / st->n[l] - m * m;
-            var += (v > 0 ? v : 0) / st->n[l];
-            absE[l] = fabs(m);
-            Vr[l] = v;
-        }
-        st->estimate = est;
-        st->var_est = var;
-        st->alpha_fit = -fit_rate_dev(st->L, absE, M);
-        st->beta_fit = -fit_rate_dev(st->L, Vr, M);
-        st->gamma_fit = fit_rate_dev(st->L, st->C, M);
-    }
-}
-
-// The update is a serial chain of a few hundred dependent fp64 operations on
-// the state, so the state is staged in LDS (a global round trip per access
-// would dominate), updated by one lane, and written back.  The same words go
-// to the host's pinned mirror: everything but `seq` first, then a
-// system-scope fence, then `seq`, so a host that sees the new `seq` sees the
-// whole update (the host waits on it instead of a copy and a stream
-// synchronisation).
-__global__ void driver_update_kernel(DriverState* st, DriverState* mirror)
-{
-    static_assert(sizeof(DriverState) % 8 == 0, "state is copied in 8-byte words");
-    static_assert(offsetof(DriverState, seq) % 8 == 0, "seq is one word");
-    constexpr int kWords = sizeof(DriverState) / 8;
-    constexpr int kSeq = offsetof(DriverState, seq) / 8;
-    __shared__ DriverState s;
-    const unsigned long long* src = (const unsigned long long*)st;
-    unsigned long long* w = (unsigned long long*)&s;
-    for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = src[i];
+    static_assert(sizeof(DriverState) % 8 == 0, "state is cleared in 8-byte words");
+    unsigned long long* w = (unsigned long long*)st;
+    for (int i = threadIdx.x; i < (int)(sizeof(DriverState) / 8); i += blockDim.x) w[i] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) {
-        driver_update_dev(&s);
-        s.seq += 1;
+        st->eps = eps;
+        st->alpha = alpha;
+        st->beta = beta;
+        st->M = M;
+        st->antithetic = antithetic;
+        st->L_min = L_min;
+        st->L_max = L_max;
+        st->max_iterations = max_iterations;
+        st->L = L_min;
+        for (int l = 0; l <= L_min; ++l) st->dN[l] = n_pilot;
     }
-    __syncthreads();
-    unsigned long long* dst = (unsigned long long*)st;
-    for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = w[i];
-    if (mirror) {
-        volatile unsigned long long* h = (volatile unsigned long long*)mirror;
-        for (int i = threadIdx.x; i < kWords; i += blockDim.x)
-            if (i != kSeq) h[i] = w[i];
-        __threadfence_system();
-        __syncthreads();
-        if (threadIdx.x == 0) h[kSeq] = w[kSeq];
-    }
+}
+
+__global__ void driver_update_kernel(DriverState* st, DriverState* mirror)
+{
+    __shared__ DriverState s;
+    driver_update_block(st, mirror, s);
 }
 
 // Wait until the host mirror shows update number `want`.  Spinning on the
@@ -273,6 +150,8 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     if (o.n_pilot < 2) return fail(ctx, MLMC_EINVAL, "n_pilot must be >= 2");
     if (o.cv && o.precision != 32)
         return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
+    if (o.persistent != 0 && o.persistent != 1)
+        return fail(ctx, MLMC_EINVAL, "persistent must be 0 or 1");
     if (o.cv && o.persistent)
         return fail(ctx, MLMC_EINVAL, "the control variate runs with per-level launches only");
     if (model->antithetic && o.persistent)
@@ -295,7 +174,12 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     h->max_iterations = 1000;
     h->L = o.L_min;
     for (int l = 0; l <= o.L_min; ++l) h->dN[l] = (double)o.n_pilot;
-    MLMC_HIP(ctx, hipMemcpyAsync(d, h, sizeof(DriverState), hipMemcpyHostToDevice, ctx->stream));
+    // the device copy from the same few values (a launch costs the host less
+    // than a host-to-device copy of the whole state)
+    hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d, h->eps, h->alpha,
+                       h->beta, h->M, h->antithetic, h->L_min, h->L_max, h->max_iterations,
+                       (double)o.n_pilot);
+    MLMC_HIP(ctx, hipGetLastError());
     if (o.persistent) {
         st = run_persistent(ctx, *model, *payoff, o, d, h);
         if (st) return st;

@@ -57,7 +57,8 @@ struct BatchDesc {
 
 // Plan: thread 0 sizes every (slot, level) pair's items and lays the pairs
 // out deepest level first; then the block writes the items in parallel.
-__global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d)
+// Every thread of the block must call it.
+__device__ __forceinline__ void plan_body(const BatchDesc* d)
 {
     constexpr int kPairs = kMaxSlots * kMaxLevels;
     __shared__ uint64_t s_first[kPairs], s_left[kPairs], s_per[kPairs];
@@ -123,8 +124,10 @@ __global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d)
     }
 }
 
+__global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d) { plan_body(d); }
+
 template <int MODEL, int PAYOFF, int M, int PPT>
-__device__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[kNumSums],
+__device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[kNumSums],
                          unsigned& nonfinite)
 {
     LevelArgs<float> a;
@@ -162,8 +165,10 @@ __device__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[k
     }
 }
 
+// Take items from the dispenser until none are left; each item ends with a
+// block reduction into its (payoff, level) record.
 template <int MODEL, int M, int PPT>
-__global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
+__device__ __forceinline__ void sample_items(const BatchDesc* d)
 {
     __shared__ unsigned s_item;
     const unsigned count = *d->count;
@@ -185,6 +190,12 @@ __global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
         }
         block_reduce_add(sums, nonfinite, &d->acc[w.slot * kMaxLevels + w.level]);
     }
+}
+
+template <int MODEL, int M, int PPT>
+__global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
+{
+    sample_items<MODEL, M, PPT>(d);
 }
 
 using PersistentFn = void (*)(const BatchDesc*);

@@ -82,6 +82,19 @@ def test_persistent_run_matches_per_level_run(gctx):
         assert close(a["estimate"], b["estimate"], 1e-10)
 
 
+@pytest.mark.parametrize("kind,scheme,pname", [(0, 1, "asian"), (1, 0, "call"), (0, 0, "lookback")])
+def test_graph_run_variants_match_per_level_run(gctx, kind, scheme, pname):
+    md = dict(W.GBM_MODEL if kind == 0 else W.HESTON_MODEL, scheme=scheme)
+    gm, gp = mlmc.model(**md), mlmc.payoff(**W.PAYOFFS[pname])
+    for eps, M in ((0.1, 4), (0.05, 2)):
+        a = gctx.mlmc_run(gm, gp, eps, M=M, seed=6, persistent=0)
+        b = gctx.mlmc_run(gm, gp, eps, M=M, seed=6, persistent=1)
+        assert a["N"] == b["N"] and a["L"] == b["L"] and a["iterations"] == b["iterations"]
+        assert close(a["estimate"], b["estimate"], 1e-10)
+    with pytest.raises(mlmc.MLMCError):
+        gctx.mlmc_run(gm, gp, 0.1, persistent=2)
+
+
 def test_batch_bad_args(gctx):
     gm = mlmc.model(**W.GBM_MODEL)
     with pytest.raises(mlmc.MLMCError):
