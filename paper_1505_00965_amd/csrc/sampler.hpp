@@ -91,13 +91,16 @@ __device__ __forceinline__ void brownian_pair(uint32_t a, uint32_t b, const Step
     d1 = P.sqh * z1;
 }
 
-// Compensated (Neumaier) accumulation for the Asian average: the sum of up
-// to 65536 terms keeps ~1e-7 relative accuracy in fp32.
+// Compensated (Kahan) accumulation for the Asian average: the path values
+// are positive and of one magnitude, so the running compensation c keeps the
+// sum of up to 65536 terms at ~1e-7 relative accuracy in fp32 (sum - c is
+// the compensated total), in four lane operations per term.
 template <typename Real>
-__device__ __forceinline__ void comp_add(Real& sum, Real& comp, Real y)
+__device__ __forceinline__ void comp_add(Real& sum, Real& comp, Real x)
 {
+    const Real y = x - comp;
     const Real t = sum + y;
-    comp += (fabs(sum) >= fabs(y)) ? ((sum - t) + y) : ((y - t) + sum);
+    comp = (t - sum) - y;
     sum = t;
 }
 
@@ -169,7 +172,7 @@ __device__ __forceinline__ void fine_step(PathPair<Real>& q, const StepParams<Re
         q.S = fmaT(q.S, fmaT(vol, dw1, P.rh), q.S);
         q.v = fmaT(P.xi * vol, dw2, fmaT(P.kappa * P.h, P.theta - vp, q.v));
     }
-    if (PAYOFF == kAsian) comp_add(q.asum, q.acomp, S0n + q.S);
+    if (PAYOFF == kAsian) comp_add(q.asum, q.acomp, q.S);   // sum of S_1 .. S_n
     if (PAYOFF == kDigitalCond) {
         q.Sl = S0n;
         q.vl = vol;
@@ -223,7 +226,7 @@ __device__ __forceinline__ void coarse_step(PathPair<Real>& q, const StepParams<
         q.vcl = volc;
         q.wcl = q.dw1c;
     }
-    if (PAYOFF == kAsian) comp_add(q.csum, q.ccomp, S0c + q.Sc);
+    if (PAYOFF == kAsian) comp_add(q.csum, q.ccomp, q.Sc);
     q.dw1c = 0;
     q.dwpc = 0;
     q.wpart = 0;
@@ -239,7 +242,9 @@ __device__ __forceinline__ Real payoff_value(const StepParams<Real>& P, Real S, 
     } else if (PAYOFF == kDigital) {
         v = S > P.K ? P.disc * P.payout : (S == P.K ? P.disc * Real(0.5) * P.payout : Real(0));
     } else if (PAYOFF == kAsian) {
-        const Real A = (sum + comp) * (dt * Real(0.5)) * P.inv_T;
+        // trapezoid over the grid: dt (S_0/2 + S_1 + ... + S_{N-1} + S_N/2)
+        //   = dt (sum_{n=1..N} S_n + (S_0 - S_N)/2)
+        const Real A = fmaT(Real(0.5), P.S0 - S, sum - comp) * dt * P.inv_T;
         v = P.disc * fmaxT<Real>(A - P.K, Real(0));
     } else {
         v = P.disc * (S - mn);   // floating-strike lookback
