@@ -122,9 +122,7 @@ __global__ void cv_phi0_kernel(CvKernelArgs c, float S0, float v0, float* out)
     __shared__ NetShared sh;
     load_shared<D>(sh, c.params, c.nc);
     __syncthreads();
-    bf16x8 a[2][4];
-    load_afwd(c.afwd, a);
-    const float phi = phi_eval<D>(sh, a, 0.0f, S0, v0);
+    const float phi = phi_eval<D>(sh, c.afwd, 0.0f, S0, v0);
     if (threadIdx.x == 0) *out = phi;
 }
 
@@ -186,16 +184,20 @@ __device__ __forceinline__ void fetch_group(const LevelArgs<float>& a, uint64_t 
 }
 
 // One sample per lane; every lane runs every network evaluation (samples
-// past the range are simulated and dropped), so waves stay converged.
+// past the range are simulated and dropped), so waves stay converged.  Two
+// blocks per compute unit (two waves per SIMD): with the network constants
+// and W2 operands read from LDS per evaluation the kernel fits 256 registers
+// per lane without spilling, and the second wave hides the matrix-core and
+// transcendental latencies of the first.
 template <int MODEL, int PAYOFF, int M>
-__global__ __launch_bounds__(256) void cv_level_kernel(LevelArgs<float> a, CvKernelArgs c)
+__global__ __launch_bounds__(256, 2) void cv_level_kernel(LevelArgs<float> a, CvKernelArgs c)
 {
     constexpr int D = (MODEL == kGBM) ? 2 : 3;
     __shared__ NetShared sh;
+    __shared__ bf16x8 s_afwd[8 * 64];   // W2 operands, read at every evaluation
     load_shared<D>(sh, c.params, c.nc);
+    for (int i = threadIdx.x; i < 8 * 64; i += blockDim.x) s_afwd[i] = c.afwd[i];
     __syncthreads();
-    bf16x8 A[2][4];
-    load_afwd(c.afwd, A);
     const StepParams<float>& P = a.P;
     const bool coupled = a.coupled && a.l > 0;
     double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
@@ -219,9 +221,9 @@ __global__ __launch_bounds__(256) void cv_level_kernel(LevelArgs<float> a, CvKer
                 const float dp = k == 0 ? dwp[0] : k == 1 ? dwp[1] : k == 2 ? dwp[2] : dwp[3];
                 const float ek = k == 0 ? e[0] : k == 1 ? e[1] : k == 2 ? e[2] : e[3];
                 const float x0 = (float)n * P.h * sh.inv_T;
-                const float phif = phi_eval<D>(sh, A, x0, q.S, q.v);
+                const float phif = phi_eval<D>(sh, s_afwd, x0, q.S, q.v);
                 q.cvf = __builtin_fmaf(phif, d1, q.cvf);
-                if (coupled && (n & (M - 1)) == 0) phic = phi_eval<D>(sh, A, x0, q.Sc, q.vc);
+                if (coupled && (n & (M - 1)) == 0) phic = phi_eval<D>(sh, s_afwd, x0, q.Sc, q.vc);
                 fine_step<float, MODEL, PAYOFF>(q, P, d1, dp, ek, n & (M - 1), coupled);
                 if (coupled && ((n + 1) & (M - 1)) == 0) {
                     q.cvc = __builtin_fmaf(phic, q.dw1c, q.cvc);

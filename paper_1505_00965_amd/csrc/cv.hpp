@@ -172,25 +172,43 @@ __device__ __forceinline__ void pair_inputs(const NetShared& sh, float S, float 
 }
 
 // phi(t, X) of this lane's sample; every lane of the wave must call it.
+// afwd: the bf16 W2 operands in lane order (in LDS in the sampler).  Layer 2
+// and layer 3 run one 32-row tile at a time, so only half of the matrix
+// accumulators are live.
 template <int D>
-__device__ __forceinline__ float phi_eval(const NetShared& sh, const bf16x8 (&a)[2][4], float x0,
+__device__ __forceinline__ float phi_eval(const NetShared& sh, const bf16x8* afwd, float x0,
                                           float S, float v)
 {
-    const int h = (threadIdx.x & 63) >> 5;
+    // The network constants are read from LDS at every evaluation: kept in
+    // registers across the path loop they would take ~190 VGPRs and leave a
+    // single wave per SIMD.  The empty asm (a compiler-only memory clobber,
+    // no instruction) stops the loads from being hoisted out of the loop.
+    __asm__ volatile("" ::: "memory");
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5;
     float x1[2], x2[2];
     pair_inputs<D>(sh, S, v, x1, x2);
     bf16x8 b[2][4];
     layer1<D, false>(sh, x0, x1, x2, b, nullptr);
-    f32x16 acc[2][2];
-    layer2(sh, a, b, acc);
     float part[2] = {0.0f, 0.0f};
 #pragma unroll
-    for (int jt = 0; jt < 2; ++jt)
+    for (int jt = 0; jt < 2; ++jt) {
+        bf16x8 a[4];
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
+        for (int kb = 0; kb < 4; ++kb) a[kb] = afwd[(jt * 4 + kb) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = sh.b2[row_d(h, jt, r)];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], b[nt][kb], acc, 0, 0, 0);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                part[nt] = __builtin_fmaf(sh.w3[row_d(h, jt, r)], tanh_fast(acc[jt][nt][r]), part[nt]);
+                part[nt] = __builtin_fmaf(sh.w3[row_d(h, jt, r)], tanh_fast(acc[r]), part[nt]);
+        }
+    }
     const float send = h == 0 ? part[1] : part[0];
     const float recv = __shfl_xor(send, 32);
     const float mine = h == 0 ? part[0] : part[1];
