@@ -151,7 +151,7 @@ static float time_shape(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p
     for (int rep = 0; rep < 4 && !*st; ++rep) {
         hipEventRecord(a, ctx->stream);
         *st = enqueue_level(ctx, m, p, l, M, N, 12345, 0, precision, kStreamNormal, 1, ctx->d_acc,
-                            nullptr, nullptr, nullptr);
+                            nullptr, nullptr, nullptr, true);
         hipEventRecord(b, ctx->stream);
         if (hipEventSynchronize(b) != hipSuccess) *st = MLMC_EDEVICE;
         float ms = 0.f;

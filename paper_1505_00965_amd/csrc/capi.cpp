@@ -94,6 +94,7 @@ LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_pa
     const uint64_t chunks = (units + chunk - 1) / chunk;
     const uint64_t cap = (uint64_t)ctx->num_cu * (2048 / s.block);
     s.grid = (int)std::max<uint64_t>(1, std::min(chunks, cap));
+    s.num_cu = ctx->num_cu;
     (void)p;
     return s;
 }
@@ -136,6 +137,7 @@ static LevelArgs<Real> make_args(const mlmc_model& m, const mlmc_payoff& p, int 
     a.phi0 = nullptr;
     return a;
 }
+
 
 static hipEvent_t pool_event(mlmc_ctx* ctx)
 {
@@ -206,8 +208,10 @@ void harvest_timing(mlmc_ctx* ctx)
 
 mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
                           uint64_t N, uint64_t seed, uint64_t offset, int precision, uint32_t stream,
-                          int coupled, LevelAcc* acc, double* d_pf, double* d_pc, const mlmc_cv* cv)
+                          int coupled, LevelAcc* acc, double* d_pf, double* d_pc, const mlmc_cv* cv,
+                          bool spread)
 {
+    const uint32_t mask = spread ? (uint32_t)(kSpread - 1) : 0u;
     if (N == 0) return MLMC_OK;
     if (cv) {
         if (precision != 32) return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
@@ -219,6 +223,7 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
             return fail(ctx, MLMC_EINVAL, "network inputs do not match the model (2: GBM, 3: Heston)");
         const double nf = (double)level_steps(l, M);
         auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
+        a.spread_mask = mask;
         hipError_t e;
         if (l == 0) {
             // one step from (0, S0): phi is the single value phi(0, S0)
@@ -248,9 +253,11 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
     hipError_t e;
     if (precision == 64) {
         auto a = make_args<double>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
+        a.spread_mask = mask;
         e = launch_level(m, p, M, 64, &a, shape, ctx->stream, t0, t1);
     } else {
         auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
+        a.spread_mask = mask;
         e = launch_level(m, p, M, 32, &a, shape, ctx->stream, t0, t1);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "level kernel launch");
@@ -260,11 +267,11 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
 static mlmc_status finish_level(mlmc_ctx* ctx, const mlmc_model& m, uint64_t N, int l, int M,
                                 int coupled, mlmc_level_result* out)
 {
-    MLMC_HIP(ctx, hipMemcpyAsync(ctx->h_acc, ctx->d_acc, sizeof(LevelAcc), hipMemcpyDeviceToHost,
-                                 ctx->stream));
+    MLMC_HIP(ctx, hipMemcpyAsync(ctx->h_acc, ctx->d_acc, sizeof(LevelAcc) * kSpread,
+                                 hipMemcpyDeviceToHost, ctx->stream));
     MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     harvest_timing(ctx);
-    const LevelAcc& r = ctx->h_acc[0];
+    const LevelAcc r = fold_records(ctx->h_acc, kSpread);
     if (out) {
         out->sum_y = r.sum[0];
         out->sum_y2 = r.sum[1];
@@ -343,6 +350,9 @@ mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx)
 mlmc_status mlmc_set_stream(mlmc_ctx* ctx, void* hip_stream)
 {
     if (!ctx) return MLMC_EINVAL;
+    // launches on the old stream must end before the new stream's start:
+    // they share the context's buffers
+    if (ctx->stream) MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->stream = hip_stream ? (hipStream_t)hip_stream : ctx->own_stream;
     return MLMC_OK;
 }
@@ -402,9 +412,9 @@ static mlmc_status level_common(mlmc_ctx* ctx, const mlmc_model* model, const ml
     if ((path_offset + N) >> 56) return fail(ctx, MLMC_EINVAL, "path index beyond 2^56");
     ctx->err.clear();
     MLMC_HIP(ctx, hipSetDevice(ctx->device));
-    MLMC_HIP(ctx, zero_records(ctx->d_acc, 1, ctx->stream));
+    MLMC_HIP(ctx, zero_records(ctx->d_acc, kSpread, ctx->stream));
     st = enqueue_level(ctx, *model, *payoff, l, M, N, seed, path_offset, precision, stream, coupled,
-                       ctx->d_acc, d_pf, d_pc, cv);
+                       ctx->d_acc, d_pf, d_pc, cv, true);
     if (st) return st;
     return finish_level(ctx, *model, N, l, M, coupled, out);
 }

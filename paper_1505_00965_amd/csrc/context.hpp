@@ -25,6 +25,8 @@ struct mlmc_ctx {
     void* d_drv = nullptr;
     void* h_drv = nullptr;        // pinned host mirror of the driver state
     void* h_drv_dev = nullptr;    // the same memory as the device sees it
+    // spread groups of the per-level launches, one per level (driver.hip)
+    mlmc::LevelAcc* d_drv_spread = nullptr;
     double* d_tmp = nullptr;                // small fp64 scratch (optimal_n)
     double* h_tmp = nullptr;
     // kernel timing (mlmc_set_timing)
@@ -43,7 +45,10 @@ struct mlmc_ctx {
 
 namespace mlmc {
 
-constexpr int kAccSlots = 64;
+// Level records: 16 spread groups (a call's level, or every level of a
+// randomised single-term estimate); also the training records and the host
+// copy of a persistent batch.
+constexpr int kAccSlots = 16 * mlmc::kSpread;
 
 // Record an error message and return the status.
 mlmc_status fail(mlmc_ctx* ctx, mlmc_status st, const std::string& msg);
@@ -63,11 +68,12 @@ mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payo
 // Launch shape for N samples at level l (honours mlmc_set_launch).
 LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
                          int M, int precision, uint64_t N);
-// Enqueue one level into record `acc` (no zeroing, no sync).
+// Enqueue one level into record `acc`, or with `spread` into the spread
+// group of kSpread records at `acc` (no zeroing, no sync).
 mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
                           uint64_t N, uint64_t seed, uint64_t offset, int precision, uint32_t stream,
                           int coupled, LevelAcc* acc, double* d_pf, double* d_pc,
-                          const mlmc_cv* cv);
+                          const mlmc_cv* cv, bool spread = false);
 // Zero `n` records with a fill kernel (safe inside graph capture).
 hipError_t zero_records(LevelAcc* acc, int n, hipStream_t st);
 

@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256, 2) void cv_level_kernel(LevelArgs<float> a, Cv
                              : 0.0f;
         if (idx < a.N) accumulate(a, idx, pf, pc, sums, nonfinite);
     }
-    block_reduce_add(sums, nonfinite, a.acc);
+    block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
 }
 
 // ------------------------------------------------------------ training

@@ -20,14 +20,18 @@ __global__ void optimal_n_kernel(int L, const double* V, const double* C, double
 }
 
 // A fresh state: zeros, the configuration, n_pilot outstanding samples on
-// levels 0..L_min (the host mirror is filled the same way on the host).
-__global__ void driver_init_kernel(DriverState* st, double eps, double alpha, double beta, int M,
-                                   int antithetic, int L_min, int L_max, int max_iterations,
-                                   double n_pilot)
+// levels 0..L_min (the host mirror is filled the same way on the host); the
+// per-level spread groups cleared.
+__global__ void driver_init_kernel(DriverState* st, LevelAcc* spread, double eps, double alpha,
+                                   double beta, int M, int antithetic, int L_min, int L_max,
+                                   int max_iterations, double n_pilot)
 {
     static_assert(sizeof(DriverState) % 8 == 0, "state is cleared in 8-byte words");
     unsigned long long* w = (unsigned long long*)st;
     for (int i = threadIdx.x; i < (int)(sizeof(DriverState) / 8); i += blockDim.x) w[i] = 0ull;
+    unsigned long long* g = (unsigned long long*)spread;
+    constexpr int kSpreadWords = kMaxLevels * kSpread * (int)sizeof(LevelAcc) / 8;
+    for (int i = threadIdx.x; i < kSpreadWords; i += blockDim.x) g[i] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) {
         st->eps = eps;
@@ -43,10 +47,10 @@ __global__ void driver_init_kernel(DriverState* st, double eps, double alpha, do
     }
 }
 
-__global__ void driver_update_kernel(DriverState* st, DriverState* mirror)
+__global__ void driver_update_kernel(DriverState* st, DriverState* mirror, LevelAcc* spread)
 {
     __shared__ DriverState s;
-    driver_update_block(st, mirror, s);
+    driver_update_block(st, mirror, s, spread);
 }
 
 // Wait until the host mirror shows update number `want`.  Spinning on the
@@ -75,9 +79,10 @@ hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long l
     }
 }
 
-hipError_t launch_driver_update(DriverState* st, DriverState* mirror, hipStream_t stream)
+hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* spread,
+                                hipStream_t stream)
 {
-    hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror);
+    hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror, spread);
     return hipGetLastError();
 }
 
@@ -85,6 +90,7 @@ static mlmc_status ensure_driver(mlmc_ctx* ctx)
 {
     if (ctx->d_drv) return MLMC_OK;
     MLMC_HIP(ctx, hipMalloc(&ctx->d_drv, sizeof(DriverState)));
+    MLMC_HIP(ctx, hipMalloc(&ctx->d_drv_spread, sizeof(LevelAcc) * kMaxLevels * kSpread));
     MLMC_HIP(ctx, hipHostMalloc(&ctx->h_drv, sizeof(DriverState)));
     MLMC_HIP(ctx, hipHostGetDevicePointer(&ctx->h_drv_dev, ctx->h_drv, 0));
     return MLMC_OK;
@@ -104,6 +110,8 @@ mlmc_status mlmc_driver_free(mlmc_ctx* ctx)
 {
     if (!ctx) return MLMC_OK;
     if (ctx->d_drv) hipFree(ctx->d_drv);
+    if (ctx->d_drv_spread) hipFree(ctx->d_drv_spread);
+    ctx->d_drv_spread = nullptr;
     if (ctx->h_drv) hipHostFree(ctx->h_drv);
     ctx->d_drv = ctx->h_drv = ctx->h_drv_dev = nullptr;
     return MLMC_OK;
@@ -176,7 +184,8 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     for (int l = 0; l <= o.L_min; ++l) h->dN[l] = (double)o.n_pilot;
     // the device copy from the same few values (a launch costs the host less
     // than a host-to-device copy of the whole state)
-    hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d, h->eps, h->alpha,
+    hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d,
+                       ctx->d_drv_spread, h->eps, h->alpha,
                        h->beta, h->M, h->antithetic, h->L_min, h->L_max, h->max_iterations,
                        (double)o.n_pilot);
     MLMC_HIP(ctx, hipGetLastError());
@@ -193,12 +202,13 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
                 if (h->dN[l] <= 0) continue;
                 const mlmc_cv* cv = (o.cv && (o.cv_levels <= 0 || l < o.cv_levels)) ? o.cv : nullptr;
                 st = enqueue_level(ctx, *model, *payoff, l, o.M, (uint64_t)h->dN[l], o.seed,
-                                   (uint64_t)h->n[l], o.precision, kStreamNormal, 1, &d->batch[l],
-                                   nullptr, nullptr, cv);
+                                   (uint64_t)h->n[l], o.precision, kStreamNormal, 1,
+                                   ctx->d_drv_spread + l * kSpread, nullptr, nullptr, cv, true);
                 if (st) return st;
             }
             const int tix = timed_begin(ctx, 17, 0.0, 0.0);
-            MLMC_HIP(ctx, launch_driver_update(d, (DriverState*)ctx->h_drv_dev, ctx->stream));
+            MLMC_HIP(ctx, launch_driver_update(d, (DriverState*)ctx->h_drv_dev, ctx->d_drv_spread,
+                                               ctx->stream));
             timed_end(ctx, tix);
             MLMC_HIP(ctx, wait_update(ctx->stream, h, (unsigned long long)it + 1));
             if (h->done) break;

@@ -134,9 +134,12 @@ __device__ __forceinline__ void driver_update_dev(DriverState* st)
 // would dominate), updated by one lane, and written back.  The same words go
 // to the host's pinned mirror (if any): everything but `seq` first, then a
 // system-scope fence, then `seq`, so a host that sees the new `seq` sees the
-// whole update.  Every thread of the block must call it; `s` is the block's
-// LDS copy of the state.
-__device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s)
+// whole update.  With `spread` (kMaxLevels spread groups, one per level) the
+// block first folds each sampled level's group into batch[l], one wave per
+// level, and clears it.  Every thread of the block must call it; `s` is the
+// block's LDS copy of the state.
+__device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s,
+                                                    LevelAcc* spread)
 {
     static_assert(sizeof(DriverState) % 8 == 0, "state is copied in 8-byte words");
     static_assert(offsetof(DriverState, seq) % 8 == 0, "seq is one word");
@@ -146,6 +149,27 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
     unsigned long long* w = (unsigned long long*)&s;
     for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = src[i];
     __syncthreads();
+    if (spread) {
+        static_assert(kSpread == 64, "one lane per record of a group");
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int nwaves = (int)(blockDim.x >> 6);
+        for (int l = wave; l <= s.L; l += nwaves) {    // wave-uniform
+            LevelAcc& r = spread[l * kSpread + lane];
+            double v[kNumSums];
+#pragma unroll
+            for (int k = 0; k < kNumSums; ++k) v[k] = wave_sum(r.sum[k]);
+            const double c = wave_sum((double)r.n_nonfinite);
+#pragma unroll
+            for (int k = 0; k < kNumSums; ++k) r.sum[k] = 0.0;
+            r.n_nonfinite = 0;
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < kNumSums; ++k) s.batch[l].sum[k] += v[k];
+                s.batch[l].n_nonfinite += (unsigned long long)c;
+            }
+        }
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         driver_update_dev(&s);
         s.seq += 1;

@@ -1,6 +1,9 @@
 // Level-sampler launcher: parameter block, dispatch to the per-variant
 // kernel tables, and the generator probes.
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include <hip/hip_ext.h>
 
@@ -69,19 +72,51 @@ static KernelFn<Real> pick(const mlmc_model& m, int payoff, int M, int ppt, int 
     }
 }
 
+// Blocks of `fn` with `block` threads that one compute unit holds at once
+// (its register count decides), cached per kernel and block size; 0 if the
+// runtime cannot say.
+static int resident_blocks(const void* fn, int block)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(fn, block);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        n = 0;
+    }
+    cache[key] = n;
+    return n;
+}
+
+static dim3 resident_grid(const void* fn, const LaunchShape& shape)
+{
+    int g = shape.grid;
+    if (shape.num_cu > 0) {
+        const int per_cu = resident_blocks(fn, shape.block);
+        if (per_cu > 0 && g > shape.num_cu * per_cu) g = shape.num_cu * per_cu;
+    }
+    return dim3(g);
+}
+
 hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int precision,
                         const void* args, LaunchShape shape, hipStream_t stream, hipEvent_t start,
                         hipEvent_t stop)
 {
-    dim3 grid(shape.grid), block(shape.block);
+    dim3 block(shape.block);
     if (precision == 64) {
         const auto& a = *(const LevelArgs<double>*)args;
         auto fn = pick<double>(m, p.kind, M, 1, a.nf);
-        hipExtLaunchKernelGGL(fn, grid, block, 0, stream, start, stop, 0, a);
+        hipExtLaunchKernelGGL(fn, resident_grid((const void*)fn, shape), block, 0, stream, start,
+                              stop, 0, a);
     } else {
         const auto& a = *(const LevelArgs<float>*)args;
         auto fn = pick<float>(m, p.kind, M, shape.ppt, a.nf);
-        hipExtLaunchKernelGGL(fn, grid, block, 0, stream, start, stop, 0, a);
+        hipExtLaunchKernelGGL(fn, resident_grid((const void*)fn, shape), block, 0, stream, start,
+                              stop, 0, a);
     }
     return hipGetLastError();
 }

@@ -20,7 +20,8 @@ struct LevelArgs {
     int nf;               // fine steps M^l
     uint32_t ngroups;     // ceil(nf / 4): groups of four fine steps
     uint32_t stream;      // Philox stream of the Brownian normals
-    LevelAcc* acc;        // (payoff, level) record receiving the sums
+    LevelAcc* acc;        // (payoff, level) record or spread group receiving the sums
+    uint32_t spread_mask = 0;   // block b adds into acc[b & mask]: 0, or kSpread - 1
     double* pf_out;       // optional per-path dump (fp64), else null
     double* pc_out;
     int coupled;          // 0: standard MC (fine path only at level l)
@@ -35,9 +36,13 @@ StepParams<Real> make_step_params(const mlmc_model& m, const mlmc_payoff& p, int
 // or kHeston.
 int sampler_variant(const mlmc_model& m);
 
-// Launch shape actually used.
+// Launch shape actually used.  `grid` is an upper bound: the launcher lowers
+// it to the number of blocks the device holds at once for the chosen kernel
+// (num_cu compute units, 0 = no cap), so that no block waits for another to
+// finish and the grid-stride loop gives every resident block the same share.
 struct LaunchShape {
     int block, ppt, grid;
+    int num_cu = 0;
 };
 
 // Enqueue one level's sampler on `stream` (accumulating into args.acc).

@@ -218,7 +218,8 @@ static PersistentFn pick_persistent(int variant, int M, int ppt)
     return M == 2 ? pick_ppt<kHeston, 2>(ppt) : pick_ppt<kHeston, 4>(ppt);
 }
 
-hipError_t launch_driver_update(DriverState* st, DriverState* mirror, hipStream_t stream);
+hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* spread,
+                                hipStream_t stream);
 hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long long want);
 
 // Device buffers of the persistent form, owned by the context.
@@ -334,7 +335,7 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
         e = hipGetLastError();
     }
     if (e == hipSuccess && driver)
-        e = launch_driver_update(driver, (DriverState*)ctx->h_drv_dev, cs);
+        e = launch_driver_update(driver, (DriverState*)ctx->h_drv_dev, nullptr, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);

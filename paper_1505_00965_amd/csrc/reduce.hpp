@@ -6,6 +6,13 @@
 // two 32-bit halves of each double, then a cross-row exchange; the block's
 // waves combine through LDS, and one lane per quantity issues a hardware
 // global_atomic_add_f64 into the (payoff, level) record.
+//
+// Adds from thousands of blocks to one cache line serialise at a few ns each,
+// which costs more than the sampling itself for launches of up to a few
+// million samples.  A level launch therefore writes into a spread group of
+// kSpread records: block b adds into record b mod kSpread, and the group's
+// value is the sum of its records (fold_records; the driver folds on the
+// device).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -20,6 +27,19 @@ struct LevelAcc {
     unsigned long long n_nonfinite;
     unsigned long long pad;
 };
+
+constexpr int kSpread = 64;   // records per spread group (one 64-byte line each)
+
+// Sum of n records, in index order.
+__host__ __device__ inline LevelAcc fold_records(const LevelAcc* g, int n)
+{
+    LevelAcc r = {};
+    for (int j = 0; j < n; ++j) {
+        for (int k = 0; k < kNumSums; ++k) r.sum[k] += g[j].sum[k];
+        r.n_nonfinite += g[j].n_nonfinite;
+    }
+    return r;
+}
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)

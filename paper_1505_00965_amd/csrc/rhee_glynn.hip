@@ -103,21 +103,23 @@ mlmc_status mlmc_rhee_glynn(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_p
     MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     std::memcpy(out->N, ctx->h_tmp, kRgLevels * sizeof(unsigned long long));
     // every drawn level on the ordinary sampler, one record per level
-    MLMC_HIP(ctx, zero_records(ctx->d_acc, kRgLevels, ctx->stream));
+    static_assert(kRgLevels * kSpread <= kAccSlots, "one spread group per level");
+    MLMC_HIP(ctx, zero_records(ctx->d_acc, kRgLevels * kSpread, ctx->stream));
     for (int l = 0; l <= L_cap; ++l) {
         if (!out->N[l]) continue;
         st = enqueue_level(ctx, *model, *payoff, l, M, out->N[l], seed, 0, precision,
-                           kStreamNormal, 1, ctx->d_acc + l, nullptr, nullptr, nullptr);
+                           kStreamNormal, 1, ctx->d_acc + l * kSpread, nullptr, nullptr, nullptr,
+                           true);
         if (st) return st;
     }
-    MLMC_HIP(ctx, hipMemcpyAsync(ctx->h_acc, ctx->d_acc, kRgLevels * sizeof(LevelAcc),
+    MLMC_HIP(ctx, hipMemcpyAsync(ctx->h_acc, ctx->d_acc, kRgLevels * kSpread * sizeof(LevelAcc),
                                  hipMemcpyDeviceToHost, ctx->stream));
     MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     harvest_timing(ctx);
     double z1 = 0.0, z2 = 0.0;
     for (int l = 0; l <= L_cap; ++l) {
         if (!out->N[l]) continue;
-        const LevelAcc& r = ctx->h_acc[l];
+        const LevelAcc r = fold_records(ctx->h_acc + l * kSpread, kSpread);
         out->sum_y[l] = r.sum[0];
         out->sum_y2[l] = r.sum[1];
         out->n_nonfinite += r.n_nonfinite;
