@@ -255,7 +255,16 @@ def main():
 
     for i in range(args.warmup):
         step(1 + i % max(args.steps, 1))   # same seeds, hence launch sizes, as timed steps
+    # Which kernel dominates: every slot timed over the same steps, untimed
+    # by the clock.  The timed region then stamps only that kernel's launches
+    # (each stamped launch adds a few microseconds of queue time).
     ctx.set_timing(True)
+    for i in range(args.steps):
+        step(1 + i)
+    survey = ctx.kernel_stats()
+    ctx.set_timing(False)
+    dom = mlmc.STAT_PERSISTENT if args.persistent else max(range(16), key=lambda l: survey[l]["ms"])
+    ctx.set_timing_slots([dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = [step(1 + i) for i in range(args.steps)]
@@ -284,7 +293,7 @@ def main():
                         "launches": s["launches"]}
     else:
         # dominant kernel: the level whose launches took the most time
-        lv = max(range(16), key=lambda l: stats[l]["ms"])
+        lv = dom
         s = stats[lv]
         if s["launches"]:
             avg_ms = s["ms"] / s["launches"]

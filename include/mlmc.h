@@ -137,8 +137,14 @@ typedef struct {
     double ms;              /* summed event-measured duration */
     double fine_steps, coarse_steps;
 } mlmc_kernel_stat;
-/* on != 0: start recording (clears the statistics); 0: stop. */
+/* on != 0: start recording every slot (clears the statistics); 0: stop. */
 mlmc_status mlmc_set_timing(mlmc_ctx* ctx, int on);
+/* Record only the slots whose bit is set in slot_mask (bit s = slot s; 0
+ * stops, a non-zero mask clears the statistics).  Each timed launch carries
+ * two events, a few microseconds of queue time, so a caller that wants one
+ * kernel's duration without slowing the rest times that slot alone.
+ * MLMC_EINVAL for bits at or above MLMC_STAT_SLOTS.                          */
+mlmc_status mlmc_set_timing_mask(mlmc_ctx* ctx, uint32_t slot_mask);
 /* Copy MLMC_STAT_SLOTS statistics into out (host array). */
 mlmc_status mlmc_kernel_stats(mlmc_ctx* ctx, mlmc_kernel_stat* out);
 

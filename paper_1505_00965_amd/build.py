@@ -1,7 +1,8 @@
 """Build libmlmc.so (HIP, gfx950) in-tree with hipcc.
 
 Every source is compiled as HIP for gfx950 only, with hardware fp64 atomics
-(-munsafe-fp-atomics) and packed-fp32 instruction selection disabled.
+(-munsafe-fp-atomics), contraction into fused multiply-adds only within an
+expression (-ffp-contract=on) and packed-fp32 instruction selection disabled.
 """
 import concurrent.futures as cf
 import os
@@ -26,6 +27,10 @@ def hipcc():
 
 
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-munsafe-fp-atomics",
+          # fused multiply-adds only where the source writes them (or within one
+          # expression): kernels compiled in different translation units then
+          # round a sample identically, whatever code surrounds it
+          "-ffp-contract=on",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
 

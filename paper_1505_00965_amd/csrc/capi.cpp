@@ -153,7 +153,7 @@ static hipEvent_t pool_event(mlmc_ctx* ctx)
 
 int timed_begin(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_steps)
 {
-    if (!ctx->timing) return -1;
+    if (!(ctx->timing >> slot & 1u)) return -1;
     mlmc_ctx::Timed t;
     t.start = pool_event(ctx);
     t.stop = pool_event(ctx);
@@ -170,7 +170,7 @@ void timed_kernel(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_step
                   hipEvent_t* start, hipEvent_t* stop)
 {
     *start = *stop = nullptr;
-    if (!ctx->timing) return;
+    if (!(ctx->timing >> slot & 1u)) return;
     mlmc_ctx::Timed t;
     t.start = pool_event(ctx);
     t.stop = pool_event(ctx);
@@ -206,13 +206,14 @@ void harvest_timing(mlmc_ctx* ctx)
     ctx->pending.clear();
 }
 
-mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
-                          uint64_t N, uint64_t seed, uint64_t offset, int precision, uint32_t stream,
-                          int coupled, LevelAcc* acc, double* d_pf, double* d_pc, const mlmc_cv* cv,
-                          bool spread)
+// One launch over a range whose generator units share their counter word 2.
+static mlmc_status enqueue_segment(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
+                                   int M, uint64_t N, uint64_t seed, uint64_t offset, int precision,
+                                   uint32_t stream, int coupled, LevelAcc* acc, double* d_pf,
+                                   double* d_pc, const mlmc_cv* cv, bool spread)
 {
     const uint32_t mask = spread ? (uint32_t)(kSpread - 1) : 0u;
-    if (N == 0) return MLMC_OK;
+    const int dim = m.kind == MLMC_HESTON ? 2 : 1;
     if (cv) {
         if (precision != 32) return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
         if (m.scheme != MLMC_EULER || m.antithetic)
@@ -224,6 +225,7 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
         const double nf = (double)level_steps(l, M);
         auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
         a.spread_mask = mask;
+        set_counter_words(a, dim);
         hipError_t e;
         if (l == 0) {
             // one step from (0, S0): phi is the single value phi(0, S0)
@@ -254,13 +256,35 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
     if (precision == 64) {
         auto a = make_args<double>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
         a.spread_mask = mask;
+        set_counter_words(a, dim);
         e = launch_level(m, p, M, 64, &a, shape, ctx->stream, t0, t1);
     } else {
         auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
         a.spread_mask = mask;
+        set_counter_words(a, dim);
         e = launch_level(m, p, M, 32, &a, shape, ctx->stream, t0, t1);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "level kernel launch");
+    return MLMC_OK;
+}
+
+mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
+                          uint64_t N, uint64_t seed, uint64_t offset, int precision, uint32_t stream,
+                          int coupled, LevelAcc* acc, double* d_pf, double* d_pc, const mlmc_cv* cv,
+                          bool spread)
+{
+    const uint64_t q = samples_per_unit(level_steps(l, M), m.kind == MLMC_HESTON ? 2 : 1);
+    const uint64_t end = offset + N;
+    for (uint64_t first = offset; first < end;) {
+        const uint64_t stop = counter_segment_end(first, end, q);
+        const uint64_t skip = first - offset;
+        const mlmc_status st =
+            enqueue_segment(ctx, m, p, l, M, stop - first, seed, first, precision, stream, coupled,
+                            acc, d_pf ? d_pf + skip : nullptr, d_pc ? d_pc + skip : nullptr, cv,
+                            spread);
+        if (st) return st;
+        first = stop;
+    }
     return MLMC_OK;
 }
 
@@ -362,15 +386,22 @@ const char* mlmc_last_error(const mlmc_ctx* ctx)
     return ctx ? ctx->err.c_str() : "null context";
 }
 
-mlmc_status mlmc_set_timing(mlmc_ctx* ctx, int on)
+mlmc_status mlmc_set_timing_mask(mlmc_ctx* ctx, uint32_t slot_mask)
 {
     if (!ctx) return MLMC_EINVAL;
-    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    if (slot_mask >> MLMC_STAT_SLOTS)
+        return fail(ctx, MLMC_EINVAL, "slot mask has bits beyond the statistics slots");
+    if (ctx->stream) MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     harvest_timing(ctx);
-    ctx->timing = on ? 1 : 0;
-    if (on)
+    ctx->timing = slot_mask;
+    if (slot_mask)
         for (auto& s : ctx->stats) s = mlmc_kernel_stat{};
     return MLMC_OK;
+}
+
+mlmc_status mlmc_set_timing(mlmc_ctx* ctx, int on)
+{
+    return mlmc_set_timing_mask(ctx, on ? (1u << MLMC_STAT_SLOTS) - 1u : 0u);
 }
 
 mlmc_status mlmc_kernel_stats(mlmc_ctx* ctx, mlmc_kernel_stat* out)

@@ -35,7 +35,7 @@ struct mlmc_ctx {
         int slot;
         double fine_steps, coarse_steps;
     };
-    int timing = 0;
+    uint32_t timing = 0;                    // bit s: time launches of slot s
     std::vector<hipEvent_t> event_pool;
     std::vector<Timed> pending;
     mlmc_kernel_stat stats[MLMC_STAT_SLOTS] = {};

@@ -26,7 +26,46 @@ struct LevelArgs {
     double* pc_out;
     int coupled;          // 0: standard MC (fine path only at level l)
     const float* phi0;    // level 0 with the control variate: phi(0, S0), else null
+    uint32_t c2 = 0;      // Philox counter word 2 of every Brownian block of the launch
+    uint32_t c2b = 0;     // and of every bridge block (set_counter_words)
 };
+
+// Philox counter word 2 of generator unit u (a block index on one- and
+// two-step levels, a sample index otherwise) at level l: l + 256 (u >> 32),
+// the same word make_path_key forms.
+__host__ __device__ inline uint32_t counter_word2(int l, uint64_t u)
+{
+    return (uint32_t)l + 256u * (uint32_t)(u >> 32);
+}
+
+// Samples per Brownian generator unit: one- and two-step levels share Philox
+// blocks (4 / (n_f d) samples each), longer paths own theirs.
+__host__ __device__ inline uint64_t samples_per_unit(int nf, int d)
+{
+    return nf < 4 ? (uint64_t)(4 / (nf * d)) : 1u;
+}
+
+// End of the leading part of the sample range [first, end) whose generator
+// units (q samples each) share one high word.  A launch covers one such part,
+// so counter word 2 is a launch constant; ranges that cross a multiple of
+// q 2^32 are split into several launches.
+__host__ __device__ inline uint64_t counter_segment_end(uint64_t first, uint64_t end, uint64_t q)
+{
+    const uint64_t next_unit = ((first / q >> 32) + 1) << 32;
+    const uint64_t lim = next_unit * q;
+    return lim < end ? lim : end;
+}
+
+// Counter words of a launch whose range [offset, offset + N) is one segment;
+// d = Brownian dimension.  Bridge blocks of one- and two-step levels are
+// numbered by generator block / d, of longer paths by sample.
+template <typename Real>
+__host__ __device__ inline void set_counter_words(LevelArgs<Real>& a, int d)
+{
+    const uint64_t u = a.offset / samples_per_unit(a.nf, d);
+    a.c2 = counter_word2(a.l, u);
+    a.c2b = counter_word2(a.l, a.nf < 4 ? u / (uint64_t)d : u);
+}
 
 // Host-side conversion of model/payoff to the kernel's parameter block.
 template <typename Real>

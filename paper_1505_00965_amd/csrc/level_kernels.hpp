@@ -41,6 +41,7 @@ __global__ __launch_bounds__(1024) void short_level_kernel(LevelArgs<Real> a)
     const uint64_t nchunks = (nblk + chunk - 1) / chunk;
     for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x)
         process_short<MODEL, PAYOFF, Real, NF, M, PPT, ANTI>(a, c * chunk, sums, nonfinite);
+    if (NF == 1) copy_y_sums(sums);
     block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
 }
 

@@ -126,6 +126,31 @@ __device__ __forceinline__ void plan_body(const BatchDesc* d)
 
 __global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d) { plan_body(d); }
 
+// The samples [a.offset, a.offset + a.N) of one item part (a.c2, a.c2b set).
+template <int MODEL, int PAYOFF, int M, int PPT>
+__device__ __forceinline__ void run_range(const LevelArgs<float>& a, double (&sums)[kNumSums],
+                                          unsigned& nonfinite)
+{
+    if (a.nf < 4) {
+        // one or two steps: samples share generator blocks
+        constexpr int D = one_factor(MODEL) ? 1 : 2;
+        const int q = 4 / (a.nf * D);
+        const uint64_t nblk = short_blocks(a.offset, a.N, q);
+        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
+        for (uint64_t base = 0; base < nblk; base += chunk) {
+            if (a.nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT, false>(a, base, sums, nonfinite);
+            else process_short<MODEL, PAYOFF, float, 2, M, PPT, false>(a, base, sums, nonfinite);
+        }
+    } else if (a.N <= blockDim.x) {
+        // fewer samples than lanes: one per lane
+        process_chunk<MODEL, PAYOFF, float, M, 1, false>(a, 0, sums, nonfinite);
+    } else {
+        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
+        for (uint64_t base = 0; base < a.N; base += chunk)
+            process_chunk<MODEL, PAYOFF, float, M, PPT, false>(a, base, sums, nonfinite);
+    }
+}
+
 template <int MODEL, int PAYOFF, int M, int PPT>
 __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[kNumSums],
                          unsigned& nonfinite)
@@ -133,8 +158,6 @@ __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, 
     LevelArgs<float> a;
     a.P = d->params[w.slot][w.level];
     a.seed = d->seed;
-    a.offset = w.first;
-    a.N = w.n;
     a.l = w.level;
     int nf = 1;
     for (int i = 0; i < a.l; ++i) nf *= M;
@@ -145,23 +168,16 @@ __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, 
     a.pf_out = a.pc_out = nullptr;
     a.coupled = 1;
     a.phi0 = nullptr;
-    if (nf < 4) {
-        // one or two steps: samples share generator blocks
-        constexpr int D = one_factor(MODEL) ? 1 : 2;
-        const int q = 4 / (nf * D);
-        const uint64_t nblk = short_blocks(w.first, w.n, q);
-        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
-        for (uint64_t base = 0; base < nblk; base += chunk) {
-            if (nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT, false>(a, base, sums, nonfinite);
-            else process_short<MODEL, PAYOFF, float, 2, M, PPT, false>(a, base, sums, nonfinite);
-        }
-    } else if (w.n <= blockDim.x) {
-        // fewer samples than lanes: one per lane
-        process_chunk<MODEL, PAYOFF, float, M, 1, false>(a, 0, sums, nonfinite);
-    } else {
-        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
-        for (uint64_t base = 0; base < w.n; base += chunk)
-            process_chunk<MODEL, PAYOFF, float, M, PPT, false>(a, base, sums, nonfinite);
+    constexpr int D = one_factor(MODEL) ? 1 : 2;
+    // one pass per part of the item whose generator units share counter word 2
+    const uint64_t q = samples_per_unit(nf, D), end = w.first + w.n;
+    for (uint64_t first = w.first; first < end;) {
+        const uint64_t stop = counter_segment_end(first, end, q);
+        a.offset = first;
+        a.N = stop - first;
+        set_counter_words(a, D);
+        run_range<MODEL, PAYOFF, M, PPT>(a, sums, nonfinite);
+        first = stop;
     }
 }
 
@@ -188,6 +204,7 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d)
         case kDigitalCond: run_item<MODEL, kDigitalCond, M, PPT>(d, w, sums, nonfinite); break;
         default: run_item<MODEL, kDigital, M, PPT>(d, w, sums, nonfinite); break;
         }
+        if (w.level == 0) copy_y_sums(sums);
         block_reduce_add(sums, nonfinite, &d->acc[w.slot * kMaxLevels + w.level]);
     }
 }

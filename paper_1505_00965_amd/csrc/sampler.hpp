@@ -236,22 +236,27 @@ template <typename Real, int PAYOFF>
 __device__ __forceinline__ Real payoff_value(const StepParams<Real>& P, Real S, Real sum,
                                              Real comp, Real mn, Real dt)
 {
-    Real v;
+    // a path that overflowed stays visible as a non-finite payoff: S - S is
+    // +0 for finite S and NaN otherwise (one lane operation, no branch); the
+    // discount multiplies in the same fused operation
+    const Real nan_if_overflow = S - S;
+    if (PAYOFF == kDigital) {
+        const Real v = S > P.K ? P.disc * P.payout
+                               : (S == P.K ? P.disc * Real(0.5) * P.payout : Real(0));
+        return v + nan_if_overflow;
+    }
+    Real u;
     if (PAYOFF == kCall) {
-        v = P.disc * fmaxT<Real>(S - P.K, Real(0));
-    } else if (PAYOFF == kDigital) {
-        v = S > P.K ? P.disc * P.payout : (S == P.K ? P.disc * Real(0.5) * P.payout : Real(0));
+        u = fmaxT<Real>(S - P.K, Real(0));
     } else if (PAYOFF == kAsian) {
         // trapezoid over the grid: dt (S_0/2 + S_1 + ... + S_{N-1} + S_N/2)
         //   = dt (sum_{n=1..N} S_n + (S_0 - S_N)/2)
-        const Real A = fmaT(Real(0.5), P.S0 - S, sum - comp) * dt * P.inv_T;
-        v = P.disc * fmaxT<Real>(A - P.K, Real(0));
+        const Real tw = fmaT(Real(0.5), P.S0 - S, sum - comp);
+        u = fmaxT<Real>(fmaT(tw, dt * P.inv_T, -P.K), Real(0));   // A - K
     } else {
-        v = P.disc * (S - mn);   // floating-strike lookback
+        u = S - mn;   // floating-strike lookback
     }
-    // a path that overflowed stays visible as a non-finite payoff: S - S is
-    // +0 for finite S and NaN otherwise (two lane operations, no branch)
-    return v + (S - S);
+    return fmaT(P.disc, u, nan_if_overflow);
 }
 
 // Standard normal distribution function, erfc(-z / sqrt 2) / 2.

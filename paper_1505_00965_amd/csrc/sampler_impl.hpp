@@ -23,6 +23,25 @@ __device__ __forceinline__ void add_sample(Real pf, Real pc, double (&sums)[kNum
     sums[5] = __builtin_fma(dc, dc, sums[5]);
 }
 
+// One-step samples have no coarse payoff, so y = P_f: only the sums of y are
+// kept per lane, and the P_f sums are copied from them once per block
+// (copy_y_sums) before the reduction.
+__device__ __forceinline__ void add_y(double y, double (&sums)[kNumSums], unsigned& nonfinite)
+{
+    if (!isfinite(y)) {
+        ++nonfinite;
+        return;
+    }
+    sums[0] += y;
+    sums[1] = __builtin_fma(y, y, sums[1]);
+}
+
+__device__ __forceinline__ void copy_y_sums(double (&sums)[kNumSums])
+{
+    sums[2] = sums[0];
+    sums[3] = sums[1];
+}
+
 // add_sample plus the optional per-sample dump.
 template <typename Real>
 __device__ __forceinline__ void accumulate(const LevelArgs<Real>& a, uint64_t idx, Real pf, Real pc,
@@ -60,8 +79,9 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
     PathKey key[PPT], bkey[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        key[p] = make_path_key(a.seed, a.l, s[p], a.stream);
-        bkey[p] = make_path_key(a.seed, a.l, s[p], a.stream + 1u);
+        key[p] = PathKey{(uint32_t)a.seed, (uint32_t)(a.seed >> 32), (uint32_t)s[p], a.c2, a.stream};
+        bkey[p] = PathKey{(uint32_t)a.seed, (uint32_t)(a.seed >> 32), (uint32_t)s[p], a.c2b,
+                          a.stream + 1u};
         init_pair<Real, MODEL, PAYOFF>(q[p], P);
         if (ANTI) init_pair<Real, MODEL, PAYOFF>(qa[p], P);
     }
@@ -145,6 +165,8 @@ __device__ __forceinline__ void pair_payoffs(const StepParams<Real>& P, const Pa
 
 // Samples base + p * blockDim + threadIdx (p < PPT) of the range described
 // by a (a.offset + index, index < a.N): simulate, then add into the lane sums.
+// a.c2 and a.c2b are the counter words of the whole range (set_counter_words):
+// the range lies within one segment of counter_segment_end.
 template <int MODEL, int PAYOFF, typename Real, int M, int PPT, bool ANTI>
 __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t base,
                                               double (&sums)[kNumSums], unsigned& nonfinite)
@@ -181,7 +203,7 @@ __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t
 // fp64 sum of squares is finite (y^2 of an fp32 value cannot overflow fp64,
 // so that sum is finite exactly when every y is); otherwise the chunk is
 // added sample by sample with the range and finiteness checks.  y = P_f
-// there, so the sums of P_f repeat those of y and the P_c sums stay zero.
+// there: the P_f sums are left to copy_y_sums and the P_c sums stay zero.
 template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT, bool ANTI>
 __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t blk_base,
                                               double (&sums)[kNumSums], unsigned& nonfinite)
@@ -199,14 +221,16 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         B[p] = B0 + blk_base + (uint64_t)p * blockDim.x + threadIdx.x;
-        const u32x4 w = path_block(make_path_key(a.seed, a.l, B[p], a.stream), 0);
+        const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+        const u32x4 w = path_block(PathKey{k0, k1, (uint32_t)B[p], a.c2, a.stream}, 0);
         Real dw[4];
         brownian_pair(w.x, w.y, P, dw[0], dw[1]);
         brownian_pair(w.z, w.w, P, dw[2], dw[3]);
         Real e[4] = {Real(0), Real(0), Real(0), Real(0)};
         if (PAYOFF == kLookback) {
             // every sample of this generator block reads bridge block B / D
-            const u32x4 u = path_block(make_path_key(a.seed, a.l, B[p] / D, a.stream + 1u), 0);
+            const u32x4 u =
+                path_block(PathKey{k0, k1, (uint32_t)(B[p] / D), a.c2b, a.stream + 1u}, 0);
             e[0] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.x));
             e[1] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.y));
             e[2] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.z));
@@ -280,8 +304,6 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
         if (inside && isfinite(cy2)) {
             sums[0] += cy;
             sums[1] += cy2;
-            sums[2] += cy;
-            sums[3] += cy2;
             return;
         }
     }
@@ -291,7 +313,8 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
         for (int r = 0; r < Q; ++r) {
             const uint64_t s = B[p] * Q + r;
             if (s < a.offset || s - a.offset >= a.N) continue;
-            add_sample(pf[p][r], pc[p][r], sums, nonfinite);
+            if (NF == 1) add_y((double)pf[p][r], sums, nonfinite);
+            else add_sample(pf[p][r], pc[p][r], sums, nonfinite);
         }
 }
 

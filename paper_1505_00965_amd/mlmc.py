@@ -24,7 +24,7 @@ EXPORTED = [
     "mlmc_levels_batch", "mlmc_set_persistent_launch",
     "mlmc_cv_create", "mlmc_cv_destroy", "mlmc_cv_nparams", "mlmc_cv_get_params",
     "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train", "mlmc_autotune",
-    "mlmc_tuned_shape", "mlmc_rhee_glynn",
+    "mlmc_tuned_shape", "mlmc_rhee_glynn", "mlmc_set_timing_mask",
 ]
 STAT_SLOTS = 20
 STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
@@ -147,6 +147,7 @@ def lib():
     L.mlmc_autotune.argtypes = [vp, M_, P_, i32, i32, C.c_char_p]
     L.mlmc_tuned_shape.argtypes = [vp, M_, P_, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.mlmc_set_timing.argtypes = [vp, i32]
+    L.mlmc_set_timing_mask.argtypes = [vp, u32]
     L.mlmc_kernel_stats.argtypes = [vp, C.POINTER(KernelStat)]
     for name in EXPORTED:
         if name != "mlmc_last_error":
@@ -218,6 +219,13 @@ class Context:
 
     def set_timing(self, on=True):
         self._check(self._lib.mlmc_set_timing(self.h, int(on)))
+
+    def set_timing_slots(self, slots):
+        """Time only the given statistics slots (levels 0..15, STAT_*)."""
+        mask = 0
+        for s in slots:
+            mask |= 1 << int(s)
+        self._check(self._lib.mlmc_set_timing_mask(self.h, mask))
 
     def kernel_stats(self):
         """Per-slot {launches, ms, fine_steps, coarse_steps} (slots 0..15 = level)."""

@@ -77,3 +77,24 @@ def test_notconv_and_bad_args(gctx):
         with pytest.raises(mlmc.MLMCError) as e:
             gctx.mlmc_run(gm, gp, eps, **kw)
         assert e.value.status == mlmc.MLMC_EINVAL
+
+
+def test_timing_mask_records_only_its_slots(gctx):
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    gctx.set_timing_slots([0, mlmc.STAT_DRIVER])
+    r = gctx.mlmc_run(gm, gp, 0.05, M=4, seed=2)
+    st = gctx.kernel_stats()
+    gctx.set_timing(False)
+    assert st[0]["launches"] >= 1 and st[0]["ms"] > 0
+    assert st[0]["fine_steps"] == sum(r["N"][:1])          # level 0: one step per sample
+    assert st[mlmc.STAT_DRIVER]["launches"] == r["iterations"]
+    assert all(st[l]["launches"] == 0 for l in range(1, 16))
+    with pytest.raises(mlmc.MLMCError) as e:
+        gctx._check(gctx._lib.mlmc_set_timing_mask(gctx.h, 1 << mlmc.STAT_SLOTS))
+    assert e.value.status == mlmc.MLMC_EINVAL
+    # all slots again, then off
+    gctx.set_timing(True)
+    gctx.mlmc_run(gm, gp, 0.05, M=4, seed=2)
+    st = gctx.kernel_stats()
+    gctx.set_timing(False)
+    assert all(st[l]["launches"] >= 1 for l in range(r["L"] + 1))

@@ -186,3 +186,30 @@ def test_user_stream(gctx):
     gctx.set_stream(None)
     b = gctx.mlmc_level(gm, gp, 2, 4, 5000, 1, precision=64)
     assert abs(a["sum_y"] - b["sum_y"]) <= 1e-12 * abs(b["sum_y"])
+
+
+# (kind, M, l, samples per generator unit): one- and two-step levels share
+# Philox blocks, so their counter high word turns over at q 2^32 samples.
+BOUNDARY_CASES = [(0, 4, 0, 4), (0, 2, 0, 4), (0, 2, 1, 2), (1, 4, 0, 2), (1, 2, 1, 1),
+                  (0, 4, 1, 1), (1, 4, 2, 1)]
+
+
+@pytest.mark.parametrize("kind,M,l,q", BOUNDARY_CASES)
+@pytest.mark.parametrize("pname", ["call", "lookback"])
+def test_ranges_across_the_counter_high_word(gctx, orc, kind, M, l, q, pname):
+    """A range whose generator units cross a multiple of 2^32 is sampled in
+    two launches (counter word 2 is a launch constant); paths must still be
+    the oracle's on both sides of the boundary."""
+    gm, om = models(orc, kind)
+    gp, op = pays(orc, pname)
+    N = 3000
+    for offset in (q * (1 << 32) - 1001, q * (1 << 32) - 1, 3 * q * (1 << 32) - 2999):
+        print(f"case kind={kind} payoff={pname} M={M} l={l} off={offset}", flush=True)
+        pf, pc, res = gpu_paths(gctx, gm, gp, l, M, N, 5, offset, 32)
+        rf, rc = orc.level_paths(om, op, l, M, N, 5, offset, nthreads=8)
+        err = max(np.abs(pf - rf).max(), np.abs(pc - rc).max())
+        assert err <= 1e-4 * S0, (offset, err)
+        y = pf - pc
+        assert abs(res["sum_y"] - y.sum()) <= 1e-12 * max(1.0, np.abs(y).sum())
+        assert abs(res["sum_pf"] - pf.sum()) <= 1e-12 * max(1.0, np.abs(pf).sum())
+        assert res["n"] == N and res["n_nonfinite"] == 0

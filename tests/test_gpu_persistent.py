@@ -101,3 +101,25 @@ def test_batch_bad_args(gctx):
         gctx.mlmc_levels_batch(gm, [mlmc.payoff(**W.CALL)] * 5, 4, 2, [[10] * 3] * 5, 1)
     with pytest.raises(mlmc.MLMCError):
         gctx.mlmc_levels_batch(gm, [mlmc.payoff(**W.CALL)], 3, 2, [[10] * 3], 1)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_batch_items_across_the_counter_high_word(gctx, kind):
+    """Items whose generator units cross a multiple of 2^32 run in two parts;
+    the sums must equal the per-level launches' (which split the same way)."""
+    md = W.GBM_MODEL if kind == 0 else W.HESTON_MODEL
+    gm = mlmc.model(**md)
+    pays = [mlmc.payoff(**W.PAYOFFS[n]) for n in ("call", "asian", "lookback", "digital")]
+    L, M = 3, 4
+    q0 = 4 if kind == 0 else 2           # samples per generator unit at level 0
+    N = [[5000 + 300 * k + 11 * l for l in range(L + 1)] for k in range(4)]
+    offs = [[(q0 if l == 0 else 1) * (1 << 32) - 2000 - 7 * k for l in range(L + 1)]
+            for k in range(4)]
+    got = gctx.mlmc_levels_batch(gm, pays, M, L, N, seed=4, offsets=offs)
+    for k, p in enumerate(pays):
+        for l in range(L + 1):
+            ref = gctx.mlmc_level(gm, p, l, M, N[k][l], 4, path_offset=offs[k][l])
+            g = got[k][l]
+            assert g["n"] == N[k][l]
+            for key in ("sum_y", "sum_y2", "sum_pf", "sum_pc"):
+                assert close(g[key], ref[key]), (k, l, key, g[key], ref[key])
