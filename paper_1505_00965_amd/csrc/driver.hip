@@ -4,8 +4,8 @@
 
 #include <atomic>
 #include <chrono>
-#include <cstddef>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 
 #include "context.hpp"
@@ -23,8 +23,8 @@ __global__ void optimal_n_kernel(int L, const double* V, const double* C, double
 // levels 0..L_min (the host mirror is filled the same way on the host); the
 // per-level spread groups cleared.
 __global__ void driver_init_kernel(DriverState* st, LevelAcc* spread, double eps, double alpha,
-                                   double beta, int M, int antithetic, int L_min, int L_max,
-                                   int max_iterations, double n_pilot)
+                                   double beta, double Ma, double Mb, int M, int antithetic,
+                                   int L_min, int L_max, int max_iterations, double n_pilot)
 {
     static_assert(sizeof(DriverState) % 8 == 0, "state is cleared in 8-byte words");
     unsigned long long* w = (unsigned long long*)st;
@@ -37,6 +37,8 @@ __global__ void driver_init_kernel(DriverState* st, LevelAcc* spread, double eps
         st->eps = eps;
         st->alpha = alpha;
         st->beta = beta;
+        st->Ma = Ma;
+        st->Mb = Mb;
         st->M = M;
         st->antithetic = antithetic;
         st->L_min = L_min;
@@ -80,9 +82,11 @@ hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long l
 }
 
 hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* spread,
-                                hipStream_t stream)
+                                hipStream_t stream, hipEvent_t start, hipEvent_t stop)
 {
+    if (start) hipEventRecord(start, stream);
     hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror, spread);
+    if (stop) hipEventRecord(stop, stream);
     return hipGetLastError();
 }
 
@@ -175,6 +179,8 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     h->eps = o.eps;
     h->alpha = o.alpha > 0 ? o.alpha : 1.0;
     h->beta = o.beta > 0 ? o.beta : 1.0;
+    h->Ma = std::pow((double)o.M, h->alpha);
+    h->Mb = std::pow((double)o.M, h->beta);
     h->M = o.M;
     h->antithetic = model->antithetic;
     h->L_min = o.L_min;
@@ -186,7 +192,7 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     // than a host-to-device copy of the whole state)
     hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d,
                        ctx->d_drv_spread, h->eps, h->alpha,
-                       h->beta, h->M, h->antithetic, h->L_min, h->L_max, h->max_iterations,
+                       h->beta, h->Ma, h->Mb, h->M, h->antithetic, h->L_min, h->L_max, h->max_iterations,
                        (double)o.n_pilot);
     MLMC_HIP(ctx, hipGetLastError());
     if (o.persistent) {
@@ -206,10 +212,10 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
                                    ctx->d_drv_spread + l * kSpread, nullptr, nullptr, cv, true);
                 if (st) return st;
             }
-            const int tix = timed_begin(ctx, 17, 0.0, 0.0);
+            hipEvent_t t0, t1;
+            timed_kernel(ctx, 17, 0.0, 0.0, &t0, &t1);
             MLMC_HIP(ctx, launch_driver_update(d, (DriverState*)ctx->h_drv_dev, ctx->d_drv_spread,
-                                               ctx->stream));
-            timed_end(ctx, tix);
+                                               ctx->stream, t0, t1));
             MLMC_HIP(ctx, wait_update(ctx->stream, h, (unsigned long long)it + 1));
             if (h->done) break;
         }

@@ -17,6 +17,7 @@ constexpr int kMaxLevels = 16;
 struct DriverState {
     // configuration
     double eps, alpha, beta;
+    double Ma, Mb;                 // M^alpha, M^beta (computed once by the host)
     int M, L_min, L_max, max_iterations;
     int antithetic, pad_cfg;       // the twin doubles the fine steps of l >= 1
     // progress

@@ -39,9 +39,10 @@ __device__ inline double fit_rate_dev(int L, const double* y, int M)
 {
     double sx = 0, sy = 0, sxx = 0, sxy = 0;
     int n = 0;
+    const double lm = log((double)M);
     for (int l = 1; l <= L; ++l) {
         if (!(y[l] > 0)) continue;
-        const double x = l, v = log(y[l]) / log((double)M);
+        const double x = l, v = log(y[l]) / lm;
         sx += x; sy += v; sxx += x * x; sxy += x * v; ++n;
     }
     if (n < 2) return nan("");
@@ -52,7 +53,7 @@ __device__ inline double fit_rate_dev(int L, const double* y, int M)
 __device__ __forceinline__ void driver_update_dev(DriverState* st)
 {
     const int M = st->M;
-    const double Ma = pow((double)M, st->alpha), Mb = pow((double)M, st->beta);
+    const double Ma = st->Ma, Mb = st->Mb;
     int L = st->L;
     for (int l = 0; l <= L; ++l) {
         if (st->dN[l] > 0) {
@@ -175,8 +176,8 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
         s.seq += 1;
     }
     __syncthreads();
-    unsigned long long* dst = (unsigned long long*)st;
-    for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = w[i];
+    // the host waits for the mirror: publish it first; the device copy is
+    // read by the next update only, which the stream orders after this one
     if (mirror) {
         volatile unsigned long long* h = (volatile unsigned long long*)mirror;
         for (int i = threadIdx.x; i < kWords; i += blockDim.x)
@@ -185,6 +186,8 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
         __syncthreads();
         if (threadIdx.x == 0) h[kSeq] = w[kSeq];
     }
+    unsigned long long* dst = (unsigned long long*)st;
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = w[i];
 }
 
 }  // namespace mlmc

@@ -98,3 +98,23 @@ def test_timing_mask_records_only_its_slots(gctx):
     st = gctx.kernel_stats()
     gctx.set_timing(False)
     assert all(st[l]["launches"] >= 1 for l in range(r["L"] + 1))
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_timed_runs_give_the_untimed_results(gctx, persistent):
+    """Kernel timing changes only how launches are stamped: the estimates,
+    N_l and level sums of a timed run are the untimed run's."""
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    runs = []
+    for mode in ("off", "all", "level0"):
+        if mode == "all":
+            gctx.set_timing(True)
+        elif mode == "level0":
+            gctx.set_timing_slots([0])
+        rs = [gctx.mlmc_run(gm, gp, 0.01, M=4, seed=s, persistent=persistent) for s in (3, 4)]
+        gctx.set_timing(False)
+        runs.append(rs)
+    for rs in runs[1:]:
+        for a, b in zip(runs[0], rs):
+            assert a["N"] == b["N"] and a["L"] == b["L"]
+            assert abs(a["estimate"] - b["estimate"]) <= 1e-12 * abs(a["estimate"])
