@@ -130,6 +130,7 @@ static bool write_cache(const std::string& path,
 bool tuned_shape(const mlmc_ctx* ctx, int model, int payoff, int precision, int M, int l,
                  int* block, int* ppt)
 {
+    if (ctx->tuned.empty()) return false;   // every launch asks: skip the key when nothing is tuned
     auto it = ctx->tuned.find(tune_key(model, payoff, precision, M, level_class(l, M)));
     if (it == ctx->tuned.end() || it->second.size() < 2) return false;
     *block = it->second[0];

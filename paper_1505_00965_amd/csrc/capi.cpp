@@ -81,10 +81,6 @@ LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_pa
         // few samples: fewer paths per thread so that more lanes take part
         const uint64_t lanes = (N + s.ppt - 1) / s.ppt;
         if (lanes < (uint64_t)ctx->num_cu * 256) s.ppt = 1;
-        // long one-step launches: the one-block-per-lane kernel holds 8 waves
-        // per SIMD against 6 for two blocks per lane, which pays once every
-        // lane has many chunks to do (measured crossover 2e6..4.6e7 samples)
-        if (!ctx->launch_ppt && level_steps(l, M) == 1 && N >= (1ull << 24)) s.ppt = 1;
     }
     const int nf = level_steps(l, M);
     uint64_t units = N;   // samples, or generator blocks for one/two-step levels

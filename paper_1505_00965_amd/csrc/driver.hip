@@ -1,5 +1,6 @@
 // Adaptive MLMC driver: the fp64 update kernel and the host loops (the
 // arithmetic itself is in driver_dev.hpp).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -84,9 +85,11 @@ hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long l
 hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* spread,
                                 hipStream_t stream, hipEvent_t start, hipEvent_t stop)
 {
-    if (start) hipEventRecord(start, stream);
-    hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror, spread);
-    if (stop) hipEventRecord(stop, stream);
+    if (start || stop)
+        hipExtLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, start, stop, 0, st,
+                              mirror, spread);
+    else
+        hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror, spread);
     return hipGetLastError();
 }
 

@@ -136,8 +136,8 @@ __device__ __forceinline__ void driver_update_dev(DriverState* st)
 // to the host's pinned mirror (if any): everything but `seq` first, then a
 // system-scope fence, then `seq`, so a host that sees the new `seq` sees the
 // whole update.  With `spread` (kMaxLevels spread groups, one per level) the
-// block first folds each sampled level's group into batch[l], one wave per
-// level, and clears it.  Every thread of the block must call it; `s` is the
+// block first folds each sampled level's group into batch[l] (the sums of Y
+// and Y^2 and the non-finite count), one wave per level, and clears it.  Every thread of the block must call it; `s` is the
 // block's LDS copy of the state.
 __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s,
                                                     LevelAcc* spread)
@@ -154,18 +154,18 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
         static_assert(kSpread == 64, "one lane per record of a group");
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int nwaves = (int)(blockDim.x >> 6);
+        // the update reads sum Y, sum Y^2 and the non-finite count only
         for (int l = wave; l <= s.L; l += nwaves) {    // wave-uniform
             LevelAcc& r = spread[l * kSpread + lane];
-            double v[kNumSums];
-#pragma unroll
-            for (int k = 0; k < kNumSums; ++k) v[k] = wave_sum(r.sum[k]);
+            const double y = wave_sum(r.sum[0]);
+            const double y2 = wave_sum(r.sum[1]);
             const double c = wave_sum((double)r.n_nonfinite);
 #pragma unroll
             for (int k = 0; k < kNumSums; ++k) r.sum[k] = 0.0;
             r.n_nonfinite = 0;
             if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < kNumSums; ++k) s.batch[l].sum[k] += v[k];
+                s.batch[l].sum[0] += y;
+                s.batch[l].sum[1] += y2;
                 s.batch[l].n_nonfinite += (unsigned long long)c;
             }
         }

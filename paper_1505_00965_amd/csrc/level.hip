@@ -5,6 +5,7 @@
 #include <mutex>
 #include <utility>
 
+#include <hip/hip_ext.h>
 
 #include "level_kernels.hpp"
 
@@ -109,15 +110,13 @@ hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int pr
     if (precision == 64) {
         const auto& a = *(const LevelArgs<double>*)args;
         auto fn = pick<double>(m, p.kind, M, 1, a.nf);
-        if (start) hipEventRecord(start, stream);
-        hipLaunchKernelGGL(fn, resident_grid((const void*)fn, shape), block, 0, stream, a);
-        if (stop) hipEventRecord(stop, stream);
+        hipExtLaunchKernelGGL(fn, resident_grid((const void*)fn, shape), block, 0, stream, start,
+                              stop, 0, a);
     } else {
         const auto& a = *(const LevelArgs<float>*)args;
         auto fn = pick<float>(m, p.kind, M, shape.ppt, a.nf);
-        if (start) hipEventRecord(start, stream);
-        hipLaunchKernelGGL(fn, resident_grid((const void*)fn, shape), block, 0, stream, a);
-        if (stop) hipEventRecord(stop, stream);
+        hipExtLaunchKernelGGL(fn, resident_grid((const void*)fn, shape), block, 0, stream, start,
+                              stop, 0, a);
     }
     return hipGetLastError();
 }

@@ -86,11 +86,11 @@ struct LaunchShape {
 
 // Enqueue one level's sampler on `stream` (accumulating into args.acc).
 // Returns hipSuccess or the launch error.  Shape chosen by the caller.  With
-// start/stop events they are recorded on the stream right before and after
-// the launch.  (Kernel-stamped events, hipExtLaunchKernelGGL, time the kernel
-// alone but cost ~15 us of queue time per launch when only some launches
-// carry them, against ~6 us for two recorded events, which read ~1.5 us more
-// than the kernel itself.)
+// start/stop events the runtime stamps them when the kernel itself starts and
+// ends (hipExtLaunchKernelGGL), so they time the kernel, not the queue: they
+// agree with the profiler's kernel durations, where events recorded around
+// the launch read ~7% more.  A stamped launch costs ~15 us of queue time
+// when only some launches carry stamps.
 hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int precision,
                         const void* args, LaunchShape shape, hipStream_t stream,
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);

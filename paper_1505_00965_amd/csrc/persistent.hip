@@ -137,9 +137,13 @@ __device__ __forceinline__ void run_range(const LevelArgs<float>& a, double (&su
         const int q = 4 / (a.nf * D);
         const uint64_t nblk = short_blocks(a.offset, a.N, q);
         const uint64_t chunk = (uint64_t)blockDim.x * PPT;
-        for (uint64_t base = 0; base < nblk; base += chunk) {
-            if (a.nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT, false>(a, base, sums, nonfinite);
-            else process_short<MODEL, PAYOFF, float, 2, M, PPT, false>(a, base, sums, nonfinite);
+        const FullChunks f = full_chunks(a.offset, a.N, q, chunk);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(f.lo), hi = __builtin_amdgcn_readfirstlane(f.hi);
+        uint32_t c = 0;
+        for (uint64_t base = 0; base < nblk; base += chunk, ++c) {
+            const bool full = c >= lo && c < hi;
+            if (a.nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT, false>(a, base, full, sums, nonfinite);
+            else process_short<MODEL, PAYOFF, float, 2, M, PPT, false>(a, base, full, sums, nonfinite);
         }
     } else if (a.N <= blockDim.x) {
         // fewer samples than lanes: one per lane

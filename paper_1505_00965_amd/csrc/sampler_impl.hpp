@@ -199,13 +199,14 @@ __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t
 // Level 0 (NF = 1, no coarse path) is the busiest launch of an adaptive run
 // and costs ~25 lane operations per sample, so its bookkeeping is per lane
 // chunk rather than per sample: the chunk's sums of y and y^2 go into the
-// lane sums at once when every sample of the chunk lies in the range and the
-// fp64 sum of squares is finite (y^2 of an fp32 value cannot overflow fp64,
+// lane sums at once when every sample of the block's chunk lies in the range
+// (`full`, a block-uniform flag from full_chunks) and the fp64 sum of squares
+// is finite (y^2 of an fp32 value cannot overflow fp64,
 // so that sum is finite exactly when every y is); otherwise the chunk is
 // added sample by sample with the range and finiteness checks.  y = P_f
 // there: the P_f sums are left to copy_y_sums and the P_c sums stay zero.
 template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT, bool ANTI>
-__device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t blk_base,
+__device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t blk_base, bool full,
                                               double (&sums)[kNumSums], unsigned& nonfinite)
 {
     static_assert(!ANTI || (NF == 2 && M == 2), "the twin exists on coupled levels only");
@@ -299,9 +300,7 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
                 cy += y;
                 cy2 = __builtin_fma(y, y, cy2);
             }
-        const uint64_t first = B[0] * Q, last = B[PPT - 1] * Q + (Q - 1);
-        const bool inside = first >= a.offset && last - a.offset < a.N;
-        if (inside && isfinite(cy2)) {
+        if (full && isfinite(cy2)) {
             sums[0] += cy;
             sums[1] += cy2;
             return;
@@ -316,6 +315,24 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
             if (NF == 1) add_y((double)pf[p][r], sums, nonfinite);
             else add_sample(pf[p][r], pc[p][r], sums, nonfinite);
         }
+}
+
+// Chunks of `chunk` generator blocks (q samples each) of the range
+// [offset, offset + N) whose samples all lie in the range: [lo, hi), counted
+// from the chunk of block offset / q.  A launch covers generator units that
+// share one counter high word, so chunk indices fit 32 bits and the test is
+// two scalar compares.
+struct FullChunks {
+    uint32_t lo, hi;
+};
+__host__ __device__ inline FullChunks full_chunks(uint64_t offset, uint64_t N, int q, uint64_t chunk)
+{
+    const uint64_t b0 = offset / (uint64_t)q;
+    const uint64_t bend = (offset + N) / (uint64_t)q;   // blocks wholly before the end
+    FullChunks f;
+    f.lo = b0 * (uint64_t)q == offset ? 0u : 1u;
+    f.hi = (uint32_t)((bend - b0) / chunk);
+    return f;
 }
 
 // Number of generator blocks a short level's range [offset, offset + N) touches.
