@@ -66,8 +66,15 @@ double level_cost(const mlmc_model& m, int l, int M)
     return (m.antithetic ? 2.0 : 1.0) * nf + nf / M;
 }
 
+// Split paths (process_split) exist for fp32 GBM paths (Euler or Milstein)
+// of the four plain payoffs without the antithetic twin.
+static bool split_eligible(const mlmc_model& m, const mlmc_payoff& p, int precision)
+{
+    return precision == 32 && m.kind == MLMC_GBM && !m.antithetic && p.kind != MLMC_DIGITAL_COND;
+}
+
 LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
-                         int M, int precision, uint64_t N)
+                         int M, int precision, uint64_t N, uint64_t n_call)
 {
     LaunchShape s;
     s.block = ctx->launch_block ? ctx->launch_block : 256;
@@ -90,7 +97,13 @@ LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_pa
         if (s.ppt > 2) s.ppt = 2;
     }
     if (m.antithetic && l > 0 && s.ppt > 2) s.ppt = 2;   // the twin doubles the path state
-    const uint64_t chunk = (uint64_t)s.block * s.ppt;
+    // GBM levels whose paths cannot fill the device: several lanes per path
+    s.split = split_lanes(nf, n_call ? n_call : N, ctx->num_cu, split_eligible(m, p, precision));
+    if (s.split > 1) {
+        s.ppt = 1;
+        units = N;   // paths, block / split per block at a time
+    }
+    const uint64_t chunk = s.split > 1 ? (uint64_t)s.block / s.split : (uint64_t)s.block * s.ppt;
     const uint64_t chunks = (units + chunk - 1) / chunk;
     const uint64_t cap = (uint64_t)ctx->num_cu * (2048 / s.block);
     s.grid = (int)std::max<uint64_t>(1, std::min(chunks, cap));
@@ -210,7 +223,7 @@ void harvest_timing(mlmc_ctx* ctx)
 static mlmc_status enqueue_segment(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
                                    int M, uint64_t N, uint64_t seed, uint64_t offset, int precision,
                                    uint32_t stream, int coupled, LevelAcc* acc, double* d_pf,
-                                   double* d_pc, const mlmc_cv* cv, bool spread)
+                                   double* d_pc, const mlmc_cv* cv, bool spread, uint64_t n_call)
 {
     const uint32_t mask = spread ? (uint32_t)(kSpread - 1) : 0u;
     const int dim = m.kind == MLMC_HESTON ? 2 : 1;
@@ -246,7 +259,7 @@ static mlmc_status enqueue_segment(mlmc_ctx* ctx, const mlmc_model& m, const mlm
         if (e != hipSuccess) return hip_fail(ctx, e, "control-variate level launch");
         return MLMC_OK;
     }
-    const LaunchShape shape = choose_shape(ctx, m, p, l, M, precision, N);
+    const LaunchShape shape = choose_shape(ctx, m, p, l, M, precision, N, n_call);
     const double nf = (double)level_steps(l, M);
     const double twins = (m.antithetic && l > 0) ? 2.0 : 1.0;   // fine paths per sample
     hipEvent_t t0, t1;
@@ -261,6 +274,7 @@ static mlmc_status enqueue_segment(mlmc_ctx* ctx, const mlmc_model& m, const mlm
     } else {
         auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
         a.spread_mask = mask;
+        a.split = (uint32_t)shape.split;
         set_counter_words(a, dim);
         e = launch_level(m, p, M, 32, &a, shape, ctx->stream, t0, t1);
     }
@@ -281,7 +295,7 @@ mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff&
         const mlmc_status st =
             enqueue_segment(ctx, m, p, l, M, stop - first, seed, first, precision, stream, coupled,
                             acc, d_pf ? d_pf + skip : nullptr, d_pc ? d_pc + skip : nullptr, cv,
-                            spread);
+                            spread, N);
         if (st) return st;
         first = stop;
     }

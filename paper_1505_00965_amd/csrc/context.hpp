@@ -65,9 +65,11 @@ mlmc_status hip_fail(mlmc_ctx* ctx, hipError_t e, const char* what);
 double level_cost(const mlmc_model& m, int l, int M);
 mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payoff* p, int l, int M,
                              int precision);
-// Launch shape for N samples at level l (honours mlmc_set_launch).
+// Launch shape for N samples at level l (honours mlmc_set_launch); paths
+// are split across lanes by the count of the whole call, n_call >= N (a call
+// may be cut into several launches at the counter's high word).
 LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
-                         int M, int precision, uint64_t N);
+                         int M, int precision, uint64_t N, uint64_t n_call = 0);
 // Enqueue one level into record `acc`, or with `spread` into the spread
 // group of kSpread records at `acc` (no zeroing, no sync).
 mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,

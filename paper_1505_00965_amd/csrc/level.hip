@@ -48,12 +48,12 @@ template StepParams<double> make_step_params<double>(const mlmc_model&, const ml
 
 // ------------------------------------------------------------ dispatch
 // Instantiated in the per-variant translation units.
-extern template KernelFn<float> pick_variant<kGBM, float>(int, int, int, int, bool);
-extern template KernelFn<double> pick_variant<kGBM, double>(int, int, int, int, bool);
-extern template KernelFn<float> pick_variant<kGBMMil, float>(int, int, int, int, bool);
-extern template KernelFn<double> pick_variant<kGBMMil, double>(int, int, int, int, bool);
-extern template KernelFn<float> pick_variant<kHeston, float>(int, int, int, int, bool);
-extern template KernelFn<double> pick_variant<kHeston, double>(int, int, int, int, bool);
+extern template KernelFn<float> pick_variant<kGBM, float>(int, int, int, int, bool, bool);
+extern template KernelFn<double> pick_variant<kGBM, double>(int, int, int, int, bool, bool);
+extern template KernelFn<float> pick_variant<kGBMMil, float>(int, int, int, int, bool, bool);
+extern template KernelFn<double> pick_variant<kGBMMil, double>(int, int, int, int, bool, bool);
+extern template KernelFn<float> pick_variant<kHeston, float>(int, int, int, int, bool, bool);
+extern template KernelFn<double> pick_variant<kHeston, double>(int, int, int, int, bool, bool);
 
 int sampler_variant(const mlmc_model& m)
 {
@@ -62,13 +62,13 @@ int sampler_variant(const mlmc_model& m)
 }
 
 template <typename Real>
-static KernelFn<Real> pick(const mlmc_model& m, int payoff, int M, int ppt, int nf)
+static KernelFn<Real> pick(const mlmc_model& m, int payoff, int M, int ppt, int nf, bool split)
 {
     const bool anti = m.antithetic != 0 && nf > 1;
     switch (sampler_variant(m)) {
-    case kGBMMil: return pick_variant<kGBMMil, Real>(payoff, M, ppt, nf, anti);
-    case kHeston: return pick_variant<kHeston, Real>(payoff, M, ppt, nf, anti);
-    default: return pick_variant<kGBM, Real>(payoff, M, ppt, nf, anti);
+    case kGBMMil: return pick_variant<kGBMMil, Real>(payoff, M, ppt, nf, anti, split);
+    case kHeston: return pick_variant<kHeston, Real>(payoff, M, ppt, nf, anti, split);
+    default: return pick_variant<kGBM, Real>(payoff, M, ppt, nf, anti, split);
     }
 }
 
@@ -109,12 +109,12 @@ hipError_t launch_level(const mlmc_model& m, const mlmc_payoff& p, int M, int pr
     dim3 block(shape.block);
     if (precision == 64) {
         const auto& a = *(const LevelArgs<double>*)args;
-        auto fn = pick<double>(m, p.kind, M, 1, a.nf);
+        auto fn = pick<double>(m, p.kind, M, 1, a.nf, false);
         hipExtLaunchKernelGGL(fn, resident_grid((const void*)fn, shape), block, 0, stream, start,
                               stop, 0, a);
     } else {
         const auto& a = *(const LevelArgs<float>*)args;
-        auto fn = pick<float>(m, p.kind, M, shape.ppt, a.nf);
+        auto fn = pick<float>(m, p.kind, M, shape.ppt, a.nf, a.split > 1);
         hipExtLaunchKernelGGL(fn, resident_grid((const void*)fn, shape), block, 0, stream, start,
                               stop, 0, a);
     }

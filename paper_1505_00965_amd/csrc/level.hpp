@@ -28,6 +28,7 @@ struct LevelArgs {
     const float* phi0;    // level 0 with the control variate: phi(0, S0), else null
     uint32_t c2 = 0;      // Philox counter word 2 of every Brownian block of the launch
     uint32_t c2b = 0;     // and of every bridge block (set_counter_words)
+    uint32_t split = 1;   // lanes per path (split_lanes); 1: one path per lane
 };
 
 // Philox counter word 2 of generator unit u (a block index on one- and
@@ -67,6 +68,21 @@ __host__ __device__ inline void set_counter_words(LevelArgs<Real>& a, int d)
     a.c2b = counter_word2(a.l, a.nf < 4 ? u / (uint64_t)d : u);
 }
 
+// Lanes per path for a GBM level whose N paths cannot fill the device: a
+// power of two G <= 64 with G <= (num_cu 1024) / N (about four paths' worth
+// of lanes per SIMD in all) and n_f / G a multiple of 4, so that every lane
+// holds whole generator blocks (and whole coarse steps); 1 when that leaves
+// fewer than 4 lanes per path or when the variant is not linear in the path's
+// start value (Heston, the conditional digital, the antithetic twin).
+__host__ __device__ inline uint32_t split_lanes(int nf, uint64_t N, int num_cu, bool eligible)
+{
+    if (!eligible || N == 0 || nf < 16) return 1;
+    const uint64_t want = (uint64_t)num_cu * 1024 / N;
+    uint32_t G = 64;
+    while (G > 1 && ((uint64_t)G > want || (uint32_t)(nf / 4) % G != 0)) G >>= 1;
+    return G >= 4 ? G : 1;
+}
+
 // Host-side conversion of model/payoff to the kernel's parameter block.
 template <typename Real>
 StepParams<Real> make_step_params(const mlmc_model& m, const mlmc_payoff& p, int l, int M);
@@ -82,6 +98,7 @@ int sampler_variant(const mlmc_model& m);
 struct LaunchShape {
     int block, ppt, grid;
     int num_cu = 0;
+    int split = 1;        // lanes per path (split_lanes)
 };
 
 // Enqueue one level's sampler on `stream` (accumulating into args.acc).

@@ -3,7 +3,7 @@
 
 namespace mlmc {
 
-template KernelFn<float> pick_variant<kGBM, float>(int, int, int, int, bool);
-template KernelFn<double> pick_variant<kGBM, double>(int, int, int, int, bool);
+template KernelFn<float> pick_variant<kGBM, float>(int, int, int, int, bool, bool);
+template KernelFn<double> pick_variant<kGBM, double>(int, int, int, int, bool, bool);
 
 }  // namespace mlmc

@@ -3,7 +3,7 @@
 
 namespace mlmc {
 
-template KernelFn<float> pick_variant<kGBMMil, float>(int, int, int, int, bool);
-template KernelFn<double> pick_variant<kGBMMil, double>(int, int, int, int, bool);
+template KernelFn<float> pick_variant<kGBMMil, float>(int, int, int, int, bool, bool);
+template KernelFn<double> pick_variant<kGBMMil, double>(int, int, int, int, bool, bool);
 
 }  // namespace mlmc

@@ -3,7 +3,7 @@
 
 namespace mlmc {
 
-template KernelFn<float> pick_variant<kHeston, float>(int, int, int, int, bool);
-template KernelFn<double> pick_variant<kHeston, double>(int, int, int, int, bool);
+template KernelFn<float> pick_variant<kHeston, float>(int, int, int, int, bool, bool);
+template KernelFn<double> pick_variant<kHeston, double>(int, int, int, int, bool, bool);
 
 }  // namespace mlmc

@@ -50,6 +50,20 @@ __global__ __launch_bounds__(1024) void short_level_kernel(LevelArgs<Real> a)
     block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
 }
 
+// GBM levels whose paths are too few to fill the device: a.split lanes per
+// path (process_split); blocks walk the paths a.split at a time per lane group.
+template <int MODEL, int PAYOFF, int M>
+__global__ __launch_bounds__(1024) void split_level_kernel(LevelArgs<float> a)
+{
+    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+    unsigned nonfinite = 0;
+    const uint64_t per_block = blockDim.x / a.split;
+    const uint64_t nchunks = (a.N + per_block - 1) / per_block;
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+        process_split<MODEL, PAYOFF, M>(a, c * per_block, sums, nonfinite);
+    block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
+}
+
 template <typename Real>
 using KernelFn = void (*)(LevelArgs<Real>);
 
@@ -57,8 +71,12 @@ using KernelFn = void (*)(LevelArgs<Real>);
 // The antithetic twin exists on coupled levels (n_f >= 2); fp64 paths run
 // one sample per lane (register budget); the twin runs at most two.
 template <int MODEL, int PAYOFF, typename Real, int M>
-KernelFn<Real> pick_ppt(int ppt, int nf, bool anti)
+KernelFn<Real> pick_ppt(int ppt, int nf, bool anti, bool split)
 {
+    if constexpr (sizeof(Real) == 4 && MODEL != kHeston && PAYOFF != kDigitalCond) {
+        if (split) return split_level_kernel<MODEL, PAYOFF, M>;
+    }
+    (void)split;
     if constexpr (sizeof(Real) == 8) {
         (void)ppt;
         if (nf == 1) return short_level_kernel<MODEL, PAYOFF, Real, 1, M, 1, false>;
@@ -90,23 +108,23 @@ KernelFn<Real> pick_ppt(int ppt, int nf, bool anti)
 }
 
 template <int MODEL, int PAYOFF, typename Real>
-KernelFn<Real> pick_m(int M, int ppt, int nf, bool anti)
+KernelFn<Real> pick_m(int M, int ppt, int nf, bool anti, bool split)
 {
-    return M == 2 ? pick_ppt<MODEL, PAYOFF, Real, 2>(ppt, nf, anti)
-                  : pick_ppt<MODEL, PAYOFF, Real, 4>(ppt, nf, anti);
+    return M == 2 ? pick_ppt<MODEL, PAYOFF, Real, 2>(ppt, nf, anti, split)
+                  : pick_ppt<MODEL, PAYOFF, Real, 4>(ppt, nf, anti, split);
 }
 
 // The kernel of one sampler variant for (payoff, M, samples per lane, n_f,
-// antithetic).  Defined here, instantiated once per variant.
+// antithetic, split paths).  Defined here, instantiated once per variant.
 template <int MODEL, typename Real>
-KernelFn<Real> pick_variant(int payoff, int M, int ppt, int nf, bool anti)
+KernelFn<Real> pick_variant(int payoff, int M, int ppt, int nf, bool anti, bool split)
 {
     switch (payoff) {
-    case kCall: return pick_m<MODEL, kCall, Real>(M, ppt, nf, anti);
-    case kAsian: return pick_m<MODEL, kAsian, Real>(M, ppt, nf, anti);
-    case kLookback: return pick_m<MODEL, kLookback, Real>(M, ppt, nf, anti);
-    case kDigitalCond: return pick_m<MODEL, kDigitalCond, Real>(M, ppt, nf, anti);
-    default: return pick_m<MODEL, kDigital, Real>(M, ppt, nf, anti);
+    case kCall: return pick_m<MODEL, kCall, Real>(M, ppt, nf, anti, split);
+    case kAsian: return pick_m<MODEL, kAsian, Real>(M, ppt, nf, anti, split);
+    case kLookback: return pick_m<MODEL, kLookback, Real>(M, ppt, nf, anti, split);
+    case kDigitalCond: return pick_m<MODEL, kDigitalCond, Real>(M, ppt, nf, anti, split);
+    default: return pick_m<MODEL, kDigital, Real>(M, ppt, nf, anti, split);
     }
 }
 

@@ -53,6 +53,9 @@ struct BatchDesc {
     unsigned resident_blocks;         // grid size of the sampler
     unsigned chunk;                   // blockDim * PPT of the sampler
     unsigned block;                   // blockDim of the sampler
+    unsigned* split;                  // lanes per path per (slot, level), set by the plan
+    int split_ok;                     // the model's paths are linear in their start (GBM)
+    int num_cu;
 };
 
 // Plan: thread 0 sizes every (slot, level) pair's items and lays the pairs
@@ -79,14 +82,24 @@ __device__ __forceinline__ void plan_body(const BatchDesc* d)
         for (int l = L; l >= 0; --l) {          // deepest (longest) items first
             const double nf = pow((double)M, (double)l);
             const double per = nf + (l ? nf / M : 0.0);
-            uint64_t paths = (uint64_t)(target / per);
-            // whole chunks where possible; at least one sample per lane of a block
-            if (paths >= d->chunk) paths = (paths / d->chunk) * d->chunk;
-            else if (paths < d->block) paths = d->block;
-            if (paths > (1ull << 31)) paths = 1ull << 31;   // item counts fit 32 bits
             for (int s = 0; s < d->nslots; ++s) {
                 const uint64_t left = (uint64_t)d->dN[s * kMaxLevels + l];
+                // lanes per path: the per-level launch's rule on the same count
+                const uint32_t G = split_lanes((int)nf, left, d->num_cu,
+                                               d->split_ok && d->payoff_kind[s] != kDigitalCond);
+                d->split[s * kMaxLevels + l] = G;
                 if (left == 0) continue;
+                uint64_t paths = (uint64_t)(target / per);
+                if (G > 1) {
+                    // split paths: whole block passes of block / G paths
+                    const uint64_t pass = d->block / G;
+                    paths = paths < pass ? pass : (paths / pass) * pass;
+                } else if (paths >= d->chunk) {
+                    paths = (paths / d->chunk) * d->chunk;   // whole chunks where possible
+                } else if (paths < d->block) {
+                    paths = d->block;                        // one sample per lane at least
+                }
+                if (paths > (1ull << 31)) paths = 1ull << 31;   // item counts fit 32 bits
                 // at most kItemsPerPair items per pair: the table never fills
                 const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
                 const uint64_t per_item = paths > min_items ? paths : min_items;
@@ -131,6 +144,14 @@ template <int MODEL, int PAYOFF, int M, int PPT>
 __device__ __forceinline__ void run_range(const LevelArgs<float>& a, double (&sums)[kNumSums],
                                           unsigned& nonfinite)
 {
+    if constexpr (MODEL != kHeston && PAYOFF != kDigitalCond) {
+        if (a.split > 1) {
+            const uint64_t pass = blockDim.x / a.split;
+            for (uint64_t base = 0; base < a.N; base += pass)
+                process_split<MODEL, PAYOFF, M>(a, base, sums, nonfinite);
+            return;
+        }
+    }
     if (a.nf < 4) {
         // one or two steps: samples share generator blocks
         constexpr int D = one_factor(MODEL) ? 1 : 2;
@@ -172,6 +193,7 @@ __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, 
     a.pf_out = a.pc_out = nullptr;
     a.coupled = 1;
     a.phi0 = nullptr;
+    a.split = d->split[w.slot * kMaxLevels + w.level];
     constexpr int D = one_factor(MODEL) ? 1 : 2;
     // one pass per part of the item whose generator units share counter word 2
     const uint64_t q = samples_per_unit(nf, D), end = w.first + w.n;
@@ -251,6 +273,7 @@ struct PersistentBufs {
     WorkItem* d_items = nullptr;
     unsigned* d_counters = nullptr;   // head, count
     LevelAcc* d_acc = nullptr;        // batch records [kMaxSlots][kMaxLevels]
+    unsigned* d_split = nullptr;      // lanes per path [kMaxSlots][kMaxLevels]
     double* d_req = nullptr;          // dN[kMaxSlots][kMaxLevels], offset[...]
     double* h_req = nullptr;
     hipGraphExec_t graph = nullptr;   // cached batch graph
@@ -285,6 +308,7 @@ static mlmc_status ensure_bufs(mlmc_ctx* ctx)
     MLMC_HIP(ctx, hipMalloc(&b->d_items, sizeof(WorkItem) * kMaxItems));
     MLMC_HIP(ctx, hipMalloc(&b->d_counters, sizeof(unsigned) * 4));
     MLMC_HIP(ctx, hipMalloc(&b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels));
+    MLMC_HIP(ctx, hipMalloc(&b->d_split, sizeof(unsigned) * kMaxSlots * kMaxLevels));
     MLMC_HIP(ctx, hipMalloc(&b->d_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels));
     MLMC_HIP(ctx, hipHostMalloc(&b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels));
     return MLMC_OK;
@@ -303,6 +327,7 @@ void free_persistent(mlmc_ctx* ctx)
     if (b->d_items) hipFree(b->d_items);
     if (b->d_counters) hipFree(b->d_counters);
     if (b->d_acc) hipFree(b->d_acc);
+    if (b->d_split) hipFree(b->d_split);
     if (b->d_req) hipFree(b->d_req);
     if (b->h_req) hipHostFree(b->h_req);
     delete b;
@@ -333,6 +358,9 @@ static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const ml
     h->count = b->d_counters + 1;
     h->resident_blocks = (unsigned)(ctx->num_cu * s.blocks_per_cu);
     h->chunk = (unsigned)(s.block * s.ppt);
+    h->split = b->d_split;
+    h->split_ok = m.kind == MLMC_GBM && !m.antithetic;
+    h->num_cu = ctx->num_cu;
     h->block = (unsigned)s.block;
 }
 

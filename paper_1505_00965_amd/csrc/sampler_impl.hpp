@@ -68,9 +68,56 @@ __host__ __device__ constexpr bool twin_coarse()
     return PAYOFF == kLookback || PAYOFF == kDigitalCond;
 }
 
+// Generator block g of a path (four fine steps): its increments, advanced
+// through q's fine and coarse paths; with ANTI also through the antithetic
+// twin qa (same generator words, the increments reversed inside every
+// coarse step).
+template <int MODEL, int PAYOFF, typename Real, int M, bool ANTI>
+__device__ __forceinline__ void advance_group(const StepParams<Real>& P, const PathKey& key,
+                                              const PathKey& bkey, uint32_t g, PathPair<Real>& q,
+                                              PathPair<Real>& qa)
+{
+    Real dw1[4], dwp[4], e[4];
+    if (one_factor(MODEL)) {
+        const u32x4 w = path_block(key, g);
+        brownian_pair(w.x, w.y, P, dw1[0], dw1[1]);
+        brownian_pair(w.z, w.w, P, dw1[2], dw1[3]);
+        dwp[0] = dwp[1] = dwp[2] = dwp[3] = Real(0);
+    } else {
+        const u32x4 wa = path_block(key, 2 * g);
+        const u32x4 wb = path_block(key, 2 * g + 1);
+        brownian_pair(wa.x, wa.y, P, dw1[0], dwp[0]);
+        brownian_pair(wa.z, wa.w, P, dw1[1], dwp[1]);
+        brownian_pair(wb.x, wb.y, P, dw1[2], dwp[2]);
+        brownian_pair(wb.z, wb.w, P, dw1[3], dwp[3]);
+    }
+    if (PAYOFF == kLookback) {
+        const u32x4 u = path_block(bkey, g);
+        e[0] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.x));
+        e[1] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.y));
+        e[2] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.z));
+        e[3] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.w));
+    } else {
+        e[0] = e[1] = e[2] = e[3] = Real(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        fine_step<Real, MODEL, PAYOFF>(q, P, dw1[k], dwp[k], e[k], k % M, true);
+        if (((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(q, P);
+    }
+    if (ANTI) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            constexpr bool tc = twin_coarse<PAYOFF>();
+            const int j = twin_index<M>(k);
+            fine_step<Real, MODEL, PAYOFF>(qa, P, dw1[j], dwp[j], e[j], k % M, tc);
+            if (tc && ((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(qa, P);
+        }
+    }
+}
+
 // Advance PPT coupled pairs through all n_f >= 4 fine steps of the level;
-// with ANTI also each pair's antithetic twin qa (same generator words, the
-// increments reversed inside every coarse step).
+// with ANTI also each pair's antithetic twin qa.
 template <int MODEL, int PAYOFF, typename Real, int M, int PPT, bool ANTI>
 __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_t (&s)[PPT],
                                          PathPair<Real> (&q)[PPT], PathPair<Real> (&qa)[PPT])
@@ -91,45 +138,8 @@ __device__ __forceinline__ void simulate(const LevelArgs<Real>& a, const uint64_
     // operations on the coupled levels than the coarse steps cost there.
     for (uint32_t g = 0; g < a.ngroups; ++g) {
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            Real dw1[4], dwp[4], e[4];
-            if (one_factor(MODEL)) {
-                const u32x4 w = path_block(key[p], g);
-                brownian_pair(w.x, w.y, P, dw1[0], dw1[1]);
-                brownian_pair(w.z, w.w, P, dw1[2], dw1[3]);
-                dwp[0] = dwp[1] = dwp[2] = dwp[3] = Real(0);
-            } else {
-                const u32x4 wa = path_block(key[p], 2 * g);
-                const u32x4 wb = path_block(key[p], 2 * g + 1);
-                brownian_pair(wa.x, wa.y, P, dw1[0], dwp[0]);
-                brownian_pair(wa.z, wa.w, P, dw1[1], dwp[1]);
-                brownian_pair(wb.x, wb.y, P, dw1[2], dwp[2]);
-                brownian_pair(wb.z, wb.w, P, dw1[3], dwp[3]);
-            }
-            if (PAYOFF == kLookback) {
-                const u32x4 u = path_block(bkey[p], g);
-                e[0] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.x));
-                e[1] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.y));
-                e[2] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.z));
-                e[3] = P.lnu_scale * flog2<Real>(uniform01<Real>(u.w));
-            } else {
-                e[0] = e[1] = e[2] = e[3] = Real(0);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                fine_step<Real, MODEL, PAYOFF>(q[p], P, dw1[k], dwp[k], e[k], k % M, true);
-                if (((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(q[p], P);
-            }
-            if (ANTI) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    constexpr bool tc = twin_coarse<PAYOFF>();
-                    const int j = twin_index<M>(k);
-                    fine_step<Real, MODEL, PAYOFF>(qa[p], P, dw1[j], dwp[j], e[j], k % M, tc);
-                    if (tc && ((k + 1) % M) == 0) coarse_step<Real, MODEL, PAYOFF>(qa[p], P);
-                }
-            }
-        }
+        for (int p = 0; p < PPT; ++p)
+            advance_group<MODEL, PAYOFF, Real, M, ANTI>(P, key[p], bkey[p], g, q[p], qa[p]);
     }
 }
 
@@ -187,6 +197,77 @@ __device__ __forceinline__ void process_chunk(const LevelArgs<Real>& a, uint64_t
         if (idx[p] >= a.N) continue;
         accumulate(a, idx[p], pf, pc, sums, nonfinite);
     }
+}
+
+// GBM paths split across G = a.split consecutive lanes (a power of two up to
+// 64), for levels whose paths are too few to fill the device.  Lane j of a
+// path runs fine steps [j n_f/G, (j+1) n_f/G) from a unit start: the Euler
+// and Milstein GBM steps, both coarse constructions and every payoff
+// functional are linear in the start value (the terminal value is a product
+// of segment factors, the sum of S_n adds the next segment's sum scaled by
+// the product so far, the bridge minima scale the same way).  The segment
+// summaries (P, Sigma, m) of fine and coarse path combine in path order,
+// (P1, S1, m1) o (P2, S2, m2) = (P1 P2, S1 + P1 S2, min(m1, P1 m2)), in fp64
+// over a shuffle tree, and the path's first lane forms the payoffs at scale
+// S0.  n_f / G is a multiple of 4, so segments hold whole generator blocks
+// and whole coarse steps.  base indexes paths; a block takes blockDim / G.
+template <int MODEL, int PAYOFF, int M>
+__device__ __forceinline__ void process_split(const LevelArgs<float>& a, uint64_t base,
+                                              double (&sums)[kNumSums], unsigned& nonfinite)
+{
+    static_assert(MODEL != kHeston, "the variance step is not linear in the start value");
+    static_assert(PAYOFF != kDigitalCond, "the conditional payoff needs the last step's state");
+    const int G = (int)a.split;
+    const int seg = (int)threadIdx.x & (G - 1);
+    const uint64_t idx = base + threadIdx.x / (uint32_t)G;
+    const uint64_t s = a.offset + idx;
+    const bool coupled = a.coupled && a.l > 0;
+    const StepParams<float>& P = a.P;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const PathKey key{k0, k1, (uint32_t)s, a.c2, a.stream};
+    const PathKey bkey{k0, k1, (uint32_t)s, a.c2b, a.stream + 1u};
+    PathPair<float> q, qa;
+    init_pair<float, MODEL, PAYOFF>(q, P);
+    q.S = 1.0f;
+    q.Sc = 1.0f;
+    const uint32_t per = a.ngroups / (uint32_t)G;     // generator blocks per lane
+    for (uint32_t g = (uint32_t)seg * per; g < (uint32_t)(seg + 1) * per; ++g)
+        advance_group<MODEL, PAYOFF, float, M, false>(P, key, bkey, g, q, qa);
+    double pf = q.S, sf = (double)q.asum - (double)q.acomp, mf = q.mn;
+    double pc = q.Sc, sc = (double)q.csum - (double)q.ccomp, mc = q.mnc;
+    for (int off = 1; off < G; off <<= 1) {
+        const double pf2 = __shfl_down(pf, off, G), pc2 = __shfl_down(pc, off, G);
+        double sf2 = 0, sc2 = 0, mf2 = 0, mc2 = 0;
+        if (PAYOFF == kAsian) {
+            sf2 = __shfl_down(sf, off, G);
+            sc2 = __shfl_down(sc, off, G);
+        }
+        if (PAYOFF == kLookback) {
+            mf2 = __shfl_down(mf, off, G);
+            mc2 = __shfl_down(mc, off, G);
+        }
+        if ((seg & (2 * off - 1)) == 0) {
+            if (PAYOFF == kAsian) {
+                sf = __builtin_fma(pf, sf2, sf);
+                sc = __builtin_fma(pc, sc2, sc);
+            }
+            if (PAYOFF == kLookback) {
+                const double a1 = pf * mf2, a2 = pc * mc2;
+                mf = a1 < mf ? a1 : mf;
+                mc = a2 < mc ? a2 : mc;
+            }
+            pf *= pf2;
+            pc *= pc2;
+        }
+    }
+    if (seg != 0) return;
+    const double S0 = (double)P.S0;
+    const float vf = payoff_value<float, PAYOFF>(P, (float)(S0 * pf), (float)(S0 * sf), 0.0f,
+                                                 (float)(S0 * mf), P.h);
+    const float vc = coupled ? payoff_value<float, PAYOFF>(P, (float)(S0 * pc), (float)(S0 * sc),
+                                                           0.0f, (float)(S0 * mc), P.H)
+                             : 0.0f;
+    if (idx < a.N) accumulate(a, idx, vf, vc, sums, nonfinite);
 }
 
 // Levels with n_f = NF in {1, 2}: Q = 4/(NF d) consecutive samples share one
