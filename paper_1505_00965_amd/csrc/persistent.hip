@@ -46,7 +46,7 @@ struct BatchDesc {
     // driver these alias DriverState::dN / n (slot 0 only)
     const double* dN;
     const double* offset;
-    LevelAcc* acc;                    // acc[slot * kMaxLevels + level]
+    LevelAcc* acc;                    // spread groups [slot][level][kSpread]
     WorkItem* items;
     unsigned* head;                   // work dispenser
     unsigned* count;                  // number of items
@@ -138,6 +138,27 @@ __device__ __forceinline__ void plan_body(const BatchDesc* d)
 }
 
 __global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d) { plan_body(d); }
+
+// Fold each spread group (kSpread records) into one record, group g by
+// block g, in record order; clears the groups for the next replay.
+__global__ __launch_bounds__(64) void fold_groups_kernel(LevelAcc* groups, LevelAcc* out)
+{
+    static_assert(kSpread == 64, "one lane per record of a group");
+    LevelAcc& r = groups[blockIdx.x * kSpread + threadIdx.x];
+    double v[kNumSums];
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) v[k] = wave_sum(r.sum[k]);
+    const double c = wave_sum((double)r.n_nonfinite);
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) r.sum[k] = 0.0;
+    r.n_nonfinite = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kNumSums; ++k) out[blockIdx.x].sum[k] = v[k];
+        out[blockIdx.x].n_nonfinite = (unsigned long long)c;
+        out[blockIdx.x].pad = 0;
+    }
+}
 
 // The samples [a.offset, a.offset + a.N) of one item part (a.c2, a.c2b set).
 template <int MODEL, int PAYOFF, int M, int PPT>
@@ -231,7 +252,8 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d)
         default: run_item<MODEL, kDigital, M, PPT>(d, w, sums, nonfinite); break;
         }
         if (w.level == 0) copy_y_sums(sums);
-        block_reduce_add(sums, nonfinite, &d->acc[w.slot * kMaxLevels + w.level]);
+        block_reduce_add(sums, nonfinite, &d->acc[(w.slot * kMaxLevels + w.level) * kSpread +
+                                                  (blockIdx.x & (kSpread - 1))]);
     }
 }
 
@@ -272,7 +294,8 @@ struct PersistentBufs {
     BatchDesc* h_desc = nullptr;
     WorkItem* d_items = nullptr;
     unsigned* d_counters = nullptr;   // head, count
-    LevelAcc* d_acc = nullptr;        // batch records [kMaxSlots][kMaxLevels]
+    LevelAcc* d_acc = nullptr;        // batch spread groups [kMaxSlots][kMaxLevels][kSpread]
+    LevelAcc* d_rec = nullptr;        // their folds [kMaxSlots][kMaxLevels]
     unsigned* d_split = nullptr;      // lanes per path [kMaxSlots][kMaxLevels]
     double* d_req = nullptr;          // dN[kMaxSlots][kMaxLevels], offset[...]
     double* h_req = nullptr;
@@ -307,7 +330,8 @@ static mlmc_status ensure_bufs(mlmc_ctx* ctx)
     MLMC_HIP(ctx, hipHostMalloc(&b->h_desc, sizeof(BatchDesc)));
     MLMC_HIP(ctx, hipMalloc(&b->d_items, sizeof(WorkItem) * kMaxItems));
     MLMC_HIP(ctx, hipMalloc(&b->d_counters, sizeof(unsigned) * 4));
-    MLMC_HIP(ctx, hipMalloc(&b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels));
+    MLMC_HIP(ctx, hipMalloc(&b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels * kSpread));
+    MLMC_HIP(ctx, hipMalloc(&b->d_rec, sizeof(LevelAcc) * kMaxSlots * kMaxLevels));
     MLMC_HIP(ctx, hipMalloc(&b->d_split, sizeof(unsigned) * kMaxSlots * kMaxLevels));
     MLMC_HIP(ctx, hipMalloc(&b->d_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels));
     MLMC_HIP(ctx, hipHostMalloc(&b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels));
@@ -327,6 +351,7 @@ void free_persistent(mlmc_ctx* ctx)
     if (b->d_items) hipFree(b->d_items);
     if (b->d_counters) hipFree(b->d_counters);
     if (b->d_acc) hipFree(b->d_acc);
+    if (b->d_rec) hipFree(b->d_rec);
     if (b->d_split) hipFree(b->d_split);
     if (b->d_req) hipFree(b->d_req);
     if (b->h_req) hipHostFree(b->h_req);
@@ -374,7 +399,8 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
     MLMC_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess && zero_batch) e = zero_records(b->d_acc, kMaxSlots * kMaxLevels, cs);
+    if (e == hipSuccess && zero_batch)
+        e = zero_records(b->d_acc, kMaxSlots * kMaxLevels * kSpread, cs);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, cs, (const BatchDesc*)b->d_desc);
         e = hipGetLastError();
@@ -384,8 +410,13 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
                            dim3(s.block), 0, cs, (const BatchDesc*)b->d_desc);
         e = hipGetLastError();
     }
+    if (e == hipSuccess && zero_batch) {
+        hipLaunchKernelGGL(fold_groups_kernel, dim3(kMaxSlots * kMaxLevels), dim3(kSpread), 0, cs,
+                           b->d_acc, b->d_rec);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess && driver)
-        e = launch_driver_update(driver, (DriverState*)ctx->h_drv_dev, nullptr, cs);
+        e = launch_driver_update(driver, (DriverState*)ctx->h_drv_dev, ctx->d_drv_spread, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -404,7 +435,8 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     mlmc_status st = ensure_bufs(ctx);
     if (st) return st;
     auto* b = bufs_of(ctx);
-    fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, o.seed, d_st->dN, d_st->n, d_st->batch);
+    fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, o.seed, d_st->dN, d_st->n,
+              ctx->d_drv_spread);
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
                                  ctx->stream));
     // the graph reads the descriptor, the driver state and its mirror at
@@ -530,8 +562,9 @@ mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc
     const int tix = timed_begin(ctx, 16, fine, coarse);
     MLMC_HIP(ctx, hipGraphLaunch(b->graph, ctx->stream));
     timed_end(ctx, tix);
-    LevelAcc* h_acc = ctx->h_acc;   // kAccSlots >= kMaxSlots * kMaxLevels
-    MLMC_HIP(ctx, hipMemcpyAsync(h_acc, b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels,
+    static_assert(kMaxSlots * kMaxLevels <= kAccSlots, "the folded records fit the host copy");
+    LevelAcc* h_acc = ctx->h_acc;
+    MLMC_HIP(ctx, hipMemcpyAsync(h_acc, b->d_rec, sizeof(LevelAcc) * kMaxSlots * kMaxLevels,
                                  hipMemcpyDeviceToHost, ctx->stream));
     MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     harvest_timing(ctx);
