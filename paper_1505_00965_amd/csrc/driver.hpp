@@ -1,10 +1,12 @@
 // Device-resident state of the adaptive MLMC driver.
 //
-// The sampler adds each level's batch sums into batch[l]; one small fp64
-// kernel (driver_update) then absorbs them, re-estimates E_l and V_l, sets the
-// optimal N_l and the next outstanding batch dN_l, runs the bias test and
-// adds a level when needed.  The host only reads this struct back to learn
-// what to launch next (or, in the persistent form, only the done flag).
+// The sampler adds each level's batch sums into that level's spread group
+// (one per level, outside this struct); one small fp64 kernel
+// (driver_update) folds the groups into batch[l], absorbs them, re-estimates
+// E_l and V_l, sets the optimal N_l and the next outstanding batch dN_l, runs
+// the bias test and adds a level when needed.  The host only reads this
+// struct back to learn what to launch next (or, in the persistent form, only
+// the done flag).
 #pragma once
 #include <stdint.h>
 

@@ -8,7 +8,9 @@
 // outstanding samples into items of roughly equal cost, deepest levels first
 // (longest-processing-time order), and a resident grid of blocks takes items
 // from an atomic counter until none are left, so cheap levels fill in around
-// the long deep-level items.  Every parameter the launches read lives in
+// the long deep-level items.  GBM levels with too few paths to fill the
+// device run each path on several lanes (process_split), with the per-level
+// launch's rule on the level's count.  Every parameter the launches read lives in
 // device memory and is rewritten between launches (by the driver kernel or
 // by host copies), so the graph is captured once and replayed.
 #include <hip/hip_runtime.h>
