@@ -49,7 +49,7 @@ def measured_traffic(kernel_label):
     import hashlib
     h = hashlib.sha256()
     for f in ("philox.hpp", "sampler.hpp", "sampler_impl.hpp", "reduce.hpp", "level.hip",
-              "level.hpp", "level_kernels.hpp", "level_gbm.hip"):
+              "level.hpp", "level_kernels.hpp", "level_gbm.hip", "../build.py"):
         with open(os.path.join(ROOT, "paper_1505_00965_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     digest = h.hexdigest()[:16]
@@ -190,11 +190,52 @@ def persistent_batch(ctx, mlmc, W, reps=3):
                 ctx.mlmc_level(gm, p, l, 4, N[0][l], 1 + r)
     torch.cuda.synchronize()
     t_levels = (time.perf_counter() - t0) / reps
+    # the tail: level 8 (1024 paths of 65536 steps) of each payoff as one launch
+    tail = {}
+    for name, p in zip(names, pays):
+        ctx.set_timing_slots([L])
+        for r in range(reps):
+            ctx.mlmc_level(gm, p, L, 4, N[0][L], 1 + r)
+        st = ctx.kernel_stats()[L]
+        ctx.set_timing(False)
+        tail[name] = 1e3 * st["ms"] / st["launches"]
     return {"workload": "GBM call/Asian/lookback/digital, M=4, levels 0..8, N_l = 2^26 4^-l",
             "fine_path_steps": fine, "persistent_ms": 1e3 * t_batch,
             "per_level_launches_ms": 1e3 * t_levels,
             "persistent_fine_steps_per_s": fine / t_batch,
-            "per_level_fine_steps_per_s": fine / t_levels}
+            "per_level_fine_steps_per_s": fine / t_levels,
+            "level8_launch_us": tail}
+
+
+def black_scholes_call(S0, K, r, sigma, T):
+    """Closed-form European call (the limit every level telescopes to)."""
+    import math
+    d1 = (math.log(S0 / K) + (r + 0.5 * sigma * sigma) * T) / (sigma * math.sqrt(T))
+    d2 = d1 - sigma * math.sqrt(T)
+    cdf = lambda x: 0.5 * math.erfc(-x / math.sqrt(2.0))
+    return S0 * cdf(d1) - K * math.exp(-r * T) * cdf(d2)
+
+
+def accuracy_targets(ctx, mlmc, W, seeds=range(1, 33)):
+    """The adaptive configuration's own accuracy targets: GBM call, M = 4,
+    eps in {2e-3, 1e-3, 5e-4} S0, 32 seeds; median wall seconds and the
+    empirical RMSE of the estimates against the Black--Scholes price."""
+    import statistics
+    m, p = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    md = W.GBM_MODEL
+    exact = black_scholes_call(md["S0"], W.CALL["K"], md["r"], md["sigma"], md["T"])
+    out = {"workload": "GBM European call, M=4, pilot 1e4, L_min 2, fp32 paths, 32 seeds",
+           "black_scholes": exact}
+    for eps in (2e-3, 1e-3, 5e-4):
+        runs = [ctx.mlmc_run(m, p, eps * W.S0, M=4, seed=s, precision=32) for s in seeds]
+        est = [r["estimate"] for r in runs]
+        rmse = (sum((e - exact) ** 2 for e in est) / len(est)) ** 0.5
+        out[f"eps_{eps:g}_S0"] = {
+            "median_s": statistics.median(r["wall_s"] for r in runs),
+            "rmse_vs_black_scholes": rmse, "target_rmse": eps * W.S0,
+            "L": [r["L"] for r in runs][len(runs) // 2],
+            "N_median_run": sorted(runs, key=lambda r: r["wall_s"])[len(runs) // 2]["N"]}
+    return out
 
 
 def fig3(ctx, mlmc, W):
@@ -341,6 +382,7 @@ def main():
     if not args.no_tta:
         line["persistent_batch"] = persistent_batch(ctx, mlmc, W)
         line["seconds_to_rmse"] = time_to_accuracy(ctx, mlmc, W, args)
+        line["accuracy_targets"] = accuracy_targets(ctx, mlmc, W)
         line["fig3"] = fig3(ctx, mlmc, W)
 
     if not args.no_cpu:
