@@ -42,9 +42,9 @@ def algorithmic_ops(level, fine_steps, samples):
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
-def measured_traffic(kernel_label):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None if the kernel sources changed since it was taken."""
+def profile_field(kernel_label, field):
+    """A figure from the committed rocprofv3 summaries (profiles/*.md) of this
+    kernel, or None if the kernel sources changed since they were taken."""
     import glob
     import hashlib
     h = hashlib.sha256()
@@ -53,15 +53,21 @@ def measured_traffic(kernel_label):
         with open(os.path.join(ROOT, "paper_1505_00965_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     digest = h.hexdigest()[:16]
-    for path in glob.glob(os.path.join(ROOT, "profiles", "*pmc*.md")):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         fields = {}
         for line in open(path):
             if ":" in line and not line.startswith(("|", "#", "-", " ")):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-        if fields.get("kernel") == kernel_label and fields.get("kernel_sources_sha256") == digest:
-            return float(fields["traffic_bytes_per_launch"])
+        if (fields.get("kernel") == kernel_label and fields.get("kernel_sources_sha256") == digest
+                and field in fields):
+            return float(fields[field])
     return None
+
+
+def measured_traffic(kernel_label):
+    """HBM bytes per launch (FETCH_SIZE/WRITE_SIZE summary)."""
+    return profile_field(kernel_label, "traffic_bytes_per_launch")
 
 
 def parse():
@@ -347,6 +353,9 @@ def main():
                         "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
                         "frac": achieved / VALU_PEAK_OPS, "traffic": measured_traffic(label),
                         "kernel": label,
+                        # issued vector instructions x 4 cycles over SIMD cycles, from
+                        # SQ_INSTS_VALU and GRBM_GUI_ACTIVE (issue slots, not method ops)
+                        "valu_issue_frac_counters": profile_field(label, "valu_issue_frac"),
                         "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_ms,
                         "launches": s["launches"],
                         "fine_steps_per_launch": s["fine_steps"] / s["launches"]}
