@@ -133,17 +133,19 @@ __device__ __forceinline__ void driver_update_dev(DriverState* st)
 // The update is a serial chain of a few hundred dependent fp64 operations on
 // the state, so the state is staged in LDS (a global round trip per access
 // would dominate), updated by one lane, and written back.  The same words go
-// to the host's pinned mirror (if any): everything but `seq` first, then a
-// system-scope fence, then `seq`, so a host that sees the new `seq` sees the
-// whole update.  With `spread` (kMaxLevels spread groups, one per level) the
+// to the host's pinned mirror (if any): everything before the batch records
+// but `seq` first, then a system-scope fence, then `seq`, so a host that sees
+// the new `seq` sees the whole update.  With `spread` (kMaxLevels spread groups, one per level) the
 // block first folds each sampled level's group into batch[l] (the sums of Y
-// and Y^2 and the non-finite count), one wave per level, and clears it.  Every thread of the block must call it; `s` is the
-// block's LDS copy of the state.
+// and Y^2 and the non-finite count), one wave per level, and clears it.
+// Every thread of the block must call it; `s` is the block's LDS copy of the
+// state.
 __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s,
                                                     LevelAcc* spread)
 {
     static_assert(sizeof(DriverState) % 8 == 0, "state is copied in 8-byte words");
     static_assert(offsetof(DriverState, seq) % 8 == 0, "seq is one word");
+    static_assert(offsetof(DriverState, batch) % 8 == 0, "batch starts a word");
     constexpr int kWords = sizeof(DriverState) / 8;
     constexpr int kSeq = offsetof(DriverState, seq) / 8;
     const unsigned long long* src = (const unsigned long long*)st;
@@ -179,8 +181,11 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
     // the host waits for the mirror: publish it first; the device copy is
     // read by the next update only, which the stream orders after this one
     if (mirror) {
+        // the host never reads the batch records: every word before them
+        constexpr int kMirrorWords = offsetof(DriverState, batch) / 8;
+        static_assert(kSeq < kMirrorWords, "seq precedes the batch records");
         volatile unsigned long long* h = (volatile unsigned long long*)mirror;
-        for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+        for (int i = threadIdx.x; i < kMirrorWords; i += blockDim.x)
             if (i != kSeq) h[i] = w[i];
         __threadfence_system();
         __syncthreads();
