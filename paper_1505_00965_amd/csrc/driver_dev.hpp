@@ -135,11 +135,11 @@ __device__ __forceinline__ void driver_update_dev(DriverState* st)
 // would dominate), updated by one lane, and written back.  The same words go
 // to the host's pinned mirror (if any): everything before the batch records
 // but `seq` first, then a system-scope fence, then `seq`, so a host that sees
-// the new `seq` sees the whole update.  With `spread` (kMaxLevels spread groups, one per level) the
-// block first folds each sampled level's group into batch[l] (the sums of Y
-// and Y^2 and the non-finite count), one wave per level, and clears it.
-// Every thread of the block must call it; `s` is the block's LDS copy of the
-// state.
+// the new `seq` sees the whole update.  With `spread` (kMaxLevels spread
+// groups, one per level) the block first folds each sampled level's group
+// into batch[l] (the sums of Y and Y^2 and the non-finite count), one wave
+// per level, and clears it.  Every thread of the block must call it; `s` is
+// the block's LDS copy of the state.
 __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s,
                                                     LevelAcc* spread)
 {
