@@ -24,7 +24,10 @@
  *   - random numbers: Philox4x32-10 keyed by the 64-bit seed; sample s of
  *     level l is a pure function of (seed, l, s), so results do not depend on
  *     the launch configuration except for the order of FP64 atomic additions
- *     (relative differences of order 1e-16).
+ *     (relative differences of order 1e-16).  On GBM levels whose paths are
+ *     split across lanes (a choice made from the call's N) an fp32 path is
+ *     rounded differently from the one-lane evaluation, by a few units in
+ *     the last place.
  */
 #ifndef MLMC_H
 #define MLMC_H
@@ -117,13 +120,17 @@ mlmc_status mlmc_ctx_create(int device, mlmc_ctx** out);
 /* Frees every device buffer of the context; NULL is accepted. */
 mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx);
 /* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream()
- * .cuda_stream) for all later work; NULL restores the context's own. */
+ * .cuda_stream) for all later work; NULL restores the context's own.  Waits
+ * for the work already enqueued on the previous stream (the context's
+ * buffers are shared by all its launches); MLMC_EDEVICE if that work failed. */
 mlmc_status mlmc_set_stream(mlmc_ctx* ctx, void* hip_stream);
 /* Last error message of this context ("" if none); valid until the next call. */
 const char* mlmc_last_error(const mlmc_ctx* ctx);
 /* Fix the level kernel's launch shape: block in {64,128,256,512,1024},
  * paths per thread ppt in {1,2,4}.  block = 0 returns to the tuned/default
- * choice.  Results do not depend on it (see determinism above).            */
+ * choice.  Results do not depend on it (see determinism above).  GBM levels
+ * whose paths are too few to fill the device run each path on several lanes
+ * (a choice made from N alone, whatever the shape).                         */
 mlmc_status mlmc_set_launch(mlmc_ctx* ctx, int block, int ppt);
 
 /* Kernel timing with HIP events on the context's stream.  Slots:
