@@ -275,7 +275,7 @@ def fig3(ctx, mlmc, W):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build runs no cross-GPU work "
+        print(f"bench.py measures one GPU only: the library runs no cross-GPU work "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
     import torch
