@@ -244,6 +244,23 @@ def accuracy_targets(ctx, mlmc, W, seeds=range(1, 33)):
     return out
 
 
+def fp64_error(ctx, mlmc, W, N_l, M=4, cap=1 << 20):
+    """Error against fp64 of the benchmark's levels: the same samples (seed 1,
+    the first min(N_l, 2^20) of each level) with fp32 and with fp64 paths;
+    per-level difference of the means and its sum (the telescoped estimate)."""
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    levels, total = [], 0.0
+    for l, n_l in enumerate(N_l):
+        n = int(min(n_l, cap))
+        a = ctx.mlmc_level(gm, gp, l, M, n, 1, precision=32)
+        b = ctx.mlmc_level(gm, gp, l, M, n, 1, precision=64)
+        d = a["sum_y"] / n - b["sum_y"] / n
+        total += d
+        levels.append({"level": l, "samples": n, "mean_fp64": b["sum_y"] / n,
+                       "fp32_minus_fp64": d})
+    return {"levels": levels, "telescoped_fp32_minus_fp64": total}
+
+
 def fig3(ctx, mlmc, W):
     """The paper's Sec. 6 experiment on the GPU: N_l per level and eps^2 x cost
     and time for adaptive MLMC and standard Monte Carlo, call and digital."""
@@ -392,6 +409,7 @@ def main():
         line["persistent_batch"] = persistent_batch(ctx, mlmc, W)
         line["seconds_to_rmse"] = time_to_accuracy(ctx, mlmc, W, args)
         line["accuracy_targets"] = accuracy_targets(ctx, mlmc, W)
+        line["fp64_error"] = fp64_error(ctx, mlmc, W, runs[-1]["N"])
         line["fig3"] = fig3(ctx, mlmc, W)
 
     if not args.no_cpu:

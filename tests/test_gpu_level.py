@@ -213,3 +213,34 @@ def test_ranges_across_the_counter_high_word(gctx, orc, kind, M, l, q, pname):
         assert abs(res["sum_y"] - y.sum()) <= 1e-12 * max(1.0, np.abs(y).sum())
         assert abs(res["sum_pf"] - pf.sum()) <= 1e-12 * max(1.0, np.abs(pf).sum())
         assert res["n"] == N and res["n_nonfinite"] == 0
+
+
+def test_full_size_adaptive_levels_sampled(gctx, orc):
+    """The adaptive benchmark's level sizes (GBM call, M = 4, RMSE 2e-5 S0:
+    N_l ~ 2e8, 1.5e7, 3.7e6, 9.3e5, 2.3e5) in the launch shapes the driver
+    uses: every path is dumped, 2048 seeded random samples per level are
+    recomputed one by one by the oracle, and the level sums equal the fp64
+    re-sum of all dumped paths."""
+    import torch
+    gm, om = models(orc, 0)
+    gp, op = pays(orc, "call")
+    rng = np.random.default_rng(12)
+    sizes = (200141354, 14852583, 3713146, 928287, 232072)
+    for l, N in enumerate(sizes):
+        offset = 10000 if l < 3 else 0          # after a pilot, as in the driver's runs
+        print(f"case level={l} N={N} offset={offset}", flush=True)
+        pf = torch.empty(N, dtype=torch.float64, device="cuda")
+        pc = torch.empty(N, dtype=torch.float64, device="cuda")
+        res = gctx.mlmc_level_paths(gm, gp, l, 4, N, 1, pf, pc, path_offset=offset)
+        y = pf - pc
+        sy, sy2 = float(y.sum()), float((y * y).sum())
+        assert abs(res["sum_y"] - sy) <= 1e-12 * float(y.abs().sum())
+        assert abs(res["sum_y2"] - sy2) <= 1e-12 * sy2
+        assert res["n"] == N and res["n_nonfinite"] == 0
+        idx = np.sort(rng.choice(N, size=2048, replace=False))
+        gf, gc = pf[torch.from_numpy(idx).cuda()].cpu().numpy(), pc[torch.from_numpy(idx).cuda()].cpu().numpy()
+        for j, i in enumerate(idx):
+            rf, rc = orc.level_paths(om, op, l, 4, 1, 1, offset + int(i))
+            assert abs(gf[j] - rf[0]) <= 1e-4 * S0 and abs(gc[j] - rc[0]) <= 1e-4 * S0, (l, i)
+        del pf, pc, y
+        torch.cuda.empty_cache()
