@@ -362,14 +362,12 @@ mlmc_status mlmc_ctx_create(int device, mlmc_ctx** out)
     return MLMC_OK;
 }
 
-mlmc_status mlmc_driver_free(mlmc_ctx* ctx);   // driver.hip
-
 mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx)
 {
     if (!ctx) return MLMC_OK;
     hipSetDevice(ctx->device);
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
-    mlmc_driver_free(ctx);
+    free_driver(ctx);
     free_persistent(ctx);
     for (auto& t : ctx->pending) {
         hipEventDestroy(t.start);

@@ -90,6 +90,8 @@ void timed_kernel(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_step
 // After the stream has been synchronised: fold finished events into stats.
 void harvest_timing(mlmc_ctx* ctx);
 
+// Release the driver state and the persistent batch buffers (idempotent).
+void free_driver(mlmc_ctx* ctx);
 void free_persistent(mlmc_ctx* ctx);
 
 // Tuned shape of the level sampler for this problem, if the tuner ran.

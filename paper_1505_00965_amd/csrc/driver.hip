@@ -93,13 +93,30 @@ hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* 
     return hipGetLastError();
 }
 
+void free_driver(mlmc_ctx* ctx)
+{
+    if (ctx->d_drv) hipFree(ctx->d_drv);
+    if (ctx->d_drv_spread) hipFree(ctx->d_drv_spread);
+    if (ctx->h_drv) hipHostFree(ctx->h_drv);
+    ctx->d_drv = ctx->h_drv = ctx->h_drv_dev = nullptr;
+    ctx->d_drv_spread = nullptr;
+}
+
+// The mirror's device address is taken last, so it marks a complete set; a
+// set left incomplete by a failed allocation is released and made again.
 static mlmc_status ensure_driver(mlmc_ctx* ctx)
 {
-    if (ctx->d_drv) return MLMC_OK;
-    MLMC_HIP(ctx, hipMalloc(&ctx->d_drv, sizeof(DriverState)));
-    MLMC_HIP(ctx, hipMalloc(&ctx->d_drv_spread, sizeof(LevelAcc) * kMaxLevels * kSpread));
-    MLMC_HIP(ctx, hipHostMalloc(&ctx->h_drv, sizeof(DriverState)));
-    MLMC_HIP(ctx, hipHostGetDevicePointer(&ctx->h_drv_dev, ctx->h_drv, 0));
+    if (ctx->h_drv_dev) return MLMC_OK;
+    free_driver(ctx);
+    hipError_t e = hipMalloc(&ctx->d_drv, sizeof(DriverState));
+    if (e == hipSuccess)
+        e = hipMalloc(&ctx->d_drv_spread, sizeof(LevelAcc) * kMaxLevels * kSpread);
+    if (e == hipSuccess) e = hipHostMalloc(&ctx->h_drv, sizeof(DriverState));
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&ctx->h_drv_dev, ctx->h_drv, 0);
+    if (e != hipSuccess) {
+        free_driver(ctx);
+        return hip_fail(ctx, e, "driver state allocation");
+    }
     return MLMC_OK;
 }
 
@@ -112,17 +129,6 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
 using namespace mlmc;
 
 extern "C" {
-
-mlmc_status mlmc_driver_free(mlmc_ctx* ctx)
-{
-    if (!ctx) return MLMC_OK;
-    if (ctx->d_drv) hipFree(ctx->d_drv);
-    if (ctx->d_drv_spread) hipFree(ctx->d_drv_spread);
-    ctx->d_drv_spread = nullptr;
-    if (ctx->h_drv) hipHostFree(ctx->h_drv);
-    ctx->d_drv = ctx->h_drv = ctx->h_drv_dev = nullptr;
-    return MLMC_OK;
-}
 
 mlmc_status mlmc_optimal_n(mlmc_ctx* ctx, int L, const double* V, const double* C, double eps,
                            double* N)

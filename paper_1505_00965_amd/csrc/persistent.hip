@@ -328,15 +328,22 @@ static mlmc_status ensure_bufs(mlmc_ctx* ctx)
     auto* b = new (std::nothrow) PersistentBufs();
     if (!b) return fail(ctx, MLMC_ENOMEM, "host allocation failed");
     ctx->persist = b;
-    MLMC_HIP(ctx, hipMalloc(&b->d_desc, sizeof(BatchDesc)));
-    MLMC_HIP(ctx, hipHostMalloc(&b->h_desc, sizeof(BatchDesc)));
-    MLMC_HIP(ctx, hipMalloc(&b->d_items, sizeof(WorkItem) * kMaxItems));
-    MLMC_HIP(ctx, hipMalloc(&b->d_counters, sizeof(unsigned) * 4));
-    MLMC_HIP(ctx, hipMalloc(&b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels * kSpread));
-    MLMC_HIP(ctx, hipMalloc(&b->d_rec, sizeof(LevelAcc) * kMaxSlots * kMaxLevels));
-    MLMC_HIP(ctx, hipMalloc(&b->d_split, sizeof(unsigned) * kMaxSlots * kMaxLevels));
-    MLMC_HIP(ctx, hipMalloc(&b->d_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels));
-    MLMC_HIP(ctx, hipHostMalloc(&b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels));
+    hipError_t e = hipMalloc(&b->d_desc, sizeof(BatchDesc));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_desc, sizeof(BatchDesc));
+    if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(WorkItem) * kMaxItems);
+    if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(unsigned) * 4);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels * kSpread);
+    if (e == hipSuccess) e = hipMalloc(&b->d_rec, sizeof(LevelAcc) * kMaxSlots * kMaxLevels);
+    if (e == hipSuccess) e = hipMalloc(&b->d_split, sizeof(unsigned) * kMaxSlots * kMaxLevels);
+    if (e == hipSuccess) e = hipMalloc(&b->d_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels);
+    if (e == hipSuccess)
+        e = hipHostMalloc(&b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels);
+    if (e != hipSuccess) {
+        // An incomplete set is released so that the next call starts over.
+        free_persistent(ctx);
+        return hip_fail(ctx, e, "persistent batch allocation");
+    }
     return MLMC_OK;
 }
 

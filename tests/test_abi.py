@@ -26,6 +26,20 @@ def test_library_exports_every_declared_symbol():
     assert set(mlmc.EXPORTED) <= set(declared_symbols())
 
 
+def test_library_exports_nothing_undeclared():
+    import shutil
+    import subprocess
+    import pytest
+    from paper_1505_00965_amd import mlmc
+    if not shutil.which("nm"):
+        pytest.skip("nm is not installed")
+    out = subprocess.run(["nm", "-D", "--defined-only", mlmc.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines()
+                if ln.split()[-1].startswith("mlmc_") and " T " in ln}
+    assert exported == set(declared_symbols()), sorted(exported ^ set(declared_symbols()))
+
+
 def test_null_context_is_rejected_without_a_gpu():
     from paper_1505_00965_amd import mlmc
     lib = mlmc.lib()
