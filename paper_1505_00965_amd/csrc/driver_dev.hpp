@@ -112,6 +112,8 @@ __device__ __forceinline__ void driver_update_dev(DriverState* st)
     }
     if (st->iterations >= st->max_iterations) st->done = 1;
     if (st->done) {
+        // nothing more is sampled: a launch planned from this state is empty
+        for (int l = 0; l < kMaxLevels; ++l) st->dN[l] = 0.0;
         double est = 0.0, var = 0.0;
         double absE[kMaxLevels], Vr[kMaxLevels];
         for (int l = 0; l <= st->L; ++l) {
@@ -135,7 +137,9 @@ __device__ __forceinline__ void driver_update_dev(DriverState* st)
 // would dominate), updated by one lane, and written back.  The same words go
 // to the host's pinned mirror (if any): everything before the batch records
 // but `seq` first, then a system-scope fence, then `seq`, so a host that sees
-// the new `seq` sees the whole update.  With `spread` (kMaxLevels spread
+// the new `seq` sees the whole update.  Once the state is done the call
+// does nothing (no write, `seq` unchanged), so launches queued past the last
+// update are harmless.  With `spread` (kMaxLevels spread
 // groups, one per level) the block first folds each sampled level's group
 // into batch[l] (the sums of Y and Y^2 and the non-finite count), one wave
 // per level, and clears it.  Every thread of the block must call it; `s` is
@@ -152,6 +156,10 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
     unsigned long long* w = (unsigned long long*)&s;
     for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = src[i];
     __syncthreads();
+    // a finished run stays as it is (block-uniform: every thread reads the
+    // same LDS word after the barrier); nothing was sampled since, so the
+    // spread groups hold zeros
+    if (s.done) return;
     if (spread) {
         static_assert(kSpread == 64, "one lane per record of a group");
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -50,7 +50,7 @@ struct BatchDesc {
     const double* offset;
     LevelAcc* acc;                    // spread groups [slot][level][kSpread]
     WorkItem* items;
-    unsigned* head;                   // work dispenser
+    unsigned* head;                   // dispenser of the items past the first gridDim.x
     unsigned* count;                  // number of items
     unsigned resident_blocks;         // grid size of the sampler
     unsigned chunk;                   // blockDim * PPT of the sampler
@@ -60,37 +60,41 @@ struct BatchDesc {
     int num_cu;
 };
 
-// Plan: thread 0 sizes every (slot, level) pair's items and lays the pairs
-// out deepest level first; then the block writes the items in parallel.
+// Plan: the first wave sizes the (slot, level) pairs, one lane each, in
+// processing order (deepest level first, then slot), so the independent
+// global reads and the 64-bit divisions run side by side; a wave scan gives
+// each pair its first item, and the block then writes the items in parallel.
 // Every thread of the block must call it.
 __device__ __forceinline__ void plan_body(const BatchDesc* d)
 {
     constexpr int kPairs = kMaxSlots * kMaxLevels;
+    static_assert(kPairs == 64, "one lane of the first wave per (slot, level) pair");
     __shared__ uint64_t s_first[kPairs], s_left[kPairs], s_per[kPairs];
     __shared__ unsigned s_start[kPairs + 1];
     __shared__ int s_slot[kPairs], s_level[kPairs];
     __shared__ int s_npairs;
-    if (threadIdx.x == 0) {
-        const int L = d->L, M = d->M;
-        double total = 0.0;
-        for (int s = 0; s < d->nslots; ++s)
-            for (int l = 0; l <= L; ++l) {
-                const double nf = pow((double)M, (double)l);
-                total += d->dN[s * kMaxLevels + l] * (nf + (l ? nf / M : 0.0));
-            }
+    if (threadIdx.x < 64) {
+        const int L = d->L, M = d->M, nslots = d->nslots;
+        const int p = (int)threadIdx.x;
+        const bool valid = p < (L + 1) * nslots;
+        const int l = valid ? L - p / nslots : 0, s = valid ? p % nslots : 0;
+        double nf = 1.0;
+        for (int i = 0; i < l; ++i) nf *= M;   // M^l, exact
+        const double per = nf + (l ? nf / M : 0.0);
+        const double dn = valid ? d->dN[s * kMaxLevels + l] : 0.0;
+        // samples x steps over the batch (lane 0's sum: the rotations leave
+        // other lanes with other association orders)
+        const double total = __shfl(wave_sum(valid ? dn * per : 0.0), 0);
         const double target = total / ((double)d->resident_blocks * kItemsPerBlock);
-        unsigned count = 0;
-        int np = 0;
-        for (int l = L; l >= 0; --l) {          // deepest (longest) items first
-            const double nf = pow((double)M, (double)l);
-            const double per = nf + (l ? nf / M : 0.0);
-            for (int s = 0; s < d->nslots; ++s) {
-                const uint64_t left = (uint64_t)d->dN[s * kMaxLevels + l];
-                // lanes per path: the per-level launch's rule on the same count
-                const uint32_t G = split_lanes((int)nf, left, d->num_cu,
-                                               d->split_ok && d->payoff_kind[s] != kDigitalCond);
-                d->split[s * kMaxLevels + l] = G;
-                if (left == 0) continue;
+        const uint64_t left = (uint64_t)dn;
+        unsigned items = 0;
+        uint64_t per_item = 0;
+        if (valid) {
+            // lanes per path: the per-level launch's rule on the same count
+            const uint32_t G = split_lanes((int)nf, left, d->num_cu,
+                                           d->split_ok && d->payoff_kind[s] != kDigitalCond);
+            d->split[s * kMaxLevels + l] = G;
+            if (left) {
                 uint64_t paths = (uint64_t)(target / per);
                 if (G > 1) {
                     // split paths: whole block passes of block / G paths
@@ -104,21 +108,35 @@ __device__ __forceinline__ void plan_body(const BatchDesc* d)
                 if (paths > (1ull << 31)) paths = 1ull << 31;   // item counts fit 32 bits
                 // at most kItemsPerPair items per pair: the table never fills
                 const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
-                const uint64_t per_item = paths > min_items ? paths : min_items;
-                s_first[np] = (uint64_t)d->offset[s * kMaxLevels + l];
-                s_left[np] = left;
-                s_per[np] = per_item;
-                s_slot[np] = s;
-                s_level[np] = l;
-                s_start[np] = count;
-                count += (unsigned)((left + per_item - 1) / per_item);
-                ++np;
+                per_item = paths > min_items ? paths : min_items;
+                items = (unsigned)((left + per_item - 1) / per_item);
             }
         }
-        s_start[np] = count;
-        s_npairs = np;
-        *d->count = count;
-        *d->head = 0;
+        // exclusive scan of the item counts over the lanes (pair order)
+        unsigned incl = items;
+#pragma unroll
+        for (int k = 1; k < 64; k <<= 1) {
+            const unsigned v = __shfl_up(incl, k);
+            if (p >= k) incl += v;
+        }
+        // pairs with samples, packed in order
+        const uint64_t active = __ballot(items > 0);
+        const int rank = __popcll(active & ((1ull << p) - 1ull));
+        if (items) {
+            s_first[rank] = (uint64_t)d->offset[s * kMaxLevels + l];
+            s_left[rank] = left;
+            s_per[rank] = per_item;
+            s_slot[rank] = s;
+            s_level[rank] = l;
+            s_start[rank] = incl - items;
+        }
+        if (p == 63) {
+            const int np = __popcll(active);
+            s_start[np] = incl;
+            s_npairs = np;
+            *d->count = incl;
+            *d->head = 0;
+        }
     }
     __syncthreads();
     const int np = s_npairs;
@@ -230,19 +248,16 @@ __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, 
     }
 }
 
-// Take items from the dispenser until none are left; each item ends with a
-// block reduction into its (payoff, level) record.
+// Block b takes item b first; later items come from the dispenser until
+// none are left, so a launch with no more items than blocks (an empty one
+// included) makes no atomics on it.  Each item ends with a block reduction
+// into its (payoff, level) spread group.
 template <int MODEL, int M, int PPT>
 __device__ __forceinline__ void sample_items(const BatchDesc* d)
 {
     __shared__ unsigned s_item;
     const unsigned count = *d->count;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(d->head, 1u);
-        __syncthreads();
-        const unsigned it = s_item;
-        __syncthreads();
-        if (it >= count) break;
+    for (unsigned it = blockIdx.x; it < count;) {   // block-uniform
         const WorkItem w = d->items[it];
         double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
         unsigned nonfinite = 0;
@@ -256,6 +271,11 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d)
         if (w.level == 0) copy_y_sums(sums);
         block_reduce_add(sums, nonfinite, &d->acc[(w.slot * kMaxLevels + w.level) * kSpread +
                                                   (blockIdx.x & (kSpread - 1))]);
+        if (count <= gridDim.x) break;
+        if (threadIdx.x == 0) s_item = gridDim.x + atomicAdd(d->head, 1u);
+        __syncthreads();
+        it = s_item;
+        __syncthreads();
     }
 }
 
@@ -460,27 +480,43 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
         std::memcpy(b->run_key, key, sizeof(key));
     }
     hipGraphExec_t g = b->run_graph;
+    // Iteration k + 1 is enqueued before the host waits for iteration k's
+    // update: its plan reads the batch that update set from the device
+    // state, so the GPU runs the iterations back to back while the host reads
+    // the mirror.  The one launch past the last update finds the driver done
+    // and does nothing (no outstanding batch; the update leaves the state).
+    int first_tix = -1;
     for (int it = 0;; ++it) {
         if (it > h_st->max_iterations + 1)
             return fail(ctx, MLMC_EDEVICE, "driver state did not reach the host");
-        // the host copy holds the batch this launch samples (for timing only)
-        double fine = 0.0, coarse = 0.0;
-        for (int l = 0; l <= h_st->L; ++l) {
-            const double nf = std::pow((double)o.M, (double)l);
-            fine += h_st->dN[l] * nf;
-            coarse += l ? h_st->dN[l] * nf / o.M : 0.0;
+        for (int k = it ? 1 : 0; k < 2; ++k) {
+            const int tix = timed_begin(ctx, 16, 0.0, 0.0);
+            if (first_tix < 0) first_tix = tix;
+            const hipError_t e = hipGraphLaunch(g, ctx->stream);
+            timed_end(ctx, tix);
+            if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
         }
-        const int tix = timed_begin(ctx, 16, fine, coarse);
-        hipError_t e = hipGraphLaunch(g, ctx->stream);
-        timed_end(ctx, tix);
         // the update kernel inside the graph also writes the host mirror h_st
-        if (e == hipSuccess) e = wait_update(ctx->stream, h_st, (unsigned long long)it + 1);
+        const hipError_t e = wait_update(ctx->stream, h_st, (unsigned long long)it + 1);
         if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
+        // done is final: a later update that the host may already see leaves it set
         if (h_st->done) break;
     }
     const hipError_t e = hipStreamSynchronize(ctx->stream);
-    harvest_timing(ctx);
     if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
+    if (first_tix >= 0) {
+        // the launches' path steps are known only as a whole: every sampled
+        // batch is absorbed into n_l, so they are charged to the first entry
+        double fine = 0.0, coarse = 0.0;
+        for (int l = 0; l <= h_st->L; ++l) {
+            const double nf = std::pow((double)o.M, (double)l);
+            fine += h_st->n[l] * nf;
+            coarse += l ? h_st->n[l] * nf / o.M : 0.0;
+        }
+        ctx->pending[first_tix].fine_steps = fine;
+        ctx->pending[first_tix].coarse_steps = coarse;
+    }
+    harvest_timing(ctx);
     return MLMC_OK;
 }
 

@@ -95,6 +95,37 @@ def test_graph_run_variants_match_per_level_run(gctx, kind, scheme, pname):
         gctx.mlmc_run(gm, gp, 0.1, persistent=2)
 
 
+def test_graph_run_stopped_at_l_max_matches_per_level_run(gctx):
+    """Graph launches are queued one iteration ahead of the host; the launch
+    past the last update must leave the finished state as it is, also when
+    the run ends at L_max without passing the bias test."""
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    kw = dict(M=4, L_min=2, L_max=2, n_pilot=2000, seed=8, allow_notconv=True)
+    a = gctx.mlmc_run(gm, gp, 0.002, persistent=0, **kw)
+    b = gctx.mlmc_run(gm, gp, 0.002, persistent=1, **kw)
+    assert not a["converged"] and not b["converged"] and a["L"] == b["L"] == 2
+    assert a["N"] == b["N"] and a["iterations"] == b["iterations"]
+    # the two forms add the same samples in another order
+    for k in ("sum_y", "sum_y2"):
+        assert all(close(x, y, 1e-10) for x, y in zip(a[k], b[k])), k
+    assert close(a["estimate"], b["estimate"], 1e-10) and close(a["rmse_est"], b["rmse_est"], 1e-8)
+
+
+def test_graph_run_timing_counts_every_launch_and_step(gctx):
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    gctx.set_timing_slots([mlmc.STAT_PERSISTENT])
+    r = gctx.mlmc_run(gm, gp, 0.01, M=4, seed=5, persistent=1)
+    st = gctx.kernel_stats()[mlmc.STAT_PERSISTENT]
+    gctx.set_timing(False)
+    # one launch per update and the one queued past the last
+    assert st["launches"] == r["iterations"] + 1 and st["ms"] > 0
+    assert st["fine_steps"] == sum(n * 4**l for l, n in enumerate(r["N"]))
+    assert st["coarse_steps"] == sum(n * 4**(l - 1) for l, n in enumerate(r["N"]) if l)
+    # a second run starts from a fresh state
+    r2 = gctx.mlmc_run(gm, gp, 0.01, M=4, seed=5, persistent=1)
+    assert r2["N"] == r["N"] and close(r2["estimate"], r["estimate"], 1e-12)
+
+
 def test_batch_bad_args(gctx):
     gm = mlmc.model(**W.GBM_MODEL)
     with pytest.raises(mlmc.MLMCError):
