@@ -20,7 +20,10 @@
  *     context's device; all others are host pointers.
  *   - a context is not thread-safe: use one per host thread.  Calls are
  *     enqueued on the context's stream (mlmc_set_stream) and synchronise it
- *     before returning results to host memory.
+ *     before returning results to host memory, except mlmc_run: it returns
+ *     once the device has published the final driver state (with kernel
+ *     timing off, work of its own that changes nothing may still be queued;
+ *     later work on the stream is ordered after it).
  *   - random numbers: Philox4x32-10 keyed by the 64-bit seed; sample s of
  *     level l is a pure function of (seed, l, s), so results do not depend on
  *     the launch configuration except for the order of FP64 atomic additions

@@ -62,10 +62,9 @@ __global__ void driver_update_kernel(DriverState* st, DriverState* mirror, Level
 // error.
 hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long long want)
 {
-    const volatile unsigned long long* seq = &h->seq;
     auto next_poll = std::chrono::steady_clock::now() + std::chrono::milliseconds(1);
     for (;;) {
-        if (*seq >= want) {
+        if (mirror_updates(h) >= want) {
             std::atomic_thread_fence(std::memory_order_acquire);
             return hipSuccess;
         }
@@ -75,7 +74,7 @@ hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long l
             const hipError_t e = hipStreamQuery(stream);
             if (e == hipSuccess) {
                 std::atomic_thread_fence(std::memory_order_acquire);
-                return *seq >= want ? hipSuccess : hipErrorUnknown;
+                return mirror_updates(h) >= want ? hipSuccess : hipErrorUnknown;
             }
             if (e != hipErrorNotReady) return e;
         }
@@ -226,10 +225,14 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
             MLMC_HIP(ctx, launch_driver_update(d, (DriverState*)ctx->h_drv_dev, ctx->d_drv_spread,
                                                ctx->stream, t0, t1));
             MLMC_HIP(ctx, wait_update(ctx->stream, h, (unsigned long long)it + 1));
-            if (h->done) break;
+            if (mirror_done(h)) break;
         }
-        MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        harvest_timing(ctx);
+        // the mirror holds the final state; the stream is waited for only to
+        // read timing events (later work on it is ordered after this run)
+        if (!ctx->pending.empty()) {
+            MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            harvest_timing(ctx);
+        }
     }
     const auto t1 = std::chrono::steady_clock::now();
     std::memset(out, 0, sizeof(*out));

@@ -34,9 +34,20 @@ struct DriverState {
     // persistent form: work table bookkeeping (persistent.hip)
     unsigned int work_head, work_count;
     unsigned int pad0, pad1;
-    // number of updates published to the host mirror (written there last)
+    // number of updates; the host mirror holds 2 seq + done, written last
     unsigned long long seq;
     LevelAcc batch[kMaxLevels];
 };
+
+// Host side: the update count and the done flag as the mirror's last
+// written word publishes them (the mirror words of that update are complete).
+inline unsigned long long mirror_updates(const DriverState* h)
+{
+    return *(const volatile unsigned long long*)&h->seq >> 1;
+}
+inline bool mirror_done(const DriverState* h)
+{
+    return (*(const volatile unsigned long long*)&h->seq & 1ull) != 0;
+}
 
 }  // namespace mlmc

@@ -136,8 +136,9 @@ __device__ __forceinline__ void driver_update_dev(DriverState* st)
 // the state, so the state is staged in LDS (a global round trip per access
 // would dominate), updated by one lane, and written back.  The same words go
 // to the host's pinned mirror (if any): everything before the batch records
-// but `seq` first, then a system-scope fence, then `seq`, so a host that sees
-// the new `seq` sees the whole update.  Once the state is done the call
+// but `seq` first, then a system-scope fence, then `seq` (there 2 x the
+// update count + the done flag), so a host that sees the new word sees the
+// whole update, and the done flag of that same update.  Once the state is done the call
 // does nothing (no write, `seq` unchanged), so launches queued past the last
 // update are harmless.  With `spread` (kMaxLevels spread
 // groups, one per level) the block first folds each sampled level's group
@@ -197,7 +198,8 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
             if (i != kSeq) h[i] = w[i];
         __threadfence_system();
         __syncthreads();
-        if (threadIdx.x == 0) h[kSeq] = w[kSeq];
+        // the published word carries the done flag beside the update count
+        if (threadIdx.x == 0) h[kSeq] = 2ull * w[kSeq] + (s.done ? 1ull : 0ull);
     }
     unsigned long long* dst = (unsigned long long*)st;
     for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = w[i];

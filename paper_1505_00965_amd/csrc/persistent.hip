@@ -325,6 +325,8 @@ struct PersistentBufs {
     int graph_key[5] = {-1, -1, -1, -1, -1};
     hipGraphExec_t run_graph = nullptr;   // cached driver-iteration graph
     int run_key[5] = {-1, -1, -1, -1, -1};
+    BatchDesc last_desc;              // the bytes of the last descriptor upload
+    bool last_ok = false;
 };
 
 static PersistentBufs* bufs_of(mlmc_ctx* ctx);
@@ -418,6 +420,20 @@ static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const ml
     h->block = (unsigned)s.block;
 }
 
+// Copy the host descriptor to the device unless the last upload from this
+// context carried the same bytes (repeated runs of one problem skip it).
+static mlmc_status upload_desc(mlmc_ctx* ctx, PersistentBufs* b)
+{
+    if (b->last_ok && std::memcmp(&b->last_desc, b->h_desc, sizeof(BatchDesc)) == 0)
+        return MLMC_OK;
+    b->last_ok = false;
+    MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
+                                 ctx->stream));
+    std::memcpy(&b->last_desc, b->h_desc, sizeof(BatchDesc));
+    b->last_ok = true;
+    return MLMC_OK;
+}
+
 // Capture [prologue?] -> plan -> persistent -> [epilogue] into a graph.
 static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
                            DriverState* driver, hipGraphExec_t* out)
@@ -466,13 +482,15 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     auto* b = bufs_of(ctx);
     fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, o.seed, d_st->dN, d_st->n,
               ctx->d_drv_spread);
-    MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
-                                 ctx->stream));
+    st = upload_desc(ctx, b);
+    if (st) return st;
     // the graph reads the descriptor, the driver state and its mirror at
     // replay, all fixed per context: one capture serves every run
     const PersistentShape s = persistent_shape(ctx);
     const int key[5] = {sampler_variant(m), o.M, s.block, s.ppt, s.blocks_per_cu};
     if (!b->run_graph || std::memcmp(key, b->run_key, sizeof(key)) != 0) {
+        // an earlier run may return with its last (empty) launch queued
+        MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
         if (b->run_graph) hipGraphExecDestroy(b->run_graph);
         b->run_graph = nullptr;
         st = capture(ctx, sampler_variant(m), o.M, false, d_st, &b->run_graph);
@@ -499,9 +517,13 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
         // the update kernel inside the graph also writes the host mirror h_st
         const hipError_t e = wait_update(ctx->stream, h_st, (unsigned long long)it + 1);
         if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
-        // done is final: a later update that the host may already see leaves it set
-        if (h_st->done) break;
+        // the flag comes in the word that publishes the update, so a mirror
+        // seen done is complete; later updates leave it as it is
+        if (mirror_done(h_st)) break;
     }
+    // the launch past the last update may still run: the result is read from
+    // the mirror, and the stream is waited for only to read timing events
+    if (ctx->pending.empty()) return MLMC_OK;
     const hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
     if (first_tix >= 0) {
@@ -542,6 +564,9 @@ mlmc_status mlmc_set_persistent_launch(mlmc_ctx* ctx, int block, int ppt, int bl
         ctx->persist_bpc = blocks_per_cu;
     }
     if (auto* b = bufs_of(ctx)) {
+        // a run may have returned with its last (empty) launch queued
+        MLMC_HIP(ctx, hipSetDevice(ctx->device));
+        MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
         if (b->graph) hipGraphExecDestroy(b->graph);
         if (b->run_graph) hipGraphExecDestroy(b->run_graph);
         b->graph = b->run_graph = nullptr;
@@ -586,8 +611,8 @@ mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc
               b->d_req + kMaxSlots * kMaxLevels, b->d_acc);
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_req, b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels,
                                  hipMemcpyHostToDevice, ctx->stream));
-    MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
-                                 ctx->stream));
+    st = upload_desc(ctx, b);
+    if (st) return st;
     const PersistentShape s = persistent_shape(ctx);
     const int key[5] = {sampler_variant(*model), M, s.block, s.ppt, s.blocks_per_cu};
     if (!b->graph || std::memcmp(key, b->graph_key, sizeof(key)) != 0) {

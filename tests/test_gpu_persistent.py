@@ -126,6 +126,32 @@ def test_graph_run_timing_counts_every_launch_and_step(gctx):
     assert r2["N"] == r["N"] and close(r2["estimate"], r["estimate"], 1e-12)
 
 
+def test_graph_runs_between_batches_and_shape_changes(gctx):
+    """The device descriptor is uploaded only when it changes and a run may
+    return with an empty launch still queued: runs interleaved with batches
+    (another descriptor) and with a new persistent shape (a new graph) must
+    reproduce the first run."""
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.ASIAN)
+    ref = gctx.mlmc_run(gm, gp, 0.02, M=4, seed=9, persistent=1)
+    again = gctx.mlmc_run(gm, gp, 0.02, M=4, seed=9, persistent=1)
+    pays = [mlmc.payoff(**W.CALL), mlmc.payoff(**W.DIGITAL)]
+    batch = gctx.mlmc_levels_batch(gm, pays, 4, 2, [[3000, 300, 30]] * 2, seed=9)
+    after_batch = gctx.mlmc_run(gm, gp, 0.02, M=4, seed=9, persistent=1)
+    gctx.set_persistent_launch(128, 2, 8)
+    try:
+        reshaped = gctx.mlmc_run(gm, gp, 0.02, M=4, seed=9, persistent=1)
+    finally:
+        gctx.set_persistent_launch(0, 0, 0)
+    batch2 = gctx.mlmc_levels_batch(gm, pays, 4, 2, [[3000, 300, 30]] * 2, seed=9)
+    for r in (again, after_batch, reshaped):
+        assert r["N"] == ref["N"] and r["L"] == ref["L"]
+        assert close(r["estimate"], ref["estimate"], 1e-10)
+    for k in range(2):
+        for l in range(3):
+            assert batch[k][l]["n"] == batch2[k][l]["n"]
+            assert close(batch[k][l]["sum_y"], batch2[k][l]["sum_y"], 1e-10)
+
+
 def test_batch_bad_args(gctx):
     gm = mlmc.model(**W.GBM_MODEL)
     with pytest.raises(mlmc.MLMCError):
