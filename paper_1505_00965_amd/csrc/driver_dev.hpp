@@ -1,5 +1,5 @@
-// Device arithmetic of the adaptive MLMC driver (shared by the update
-// kernel and the device-resident run loop).
+// Device arithmetic of the adaptive MLMC driver (the update kernel and the
+// optimal-N entry point).
 //
 // The paper fixes the estimator Y = sum_l Yhat_l (eq. (eq:mlmc:ident)), that
 // level variances add (Sec. 5), the cost measure (Sec. 3), and leaves N_l to
@@ -49,92 +49,175 @@ __device__ inline double fit_rate_dev(int L, const double* y, int M)
     return (n * sxy - sx * sy) / (n * sxx - sx * sx);
 }
 
-// Absorb the batch, re-plan.  One thread; a handful of fp64 operations.
-__device__ __forceinline__ void driver_update_dev(DriverState* st)
+// Value of lane l (wave-uniform l) of a per-lane double.
+__device__ __forceinline__ double lane_f64(double v, int l)
 {
-    const int M = st->M;
-    const double Ma = st->Ma, Mb = st->Mb;
-    int L = st->L;
-    for (int l = 0; l <= L; ++l) {
-        if (st->dN[l] > 0) {
-            st->sum1[l] += st->batch[l].sum[0];
-            st->sum2[l] += st->batch[l].sum[1];
-            st->n[l] += st->dN[l];
-            st->n_nonfinite += st->batch[l].n_nonfinite;
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// sum_{k <= L} v_k in level order (the order of the one-lane loops above),
+// so every sum over levels rounds as optimal_n_dev and fit_rate_dev round it.
+__device__ __forceinline__ double ordered_sum(double v, int L)
+{
+    double t = 0.0;
+    for (int k = 0; k <= L; ++k) t += lane_f64(v, k);
+    return t;
+}
+
+// Absorb the batch, re-plan: the first wave of the block, lane l holding
+// level l.  The per-level formulas run side by side; what couples levels
+// (the floors from the level below, the sums over levels, the bias test)
+// takes the levels in order, so every result is the one-lane loop's, bit
+// for bit.  `s` is the block's LDS copy of the state; all 64 lanes call it.
+__device__ __forceinline__ void driver_update_wave(DriverState& s)
+{
+    static_assert(kMaxLevels <= 64, "one lane per level");
+    const int lane = (int)(threadIdx.x & 63);
+    const int li = lane < kMaxLevels ? lane : kMaxLevels - 1;   // in-bounds index
+    const int M = s.M;
+    const double Ma = s.Ma, Mb = s.Mb, eps = s.eps;
+    const int L0 = __builtin_amdgcn_readfirstlane(s.L);   // the same word in every lane
+    bool in = lane <= L0;
+    double n = s.n[li], dN = s.dN[li], sum1 = s.sum1[li], sum2 = s.sum2[li];
+    double E = s.E[li], V = s.V[li], C = s.C[li], Nopt = s.Nopt[li];
+    // absorb the batch (every level's record is cleared)
+    unsigned long long nonfinite = 0;
+    if (in && dN > 0) {
+        sum1 += s.batch[li].sum[0];
+        sum2 += s.batch[li].sum[1];
+        n += dN;
+        nonfinite = s.batch[li].n_nonfinite;
+    }
+    if (in) dN = 0.0;
+    // estimates, then the floors from the level below (l >= 2, in order)
+    double m = 0.0;
+    if (in) {
+        C = level_cost_dev(lane, M, s.antithetic);
+        m = sum1 / n;
+        E = fabs(m);
+        V = sum2 / n - m * m;
+        if (V < 0) V = 0;
+    }
+    for (int l = 2; l <= L0; ++l) {
+        const double Ep = lane_f64(E, l - 1), Vp = lane_f64(V, l - 1);
+        if (lane == l) {
+            if (E < Ep / Ma) E = Ep / Ma;
+            if (V < Vp / Mb) V = Vp / Mb;
         }
-        for (int k = 0; k < kNumSums; ++k) st->batch[l].sum[k] = 0.0;
-        st->batch[l].n_nonfinite = 0;
-        st->dN[l] = 0.0;
     }
-    st->iterations += 1;
-    for (int l = 0; l <= L; ++l) {
-        st->C[l] = level_cost_dev(l, M, st->antithetic);
-        const double m = st->sum1[l] / st->n[l];
-        st->E[l] = fabs(m);
-        st->V[l] = st->sum2[l] / st->n[l] - m * m;
-        if (st->V[l] < 0) st->V[l] = 0;
+    // optimal N_l, the outstanding batch
+    double total = ordered_sum(in ? sqrt(V * C) : 0.0, L0);
+    if (in) Nopt = ceil(2.0 / (eps * eps) * sqrt(V / C) * total);
+    if (in) {
+        const double d = Nopt - n;
+        dN = (d > 0.01 * n) ? d : 0.0;
     }
-    for (int l = 2; l <= L; ++l) {
-        if (st->E[l] < st->E[l - 1] / Ma) st->E[l] = st->E[l - 1] / Ma;
-        if (st->V[l] < st->V[l - 1] / Mb) st->V[l] = st->V[l - 1] / Mb;
-    }
-    optimal_n_dev(L, st->V, st->C, st->eps, st->Nopt);
-    int more = 0;
-    for (int l = 0; l <= L; ++l) {
-        const double d = st->Nopt[l] - st->n[l];
-        st->dN[l] = (d > 0.01 * st->n[l]) ? d : 0.0;
-        if (st->dN[l] > 0) more = 1;
-    }
+    const bool more = __ballot(in && dN > 0) != 0;
+    int L = L0;
+    int done = s.done, converged = s.converged;
     if (!more) {
-        const double rem = fmax(st->E[L], st->E[L - 1] / Ma) / (Ma - 1.0);
-        st->bias_est = rem;
-        if (rem <= st->eps / sqrt(2.0)) {
-            st->converged = 1;
-            st->done = 1;
-        } else if (L == st->L_max) {
-            st->done = 1;
+        const double EL = lane_f64(E, L), EL1 = lane_f64(E, L - 1);
+        const double rem = fmax(EL, EL1 / Ma) / (Ma - 1.0);
+        if (lane == 0) s.bias_est = rem;
+        if (rem <= eps / sqrt(2.0)) {
+            converged = 1;
+            done = 1;
+        } else if (L == __builtin_amdgcn_readfirstlane(s.L_max)) {
+            done = 1;
         } else {
+            const double VL = lane_f64(V, L);
             ++L;
-            st->V[L] = st->V[L - 1] / Mb;
-            st->E[L] = st->E[L - 1] / Ma;
-            st->C[L] = level_cost_dev(L, M, st->antithetic);
-            st->n[L] = 0;
-            st->sum1[L] = 0;
-            st->sum2[L] = 0;
-            optimal_n_dev(L, st->V, st->C, st->eps, st->Nopt);
-            for (int l = 0; l <= L; ++l) {
-                const double d = st->Nopt[l] - st->n[l];
-                st->dN[l] = (l == L) ? (st->Nopt[l] > 1 ? st->Nopt[l] : 1.0)
-                                     : ((d > 0.01 * st->n[l]) ? d : 0.0);
+            in = lane <= L;
+            if (lane == L) {
+                V = VL / Mb;
+                E = EL / Ma;
+                C = level_cost_dev(L, M, s.antithetic);
+                n = 0;
+                sum1 = 0;
+                sum2 = 0;
             }
-            st->L = L;
+            total = ordered_sum(in ? sqrt(V * C) : 0.0, L);
+            if (in) {
+                Nopt = ceil(2.0 / (eps * eps) * sqrt(V / C) * total);
+                const double d = Nopt - n;
+                dN = (lane == L) ? (Nopt > 1 ? Nopt : 1.0) : ((d > 0.01 * n) ? d : 0.0);
+            }
         }
     }
-    if (st->iterations >= st->max_iterations) st->done = 1;
-    if (st->done) {
+    const int iterations = s.iterations + 1;
+    if (iterations >= s.max_iterations) done = 1;
+    // the non-finite counts of the absorbed levels, in any order (integers)
+    unsigned long long nf_total = 0;
+    for (int l = 0; l <= L0; ++l)
+        nf_total += ((unsigned long long)__builtin_amdgcn_readlane((unsigned)(nonfinite >> 32), l) << 32) |
+                    __builtin_amdgcn_readlane((unsigned)nonfinite, l);
+    if (done) {
         // nothing more is sampled: a launch planned from this state is empty
-        for (int l = 0; l < kMaxLevels; ++l) st->dN[l] = 0.0;
-        double est = 0.0, var = 0.0;
-        double absE[kMaxLevels], Vr[kMaxLevels];
-        for (int l = 0; l <= st->L; ++l) {
-            const double m = st->sum1[l] / st->n[l];
-            est += m;
-            const double v = st->sum2[l] / st->n[l] - m * m;
-            var += (v > 0 ? v : 0) / st->n[l];
-            absE[l] = fabs(m);
-            Vr[l] = v;
+        dN = 0.0;
+        const double mr = in ? sum1 / n : 0.0;
+        const double v = in ? sum2 / n - mr * mr : 0.0;
+        const double est = ordered_sum(mr, L);
+        const double var = ordered_sum(in ? (v > 0 ? v : 0) / n : 0.0, L);
+        // fitted rates over l = 1..L of |E_l|, V_l and C_l
+        const double lm = log((double)M);
+        double rate[3];
+        for (int f = 0; f < 3; ++f) {
+            const double y = f == 0 ? fabs(mr) : (f == 1 ? v : C);
+            const bool use = in && lane >= 1 && y > 0;
+            const double vy = use ? log(y) / lm : 0.0;
+            const unsigned long long used = __ballot(use);
+            double sx = 0, sy = 0, sxx = 0, sxy = 0;
+            int cnt = 0;
+            for (int l = 1; l <= L; ++l) {
+                if (!((used >> l) & 1ull)) continue;
+                const double x = l, w = lane_f64(vy, l);
+                sx += x; sy += w; sxx += x * x; sxy += x * w; ++cnt;
+            }
+            rate[f] = cnt < 2 ? nan("") : (cnt * sxy - sx * sy) / (cnt * sxx - sx * sx);
         }
-        st->estimate = est;
-        st->var_est = var;
-        st->alpha_fit = -fit_rate_dev(st->L, absE, M);
-        st->beta_fit = -fit_rate_dev(st->L, Vr, M);
-        st->gamma_fit = fit_rate_dev(st->L, st->C, M);
+        if (lane == 0) {
+            s.estimate = est;
+            s.var_est = var;
+            s.alpha_fit = -rate[0];
+            s.beta_fit = -rate[1];
+            s.gamma_fit = rate[2];
+        }
+    }
+    // write back: every level the update touched (the finished state has
+    // no outstanding batch on any level)
+    if (lane < kMaxLevels) {
+        if (lane <= L) {
+            s.n[lane] = n;
+            s.sum1[lane] = sum1;
+            s.sum2[lane] = sum2;
+            s.E[lane] = E;
+            s.V[lane] = V;
+            s.C[lane] = C;
+            s.Nopt[lane] = Nopt;
+        }
+        if (lane <= L || done) s.dN[lane] = lane <= L ? dN : 0.0;
+        if (lane <= L0) {
+#pragma unroll
+            for (int k = 0; k < kNumSums; ++k) s.batch[lane].sum[k] = 0.0;
+            s.batch[lane].n_nonfinite = 0;
+        }
+    }
+    if (lane == 0) {
+        s.n_nonfinite += nf_total;
+        s.iterations = iterations;
+        s.L = L;
+        s.done = done;
+        s.converged = converged;
     }
 }
 
-// The update is a serial chain of a few hundred dependent fp64 operations on
-// the state, so the state is staged in LDS (a global round trip per access
-// would dominate), updated by one lane, and written back.  The same words go
+// The update is a chain of a few hundred dependent fp64 operations on the
+// state, so the state is staged in LDS (a global round trip per access
+// would dominate), updated by the first wave (one lane per level), and
+// written back.  The same words go
 // to the host's pinned mirror (if any): everything before the batch records
 // but `seq` first, then a system-scope fence, then `seq` (there 2 x the
 // update count + the done flag), so a host that sees the new word sees the
@@ -182,10 +265,8 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        driver_update_dev(&s);
-        s.seq += 1;
-    }
+    if (threadIdx.x < 64) driver_update_wave(s);
+    if (threadIdx.x == 0) s.seq += 1;
     __syncthreads();
     // the host waits for the mirror: publish it first; the device copy is
     // read by the next update only, which the stream orders after this one
