@@ -27,6 +27,9 @@ struct mlmc_ctx {
     void* h_drv_dev = nullptr;    // the same memory as the device sees it
     // spread groups of the per-level launches, one per level (driver.hip)
     mlmc::LevelAcc* d_drv_spread = nullptr;
+    // the groups are known to hold zeros: the last run ended normally (its
+    // updates folded and cleared every group it used)
+    bool drv_clean = false;
     double* d_tmp = nullptr;                // small fp64 scratch (optimal_n)
     double* h_tmp = nullptr;
     // kernel timing (mlmc_set_timing)

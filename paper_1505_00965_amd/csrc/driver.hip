@@ -23,37 +23,21 @@ __global__ void optimal_n_kernel(int L, const double* V, const double* C, double
 // A fresh state: zeros, the configuration, n_pilot outstanding samples on
 // levels 0..L_min (the host mirror is filled the same way on the host); the
 // per-level spread groups cleared.
-__global__ void driver_init_kernel(DriverState* st, LevelAcc* spread, double eps, double alpha,
-                                   double beta, double Ma, double Mb, int M, int antithetic,
-                                   int L_min, int L_max, int max_iterations, double n_pilot)
+__global__ void driver_init_kernel(DriverState* st, LevelAcc* spread, DriverInit c)
 {
-    static_assert(sizeof(DriverState) % 8 == 0, "state is cleared in 8-byte words");
-    unsigned long long* w = (unsigned long long*)st;
-    for (int i = threadIdx.x; i < (int)(sizeof(DriverState) / 8); i += blockDim.x) w[i] = 0ull;
     unsigned long long* g = (unsigned long long*)spread;
     constexpr int kSpreadWords = kMaxLevels * kSpread * (int)sizeof(LevelAcc) / 8;
     for (int i = threadIdx.x; i < kSpreadWords; i += blockDim.x) g[i] = 0ull;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        st->eps = eps;
-        st->alpha = alpha;
-        st->beta = beta;
-        st->Ma = Ma;
-        st->Mb = Mb;
-        st->M = M;
-        st->antithetic = antithetic;
-        st->L_min = L_min;
-        st->L_max = L_max;
-        st->max_iterations = max_iterations;
-        st->L = L_min;
-        for (int l = 0; l <= L_min; ++l) st->dN[l] = n_pilot;
-    }
+    init_state(*st, c);
 }
 
-__global__ void driver_update_kernel(DriverState* st, DriverState* mirror, LevelAcc* spread)
+// has_init: the run's first update, which builds the state itself (the
+// spread groups hold the pilot's sums and nothing else).
+__global__ void driver_update_kernel(DriverState* st, DriverState* mirror, LevelAcc* spread,
+                                     DriverInit c, int has_init)
 {
     __shared__ DriverState s;
-    driver_update_block(st, mirror, s, spread);
+    driver_update_block(st, mirror, s, spread, has_init ? &c : nullptr);
 }
 
 // Wait until the host mirror shows update number `want`.  Spinning on the
@@ -82,13 +66,17 @@ hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long l
 }
 
 hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* spread,
-                                hipStream_t stream, hipEvent_t start, hipEvent_t stop)
+                                hipStream_t stream, hipEvent_t start, hipEvent_t stop,
+                                const DriverInit* init)
 {
+    const DriverInit c = init ? *init : DriverInit{};
+    const int has_init = init ? 1 : 0;
     if (start || stop)
         hipExtLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, start, stop, 0, st,
-                              mirror, spread);
+                              mirror, spread, c, has_init);
     else
-        hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror, spread);
+        hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror, spread, c,
+                           has_init);
     return hipGetLastError();
 }
 
@@ -198,11 +186,30 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     for (int l = 0; l <= o.L_min; ++l) h->dN[l] = (double)o.n_pilot;
     // the device copy from the same few values (a launch costs the host less
     // than a host-to-device copy of the whole state)
-    hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d,
-                       ctx->d_drv_spread, h->eps, h->alpha,
-                       h->beta, h->Ma, h->Mb, h->M, h->antithetic, h->L_min, h->L_max, h->max_iterations,
-                       (double)o.n_pilot);
-    MLMC_HIP(ctx, hipGetLastError());
+    DriverInit init;
+    init.eps = h->eps;
+    init.alpha = h->alpha;
+    init.beta = h->beta;
+    init.Ma = h->Ma;
+    init.Mb = h->Mb;
+    init.n_pilot = (double)o.n_pilot;
+    init.M = h->M;
+    init.antithetic = h->antithetic;
+    init.L_min = h->L_min;
+    init.L_max = h->L_max;
+    init.max_iterations = h->max_iterations;
+    init.pad = 0;
+    // The per-level form lets its first update build the state when the
+    // spread groups are known to hold zeros (one launch fewer on the pilot's
+    // path); otherwise, and for the graph form, a kernel clears both first.
+    // Until this run ends normally the groups are not known to be clear.
+    const bool fused_init = ctx->drv_clean && !o.persistent;
+    ctx->drv_clean = false;
+    if (!fused_init) {
+        hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d,
+                           ctx->d_drv_spread, init);
+        MLMC_HIP(ctx, hipGetLastError());
+    }
     if (o.persistent) {
         st = run_persistent(ctx, *model, *payoff, o, d, h);
         if (st) return st;
@@ -226,7 +233,8 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
             hipEvent_t t0, t1;
             timed_kernel(ctx, 17, 0.0, 0.0, &t0, &t1);
             MLMC_HIP(ctx, launch_driver_update(d, (DriverState*)ctx->h_drv_dev, ctx->d_drv_spread,
-                                               ctx->stream, t0, t1));
+                                               ctx->stream, t0, t1,
+                                               (it == 0 && fused_init) ? &init : nullptr));
             MLMC_HIP(ctx, wait_update(ctx->stream, h, (unsigned long long)it + 1));
             if (mirror_done(h)) break;
         }
@@ -237,6 +245,7 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
             harvest_timing(ctx);
         }
     }
+    ctx->drv_clean = true;
     const auto t1 = std::chrono::steady_clock::now();
     std::memset(out, 0, sizeof(*out));
     out->estimate = h->estimate;

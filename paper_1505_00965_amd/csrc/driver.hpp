@@ -39,6 +39,21 @@ struct DriverState {
     LevelAcc batch[kMaxLevels];
 };
 
+// Configuration of a fresh state (n_pilot outstanding samples on levels
+// 0..L_min); passed by value to the kernel that builds the state.
+struct DriverInit {
+    double eps, alpha, beta, Ma, Mb, n_pilot;
+    int M, antithetic, L_min, L_max, max_iterations, pad;
+};
+
+// One update launch (driver.hip): with `init`, the run's first update, which
+// builds the state itself; start/stop stamp the kernel when both are given.
+hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* spread,
+                                hipStream_t stream, hipEvent_t start = nullptr,
+                                hipEvent_t stop = nullptr, const DriverInit* init = nullptr);
+// Wait until the host mirror shows update number `want` (driver.hip).
+hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long long want);
+
 // Host side: the update count and the done flag as the mirror's last
 // written word publishes them (the mirror words of that update are complete).
 inline unsigned long long mirror_updates(const DriverState* h)

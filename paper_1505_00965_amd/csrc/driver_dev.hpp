@@ -49,6 +49,31 @@ __device__ inline double fit_rate_dev(int L, const double* y, int M)
     return (n * sxy - sx * sy) / (n * sxx - sx * sx);
 }
 
+// A fresh state in `s` (global or LDS): zeros, the configuration, the pilot
+// batch.  Every thread of the block must call it; it ends with a barrier.
+__device__ __forceinline__ void init_state(DriverState& s, const DriverInit& c)
+{
+    static_assert(sizeof(DriverState) % 8 == 0, "state is cleared in 8-byte words");
+    unsigned long long* w = (unsigned long long*)&s;
+    for (int i = threadIdx.x; i < (int)(sizeof(DriverState) / 8); i += blockDim.x) w[i] = 0ull;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s.eps = c.eps;
+        s.alpha = c.alpha;
+        s.beta = c.beta;
+        s.Ma = c.Ma;
+        s.Mb = c.Mb;
+        s.M = c.M;
+        s.antithetic = c.antithetic;
+        s.L_min = c.L_min;
+        s.L_max = c.L_max;
+        s.max_iterations = c.max_iterations;
+        s.L = c.L_min;
+        for (int l = 0; l <= c.L_min; ++l) s.dN[l] = c.n_pilot;
+    }
+    __syncthreads();
+}
+
 // Value of lane l (wave-uniform l) of a per-lane double.
 __device__ __forceinline__ double lane_f64(double v, int l)
 {
@@ -226,10 +251,12 @@ __device__ __forceinline__ void driver_update_wave(DriverState& s)
 // update are harmless.  With `spread` (kMaxLevels spread
 // groups, one per level) the block first folds each sampled level's group
 // into batch[l] (the sums of Y and Y^2 and the non-finite count), one wave
-// per level, and clears it.  Every thread of the block must call it; `s` is
+// per level, and clears it.  With `init` the state is built fresh in `s`
+// instead of read (the first update of a run whose groups hold only the
+// pilot's sums).  Every thread of the block must call it; `s` is
 // the block's LDS copy of the state.
 __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s,
-                                                    LevelAcc* spread)
+                                                    LevelAcc* spread, const DriverInit* init = nullptr)
 {
     static_assert(sizeof(DriverState) % 8 == 0, "state is copied in 8-byte words");
     static_assert(offsetof(DriverState, seq) % 8 == 0, "seq is one word");
@@ -238,8 +265,12 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
     constexpr int kSeq = offsetof(DriverState, seq) / 8;
     const unsigned long long* src = (const unsigned long long*)st;
     unsigned long long* w = (unsigned long long*)&s;
-    for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = src[i];
-    __syncthreads();
+    if (init) {
+        init_state(s, *init);    // the run's first update: a fresh state
+    } else {
+        for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = src[i];
+        __syncthreads();
+    }
     // a finished run stays as it is (block-uniform: every thread reads the
     // same LDS word after the barrier); nothing was sampled since, so the
     // spread groups hold zeros

@@ -305,10 +305,6 @@ static PersistentFn pick_persistent(int variant, int M, int ppt)
     return M == 2 ? pick_ppt<kHeston, 2>(ppt) : pick_ppt<kHeston, 4>(ppt);
 }
 
-hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* spread,
-                                hipStream_t stream, hipEvent_t start = nullptr,
-                                hipEvent_t stop = nullptr);
-hipError_t wait_update(hipStream_t stream, const DriverState* h, unsigned long long want);
 
 // Device buffers of the persistent form, owned by the context.
 struct PersistentBufs {

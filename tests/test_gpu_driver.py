@@ -118,3 +118,27 @@ def test_timed_runs_give_the_untimed_results(gctx, persistent):
         for a, b in zip(runs[0], rs):
             assert a["N"] == b["N"] and a["L"] == b["L"]
             assert abs(a["estimate"] - b["estimate"]) <= 1e-12 * abs(a["estimate"])
+
+
+def test_first_run_of_a_context_equals_later_runs():
+    """A context's first run clears the driver state and spread groups with
+    a kernel; later runs (after a normal end) let the first update build the
+    state.  Both must give the same run, also after runs of other shapes and
+    after a run that stopped with an error."""
+    from paper_1505_00965_amd import mlmc as m_
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    ctx = m_.Context(0)
+    try:
+        first = ctx.mlmc_run(gm, gp, 0.01, M=4, seed=12)
+        others = [ctx.mlmc_run(gm, mlmc.payoff(**W.ASIAN), 0.02, M=2, seed=3),
+                  ctx.mlmc_run(gm, gp, 0.005, M=4, seed=5, persistent=1)]
+        with pytest.raises(mlmc.MLMCError):
+            ctx.mlmc_run(gm, gp, 0.002, M=4, L_min=2, L_max=2, n_pilot=2000)   # ENOTCONV
+        again = [ctx.mlmc_run(gm, gp, 0.01, M=4, seed=12) for _ in range(2)]
+    finally:
+        ctx.close()
+    assert all(o["converged"] for o in others)
+    for r in again:
+        assert r["N"] == first["N"] and r["L"] == first["L"]
+        assert r["iterations"] == first["iterations"]
+        assert abs(r["estimate"] - first["estimate"]) <= 1e-12 * abs(first["estimate"])
