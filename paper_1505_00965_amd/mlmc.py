@@ -86,14 +86,14 @@ class RunResult(C.Structure):
                 ("gamma", C.c_double), ("cost", C.c_double), ("n_nonfinite", C.c_uint64)]
 
     def as_dict(self):
-        L = self.L
-        d = {k: getattr(self, k) for k in ("estimate", "rmse_est", "wall_s", "L", "converged",
-                                           "iterations", "alpha", "beta", "gamma", "cost",
-                                           "n_nonfinite")}
-        d["converged"] = bool(d["converged"])
-        for k in ("N", "E", "V", "C", "sum_y", "sum_y2"):
-            d[k] = list(getattr(self, k))[:L + 1]
-        return d
+        n = self.L + 1
+        # slicing a ctypes array yields a list of Python numbers
+        return {"estimate": self.estimate, "rmse_est": self.rmse_est, "wall_s": self.wall_s,
+                "L": self.L, "converged": bool(self.converged), "iterations": self.iterations,
+                "alpha": self.alpha, "beta": self.beta, "gamma": self.gamma, "cost": self.cost,
+                "n_nonfinite": self.n_nonfinite, "N": self.N[:n], "E": self.E[:n],
+                "V": self.V[:n], "C": self.C[:n], "sum_y": self.sum_y[:n],
+                "sum_y2": self.sum_y2[:n]}
 
 
 _lib = None
