@@ -321,7 +321,7 @@ def main():
         step(1 + i % max(args.steps, 1))   # same seeds, hence launch sizes, as timed steps
     # Which kernel dominates: every slot timed over the same steps, untimed
     # by the clock.  The timed region then stamps only that kernel's launches
-    # (each stamped launch adds a few microseconds of queue time).
+    # (each stamped launch costs the host ~10 us more than a plain one).
     ctx.set_timing(True)
     for i in range(args.steps):
         step(1 + i)
@@ -336,6 +336,14 @@ def main():
     dt = time.perf_counter() - t0
     stats = ctx.kernel_stats()
     ctx.set_timing(False)
+    # context: the same steps with no kernel stamped (a stamped launch costs
+    # the host ~10 us of event handling); `value` stays the timed region's
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(1 + i)
+    torch.cuda.synchronize()
+    dt_unstamped = time.perf_counter() - t0
 
     fine = sum(fine_steps_of(r, M) for r in runs)
     value = fine / dt
@@ -379,6 +387,7 @@ def main():
 
     line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+            "ms_per_step_unstamped": 1e3 * dt_unstamped / args.steps,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": f"adaptive MLMC, GBM European call S0=100 r=0.05 sigma=0.2 "
