@@ -215,7 +215,8 @@ mlmc_status mlmc_stdmc(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff
  * of one MLMC iteration -- levels 0..L, npayoffs payoffs on one model -- in
  * ONE launch of a persistent kernel, replayed from a captured HIP graph:
  * a plan kernel cuts the samples into items of about equal cost (deepest
- * level first), resident blocks take items from an atomic counter.
+ * level first), resident blocks take them (block b item b, the rest from
+ * an atomic counter).
  *   N[k * (L+1) + l]: samples of payoff k at level l (0 allowed);
  *   offsets: same layout, first sample index (NULL = all 0);
  *   out[k * (L+1) + l]: the level sums, identical in law (and, up to fp64

@@ -7,8 +7,8 @@
 // paper's cost measure, Sec. 3) and N_l falls with l.  A plan kernel cuts the
 // outstanding samples into items of roughly equal cost, deepest levels first
 // (longest-processing-time order), and a resident grid of blocks takes items
-// from an atomic counter until none are left, so cheap levels fill in around
-// the long deep-level items.  GBM levels with too few paths to fill the
+// (block b item b first, then from an atomic counter) until none are left, so
+// cheap levels fill in around the long deep-level items.  GBM levels with too few paths to fill the
 // device run each path on several lanes (process_split), with the per-level
 // launch's rule on the level's count.  Every parameter the launches read lives in
 // device memory and is rewritten between launches (by the driver kernel or
