@@ -39,6 +39,37 @@ def test_batch_equals_per_level(gctx, kind):
     gctx.set_persistent_launch(0, 0, 0)
 
 
+def test_batch_random_patterns(gctx):
+    """Random (payoff, level) counts, zeros and single samples among them, on
+    one to four payoffs and up to eight levels: the plan packs the non-empty
+    pairs and gives each its items; every pair must equal its own launch."""
+    import numpy as np
+    rng = np.random.default_rng(2024)
+    gm = mlmc.model(**W.GBM_MODEL)
+    names = ("call", "asian", "lookback", "digital")
+    for trial in range(6):
+        npay = int(rng.integers(1, 5))
+        L = int(rng.choice([0, 3, 7]))
+        M = int(rng.choice([2, 4]))
+        pays = [mlmc.payoff(**W.PAYOFFS[names[int(rng.integers(0, 4))]]) for _ in range(npay)]
+        N = [[int(rng.choice([0, 1, 63, 257, 4099, 70001])) // (M ** min(l, 3)) + (l == L)
+              for l in range(L + 1)] for _ in range(npay)]
+        got = gctx.mlmc_levels_batch(gm, pays, M, L, N, seed=100 + trial)
+        for k, p in enumerate(pays):
+            for l in range(L + 1):
+                g = got[k][l]
+                assert g["n"] == N[k][l], (trial, k, l)
+                if N[k][l] == 0:
+                    assert g["sum_y"] == 0.0 and g["sum_y2"] == 0.0
+                    continue
+                ref = gctx.mlmc_level(gm, p, l, M, N[k][l], 100 + trial)
+                # the same terms added in another order: the error is bounded
+                # by a few ulps of sum |Y| <= sqrt(N sum Y^2)
+                scale_y = (N[k][l] * ref["sum_y2"]) ** 0.5
+                assert abs(g["sum_y"] - ref["sum_y"]) <= 1e-12 * scale_y + 1e-300, (trial, k, l)
+                assert close(g["sum_y2"], ref["sum_y2"], 1e-11), (trial, k, l)
+
+
 def test_graph_replay_with_new_sizes(gctx):
     gm = mlmc.model(**W.GBM_MODEL)
     pays = [mlmc.payoff(**W.CALL)]
