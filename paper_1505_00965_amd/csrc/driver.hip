@@ -219,9 +219,9 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
             // the mirror is not being written
             if (it > h->max_iterations + 1)
                 return fail(ctx, MLMC_EDEVICE, "driver state did not reach the host");
-            // deepest level first: the host's first launch after an update
-            // is its slowest, and the later ones (level 0's, the largest,
-            // last) are enqueued while the deeper levels run
+            // deepest level first: level 0's launch (the largest, and the
+            // dearest for the host when its kernels are timed) is enqueued
+            // last, while the deeper levels run
             for (int l = h->L; l >= 0; --l) {
                 if (h->dN[l] <= 0) continue;
                 const mlmc_cv* cv = (o.cv && (o.cv_levels <= 0 || l < o.cv_levels)) ? o.cv : nullptr;
