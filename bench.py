@@ -182,7 +182,8 @@ def time_to_accuracy(ctx, mlmc, W, args):
 
 def persistent_batch(ctx, mlmc, W, reps=3):
     """All levels 0..8 of four payoffs (N_l = 2^26 4^-l) in one graph-replayed
-    persistent launch, against the sum of the 36 per-level launches."""
+    persistent launch with the autotuned shape (and the default one), against
+    the sum of the 36 per-level launches."""
     import torch
     gm = mlmc.model(**W.GBM_MODEL)
     names = ("call", "asian", "lookback", "digital")
@@ -190,13 +191,23 @@ def persistent_batch(ctx, mlmc, W, reps=3):
     L = 8
     N = [[W.persistent_n(l) for l in range(L + 1)] for _ in pays]
     fine = sum(N[0][l] * 4**l for l in range(L + 1)) * len(pays)
-    ctx.mlmc_levels_batch(gm, pays, 4, L, N, seed=1)          # capture + warm
-    torch.cuda.synchronize()
+
+    def time_batch():
+        ctx.mlmc_levels_batch(gm, pays, 4, L, N, seed=1)          # capture + warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            ctx.mlmc_levels_batch(gm, pays, 4, L, N, seed=1 + r)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    ctx.set_persistent_launch(0, 0, 0)
+    t_default = time_batch()
+    # the persistent form's autotuner on this batch's payoffs and levels
     t0 = time.perf_counter()
-    for r in range(reps):
-        ctx.mlmc_levels_batch(gm, pays, 4, L, N, seed=1 + r)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / reps
+    shape = ctx.autotune_persistent(gm, pays, M=4, L=L)
+    t_tune = time.perf_counter() - t0
+    t_batch = time_batch()
     t0 = time.perf_counter()
     for r in range(reps):
         for p in pays:
@@ -215,6 +226,9 @@ def persistent_batch(ctx, mlmc, W, reps=3):
         tail[name] = 1e3 * st["ms"] / st["launches"]
     return {"workload": "GBM call/Asian/lookback/digital, M=4, levels 0..8, N_l = 2^26 4^-l",
             "fine_path_steps": fine, "persistent_ms": 1e3 * t_batch,
+            "autotuned_shape": {"block": shape[0], "ppt": shape[1], "blocks_per_cu": shape[2],
+                                "tuning_s": t_tune},
+            "persistent_ms_default_shape": 1e3 * t_default,
             "per_level_launches_ms": 1e3 * t_levels,
             "persistent_fine_steps_per_s": fine / t_batch,
             "per_level_fine_steps_per_s": fine / t_levels,

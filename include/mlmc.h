@@ -230,6 +230,20 @@ mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc
  * to the tuned/default shape.                                               */
 mlmc_status mlmc_set_persistent_launch(mlmc_ctx* ctx, int block, int ppt, int blocks_per_cu);
 
+/* Autotuner of the persistent form: times mlmc_levels_batch for these
+ * payoffs, M and L at N_l = 2^24 M^-l (at least 1) for every block size
+ * {128, 256, 512} x samples per lane {1, 2, 4} x resident blocks per compute
+ * unit {2, 4, 8} with at most 2048 threads per compute unit (median of three
+ * after a capture run) and sets the fastest with mlmc_set_persistent_launch.
+ * Results do not depend on the shape (see determinism above).  Cached like
+ * mlmc_autotune's (cache_path, else $MLMC_TUNE_CACHE) under the machine key
+ * and (model kind, scheme, M, L, npayoffs, first payoff kind); a cached
+ * shape is set without measuring.  Arguments as for mlmc_levels_batch;
+ * shape (host, 3 ints, may be NULL) receives block, ppt, blocks_per_cu.    */
+mlmc_status mlmc_autotune_persistent(mlmc_ctx* ctx, const mlmc_model* model,
+                                     const mlmc_payoff* payoffs, int npayoffs, int M, int L,
+                                     const char* cache_path, int* shape);
+
 /* ---------------------------------------------------------------- driver
  * Sample counts N_l = ceil(2 eps^-2 sqrt(V_l/C_l) sum_k sqrt(V_k C_k)) for
  * l = 0..L (the optimisation of Sec. 5's "Constructive Upper Bound" remark,

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -16,6 +17,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <vector>
 
 #include "context.hpp"
 
@@ -217,6 +219,83 @@ mlmc_status mlmc_autotune(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_pay
         dirty = true;
     }
     if (dirty && !path.empty() && !write_cache(path, cache))
+        return fail(ctx, MLMC_EINVAL, "could not write the tuning cache " + path);
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_autotune_persistent(mlmc_ctx* ctx, const mlmc_model* model,
+                                     const mlmc_payoff* payoffs, int npayoffs, int M, int L,
+                                     const char* cache_path, int* shape)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (!model || !payoffs) return fail(ctx, MLMC_EINVAL, "model and payoffs must not be NULL");
+    if (npayoffs < 1 || npayoffs > 4) return fail(ctx, MLMC_EINVAL, "npayoffs must be in 1..4");
+    if (L < 0 || L > 15) return fail(ctx, MLMC_EINVAL, "L must be in 0..15");
+    for (int k = 0; k < npayoffs; ++k) {
+        const mlmc_status st = check_level_args(ctx, model, &payoffs[k], L, M, 32);
+        if (st) return st;
+    }
+    ctx->err.clear();
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    std::string path;
+    if (cache_path && *cache_path) path = cache_path;
+    else if (const char* e = std::getenv("MLMC_TUNE_CACHE")) path = e;
+    const std::string mk = machine_key(ctx);
+    auto cache = path.empty() ? decltype(read_cache(path)){} : read_cache(path);
+    char kb[96];
+    std::snprintf(kb, sizeof kb, "persist:%d:%d:%d:%d:%d:%d", model->kind, model->scheme, M, L,
+                  npayoffs, payoffs[0].kind);
+    const std::string key = kb;
+    auto mit = cache.find(mk);
+    if (mit != cache.end() && mit->second.count(key) && mit->second[key].size() == 3) {
+        const auto& v = mit->second[key];
+        if (shape) std::memcpy(shape, v.data(), 3 * sizeof(int));
+        return mlmc_set_persistent_launch(ctx, v[0], v[1], v[2]);
+    }
+    // the caller's levels and payoffs at an MLMC-shaped count, N_l = 2^24 M^-l
+    std::vector<uint64_t> N((size_t)npayoffs * (L + 1));
+    for (int k = 0; k < npayoffs; ++k) {
+        double n = (double)(1ull << 24);
+        for (int l = 0; l <= L; ++l, n /= M) N[(size_t)k * (L + 1) + l] = (uint64_t)std::max(1.0, n);
+    }
+    std::vector<mlmc_level_result> out((size_t)npayoffs * (L + 1));
+    const int blocks[] = {128, 256, 512};
+    const int bpcs[] = {2, 4, 8};
+    const int ppts[] = {1, 2, 4};
+    double best = 1e30;
+    int bb = 256, bp = 1, bc = 4;
+    for (int b : blocks)
+        for (int c : bpcs) {
+            if (b * c > 2048) continue;   // resident: at most 2048 threads per compute unit
+            for (int p : ppts) {
+                mlmc_status st = mlmc_set_persistent_launch(ctx, b, p, c);
+                double t[3] = {0, 0, 0};
+                // the first call captures the graph; then the median of three
+                for (int rep = 0; rep < 4 && !st; ++rep) {
+                    const auto t0 = std::chrono::steady_clock::now();
+                    st = mlmc_levels_batch(ctx, model, payoffs, npayoffs, M, L, N.data(), nullptr,
+                                           12345, out.data());
+                    if (st == MLMC_ENONFINITE) st = MLMC_OK;   // timed all the same
+                    const auto t1 = std::chrono::steady_clock::now();
+                    if (rep > 0) t[rep - 1] = std::chrono::duration<double>(t1 - t0).count();
+                }
+                if (st) {
+                    mlmc_set_persistent_launch(ctx, 0, 0, 0);
+                    return st;
+                }
+                std::sort(t, t + 3);
+                if (t[1] < best) { best = t[1]; bb = b; bp = p; bc = c; }
+            }
+        }
+    cache[mk][key] = {bb, bp, bc};
+    const mlmc_status st = mlmc_set_persistent_launch(ctx, bb, bp, bc);
+    if (st) return st;
+    if (shape) {
+        shape[0] = bb;
+        shape[1] = bp;
+        shape[2] = bc;
+    }
+    if (!path.empty() && !write_cache(path, cache))
         return fail(ctx, MLMC_EINVAL, "could not write the tuning cache " + path);
     return MLMC_OK;
 }

@@ -24,6 +24,7 @@ EXPORTED = [
     "mlmc_levels_batch", "mlmc_set_persistent_launch",
     "mlmc_cv_create", "mlmc_cv_destroy", "mlmc_cv_nparams", "mlmc_cv_get_params",
     "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train", "mlmc_autotune",
+    "mlmc_autotune_persistent",
     "mlmc_tuned_shape", "mlmc_rhee_glynn", "mlmc_set_timing_mask",
 ]
 STAT_SLOTS = 20
@@ -145,6 +146,8 @@ def lib():
                                     C.POINTER(d), C.POINTER(d)]
     L.mlmc_cv_train.argtypes = [vp, M_, P_, i32, i32, i32, u64, d, u64, C.POINTER(C.c_float)]
     L.mlmc_autotune.argtypes = [vp, M_, P_, i32, i32, C.c_char_p]
+    L.mlmc_autotune_persistent.argtypes = [vp, M_, P_, i32, i32, i32, C.c_char_p,
+                                           C.POINTER(C.c_int)]
     L.mlmc_tuned_shape.argtypes = [vp, M_, P_, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.mlmc_set_timing.argtypes = [vp, i32]
     L.mlmc_set_timing_mask.argtypes = [vp, u32]
@@ -236,6 +239,15 @@ class Context:
     def autotune(self, m, p, M=4, precision=32, cache_path=None):
         self._check(self._lib.mlmc_autotune(self.h, C.byref(m), C.byref(p), M, precision,
                                             cache_path.encode() if cache_path else None))
+
+    def autotune_persistent(self, m, payoffs, M=4, L=8, cache_path=None):
+        """Tune the persistent form's launch shape; returns (block, ppt, blocks_per_cu)."""
+        npay = len(payoffs)
+        P = (Payoff * npay)(*payoffs)
+        shape = (C.c_int * 3)()
+        self._check(self._lib.mlmc_autotune_persistent(
+            self.h, C.byref(m), P, npay, M, L, cache_path.encode() if cache_path else None, shape))
+        return tuple(shape)
 
     def tuned_shape(self, m, p, l, M=4, precision=32):
         b, q = C.c_int(), C.c_int()

@@ -31,3 +31,37 @@ def test_autotune_cache_and_invariance(tmp_path):
         ctx.autotune(gm, gp, M=4, precision=32, cache_path=path)
         assert [ctx.tuned_shape(gm, gp, l) for l in (0, 2, 5)] == shapes
     assert os.path.getsize(path) > 0
+
+
+def test_autotune_persistent_cache_and_invariance(tmp_path):
+    """The persistent form's tuner picks a shape from its candidate set, sets
+    it, caches it, and the batch sums do not depend on it."""
+    import time
+    path = str(tmp_path / "tune_persist.json")
+    gm = mlmc.model(**W.GBM_MODEL)
+    pays = [mlmc.payoff(**W.CALL), mlmc.payoff(**W.LOOKBACK)]
+    L, M = 5, 4
+    N = [[200000 // 4**l + 1 for l in range(L + 1)] for _ in pays]
+    with mlmc.Context(0) as ctx:
+        ref = ctx.mlmc_levels_batch(gm, pays, M, L, N, seed=21)
+        shape = ctx.autotune_persistent(gm, pays, M=M, L=L, cache_path=path)
+        b, p, c = shape
+        assert b in (128, 256, 512) and p in (1, 2, 4) and c in (2, 4, 8) and b * c <= 2048
+        got = ctx.mlmc_levels_batch(gm, pays, M, L, N, seed=21)
+        for k in range(len(pays)):
+            for l in range(L + 1):
+                a, g = ref[k][l], got[k][l]
+                assert a["n"] == g["n"]
+                scale = (a["n"] * a["sum_y2"]) ** 0.5
+                assert abs(a["sum_y"] - g["sum_y"]) <= 1e-12 * scale + 1e-300, (k, l)
+    data = json.load(open(path))
+    (machine, entries), = data.items()
+    assert "gfx950" in machine and list(entries.values()) == [list(shape)]
+    # a new context reads the cache instead of measuring
+    with mlmc.Context(0) as ctx:
+        t0 = time.perf_counter()
+        again = ctx.autotune_persistent(gm, pays, M=M, L=L, cache_path=path)
+        assert again == shape and time.perf_counter() - t0 < 0.5
+    with mlmc.Context(0) as ctx:
+        with pytest.raises(mlmc.MLMCError):
+            ctx.autotune_persistent(gm, pays * 3, M=M, L=L)     # six payoffs
