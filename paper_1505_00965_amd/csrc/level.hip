@@ -41,6 +41,8 @@ StepParams<Real> make_step_params(const mlmc_model& m, const mlmc_payoff& p, int
     P.inv_T = (Real)(1.0 / m.T);
     P.lnu_scale = (Real)(-2.0 * h * std::log(2.0));
     P.asian_scale = (Real)(h / (2.0 * m.T));
+    P.l0_base = (Real)(m.S0 * (1.0 + m.r * h) - p.K);
+    P.l0_slope = (Real)(m.S0 * m.sigma);
     return P;
 }
 template StepParams<float> make_step_params<float>(const mlmc_model&, const mlmc_payoff&, int, int);

@@ -35,6 +35,9 @@ struct StepParams {
     Real K, payout, disc, inv_T;     // payoff
     Real lnu_scale;                  // -2 h ln(2): bridge term e = lnu_scale * log2(U)
     Real asian_scale;                // h / (2T)
+    // level 0 of a European call (one Euler step from S0):
+    // S_1 - K = l0_base + l0_slope dW, l0_base = S0 (1 + r T) - K, l0_slope = S0 sigma
+    Real l0_base, l0_slope;
 };
 
 // Fused multiply-add in the path's own precision (no promotion to fp64).

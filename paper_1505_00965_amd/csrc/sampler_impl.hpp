@@ -1,5 +1,7 @@
 // Path loop shared by the per-level kernel and the persistent kernel.
 #pragma once
+#include <type_traits>
+
 #include "level.hpp"
 
 namespace mlmc {
@@ -286,6 +288,11 @@ __device__ __forceinline__ void process_split(const LevelArgs<float>& a, uint64_
 // so that sum is finite exactly when every y is); otherwise the chunk is
 // added sample by sample with the range and finiteness checks.  y = P_f
 // there: the P_f sums are left to copy_y_sums and the P_c sums stay zero.
+// Level 0 of a GBM Euler call in fp32 paths: process_short folds the step into the payoff.
+template <int MODEL, int PAYOFF, typename Real, int NF, bool ANTI>
+constexpr bool kFusedLevel0 = NF == 1 && MODEL == kGBM && PAYOFF == kCall && !ANTI &&
+                              std::is_same<Real, float>::value;
+
 template <int MODEL, int PAYOFF, typename Real, int NF, int M, int PPT, bool ANTI>
 __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t blk_base, bool full,
                                               double (&sums)[kNumSums], unsigned& nonfinite)
@@ -320,6 +327,15 @@ __device__ __forceinline__ void process_short(const LevelArgs<Real>& a, uint64_t
         }
 #pragma unroll
         for (int r = 0; r < Q; ++r) {
+            if constexpr (kFusedLevel0<MODEL, PAYOFF, Real, NF, ANTI>) {
+                // level 0 of a GBM Euler call: the one step and the payoff fold
+                // into S_1 - K = (S0 (1 + r T) - K) + S0 sigma dW, one fma
+                const Real u = fmaT(P.l0_slope, dw[r], P.l0_base);
+                pf[p][r] = fmaT(P.disc, fmaxT(u, Real(0)), u - u);   // u - u: NaN if u overflowed
+                pc[p][r] = Real(0);
+                dwf[p][r] = dw[r];
+                continue;
+            }
             const uint64_t s = B[p] * Q + r;
             PathPair<Real> q;
             init_pair<Real, MODEL, PAYOFF>(q, P);
