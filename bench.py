@@ -30,7 +30,9 @@ UNIT = "fine path-steps/s"
 # radius (6.5), the Euler step (2 fma), coarse increment sum and a quarter
 # coarse step (1.5); per sample, payoffs and fp64 sums.
 OPS_PER_FINE_STEP = 20.0
-OPS_PER_SAMPLE_L0 = 24.5      # level 0: the one step plus payoff (3) and Y, Y^2 sums (3)
+# level 0: the one step plus payoff (3) and Y, Y^2 sums (3), the method's count
+# (the fp32 call kernel folds step and strike into one fma: it issues 2 fewer)
+OPS_PER_SAMPLE_L0 = 24.5
 OPS_PER_SAMPLE = 11.0         # levels >= 1: two payoffs, difference, sums
 
 
