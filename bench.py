@@ -109,20 +109,22 @@ def cpu_baseline(ref_run, M, budget_s):
     total_cost = sum(n * (M**l + (M ** (l - 1) if l else 0)) for l, n in enumerate(ref_run["N"]))
     # a run that fits the budget is repeated (seeds 1, 2, ...), a larger one scaled down
     scale = budget_s * rate / total_cost
-    reps, scale = (int(scale), 1.0) if scale >= 1.0 else (1, scale)
+    whole = scale >= 1.0
+    scale = min(scale, 1.0)
     fine = 0.0
     t0 = time.perf_counter()
     done = 0
-    while done < reps and (done == 0 or time.perf_counter() - t0 < budget_s):
+    # another pass only while the measured passes project within the budget
+    while done == 0 or (whole and done < 1000 and
+                        (time.perf_counter() - t0) * (done + 1) / done <= budget_s):
         for l, n in enumerate(ref_run["N"]):
             nn = max(1, int(n * scale))
             oracle.level(om, op, l, M, nn, 1 + done, nthreads=cores)
             fine += nn * M**l
         done += 1
-    reps = done
     dt = time.perf_counter() - t0
-    what = (f"{reps} pass(es) over levels 0..{len(ref_run['N']) - 1} of one adaptive run with its N_l"
-            if scale == 1.0 else
+    what = (f"{done} pass(es) over levels 0..{len(ref_run['N']) - 1} of one adaptive run with its N_l"
+            if whole else
             f"levels 0..{len(ref_run['N']) - 1} of one adaptive run with every N_l scaled by {scale:.3g}")
     return {"value": fine / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": f"{what} ({fine:.3g} fine path steps, {dt:.1f} s, fp64)"}
