@@ -351,9 +351,9 @@ def main():
     ctx.set_timing(True)
     for i in range(args.steps):
         step(1 + i)
-    survey = ctx.kernel_stats()
+    all_slots = ctx.kernel_stats()
     ctx.set_timing(False)
-    dom = mlmc.STAT_PERSISTENT if args.persistent else max(range(16), key=lambda l: survey[l]["ms"])
+    dom = mlmc.STAT_PERSISTENT if args.persistent else max(range(16), key=lambda l: all_slots[l]["ms"])
     ctx.set_timing_slots([dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
