@@ -40,11 +40,15 @@ __global__ __launch_bounds__(1024) void short_level_kernel(LevelArgs<Real> a)
     const uint64_t chunk = (uint64_t)blockDim.x * PPT;
     const uint64_t nchunks = (nblk + chunk - 1) / chunk;
     const FullChunks f = full_chunks(a.offset, a.N, Q, chunk);
-    // block-uniform bounds (computed with a vector division): scalar registers
+    // block-uniform bounds (computed with a vector division): scalar registers.
+    // A launch's generator blocks share one counter high word, so chunk
+    // indices fit 32 bits and the loop test is a scalar compare.
     const uint32_t lo = __builtin_amdgcn_readfirstlane(f.lo), hi = __builtin_amdgcn_readfirstlane(f.hi);
-    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const bool full = (uint32_t)c >= lo && (uint32_t)c < hi;
-        process_short<MODEL, PAYOFF, Real, NF, M, PPT, ANTI>(a, c * chunk, full, sums, nonfinite);
+    const uint32_t n32 = __builtin_amdgcn_readfirstlane((uint32_t)nchunks);
+    for (uint32_t c = blockIdx.x; c < n32; c += gridDim.x) {
+        const bool full = c >= lo && c < hi;
+        process_short<MODEL, PAYOFF, Real, NF, M, PPT, ANTI>(a, (uint64_t)c * chunk, full, sums,
+                                                             nonfinite);
     }
     if (NF == 1) copy_y_sums(sums);
     block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
