@@ -201,8 +201,10 @@ __device__ __forceinline__ void run_range(const LevelArgs<float>& a, double (&su
         const uint64_t chunk = (uint64_t)blockDim.x * PPT;
         const FullChunks f = full_chunks(a.offset, a.N, q, chunk);
         const uint32_t lo = __builtin_amdgcn_readfirstlane(f.lo), hi = __builtin_amdgcn_readfirstlane(f.hi);
-        uint32_t c = 0;
-        for (uint64_t base = 0; base < nblk; base += chunk, ++c) {
+        // one counter segment: chunk indices fit 32 bits (a scalar loop test)
+        const uint32_t nch = __builtin_amdgcn_readfirstlane((uint32_t)((nblk + chunk - 1) / chunk));
+        for (uint32_t c = 0; c < nch; ++c) {
+            const uint64_t base = (uint64_t)c * chunk;
             const bool full = c >= lo && c < hi;
             if (a.nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT, false>(a, base, full, sums, nonfinite);
             else process_short<MODEL, PAYOFF, float, 2, M, PPT, false>(a, base, full, sums, nonfinite);
