@@ -161,8 +161,10 @@ mlmc_status mlmc_kernel_stats(mlmc_ctx* ctx, mlmc_kernel_stat* out);
 /* Autotuner: times every block size {64..1024} x samples-per-lane {1,2,4}
  * (fp64: 1) of the level sampler on a device-filling sample count for three
  * level classes (one-step levels, 2..16 fine steps, longer paths) and keeps
- * the fastest for this (model, payoff, precision, M); later launches use it
- * unless mlmc_set_launch fixed a shape.  Results are cached in the JSON file
+ * the fastest for this (model kind, scheme, antithetic flag, payoff,
+ * precision, M); later launches use it unless mlmc_set_launch fixed a shape
+ * (a launch with fewer samples than 256 lanes per compute unit at the tuned
+ * ppt still takes ppt 1).  Results are cached in the JSON file
  * cache_path (or $MLMC_TUNE_CACHE; NULL/"" and no variable: no cache) under
  * a key of GPU architecture, compute-unit count and HIP runtime version, and
  * read back instead of measured when present.                             */
@@ -237,7 +239,7 @@ mlmc_status mlmc_set_persistent_launch(mlmc_ctx* ctx, int block, int ppt, int bl
  * after a capture run) and sets the fastest with mlmc_set_persistent_launch.
  * Results do not depend on the shape (see determinism above).  Cached like
  * mlmc_autotune's (cache_path, else $MLMC_TUNE_CACHE) under the machine key
- * and (model kind, scheme, M, L, npayoffs, first payoff kind); a cached
+ * and (model kind, scheme, M, L, npayoffs, every payoff kind); a cached
  * shape is set without measuring.  Arguments as for mlmc_levels_batch;
  * shape (host, 3 ints, may be NULL) receives block, ppt, blocks_per_cu.    */
 mlmc_status mlmc_autotune_persistent(mlmc_ctx* ctx, const mlmc_model* model,

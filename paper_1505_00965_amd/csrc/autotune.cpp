@@ -34,10 +34,13 @@ int level_class(int l, int M)
     return 2;
 }
 
-static std::string tune_key(int model, int payoff, int precision, int M, int cls)
+// The scheme and the antithetic twin change the kernel (register use, work
+// per step), so they are part of the key.
+static std::string tune_key(const mlmc_model& m, int payoff, int precision, int M, int cls)
 {
-    char b[64];
-    std::snprintf(b, sizeof b, "level:%d:%d:%d:%d:%d", model, payoff, precision, M, cls);
+    char b[80];
+    std::snprintf(b, sizeof b, "level:%d:%d:%d:%d:%d:%d:%d", m.kind, m.scheme, m.antithetic, payoff,
+                  precision, M, cls);
     return b;
 }
 
@@ -129,11 +132,11 @@ static bool write_cache(const std::string& path,
     return std::rename(tmp.c_str(), path.c_str()) == 0;
 }
 
-bool tuned_shape(const mlmc_ctx* ctx, int model, int payoff, int precision, int M, int l,
+bool tuned_shape(const mlmc_ctx* ctx, const mlmc_model& m, int payoff, int precision, int M, int l,
                  int* block, int* ppt)
 {
     if (ctx->tuned.empty()) return false;   // every launch asks: skip the key when nothing is tuned
-    auto it = ctx->tuned.find(tune_key(model, payoff, precision, M, level_class(l, M)));
+    auto it = ctx->tuned.find(tune_key(m, payoff, precision, M, level_class(l, M)));
     if (it == ctx->tuned.end() || it->second.size() < 2) return false;
     *block = it->second[0];
     *ppt = it->second[1];
@@ -194,7 +197,7 @@ mlmc_status mlmc_autotune(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_pay
     // representative levels and sizes per class: saturate the device
     const int reps[3] = {0, M == 4 ? 2 : 3, M == 4 ? 4 : 7};
     for (int cls = 0; cls < 3; ++cls) {
-        const std::string key = tune_key(model->kind, payoff->kind, precision, M, cls);
+        const std::string key = tune_key(*model, payoff->kind, precision, M, cls);
         auto mit = cache.find(mk);
         if (mit != cache.end() && mit->second.count(key)) {
             ctx->tuned[key] = mit->second[key];
@@ -242,10 +245,12 @@ mlmc_status mlmc_autotune_persistent(mlmc_ctx* ctx, const mlmc_model* model,
     else if (const char* e = std::getenv("MLMC_TUNE_CACHE")) path = e;
     const std::string mk = machine_key(ctx);
     auto cache = path.empty() ? decltype(read_cache(path)){} : read_cache(path);
+    // every payoff of the batch is part of the key: the mix sets the work
     char kb[96];
-    std::snprintf(kb, sizeof kb, "persist:%d:%d:%d:%d:%d:%d", model->kind, model->scheme, M, L,
-                  npayoffs, payoffs[0].kind);
-    const std::string key = kb;
+    std::snprintf(kb, sizeof kb, "persist:%d:%d:%d:%d:%d:", model->kind, model->scheme, M, L,
+                  npayoffs);
+    std::string key = kb;
+    for (int k = 0; k < npayoffs; ++k) key += std::to_string(payoffs[k].kind) + (k + 1 < npayoffs ? "," : "");
     auto mit = cache.find(mk);
     if (mit != cache.end() && mit->second.count(key) && mit->second[key].size() == 3) {
         const auto& v = mit->second[key];
@@ -304,7 +309,7 @@ mlmc_status mlmc_tuned_shape(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_
                              int l, int M, int precision, int* block, int* ppt)
 {
     if (!ctx || !model || !payoff || !block || !ppt) return MLMC_EINVAL;
-    if (!tuned_shape(ctx, model->kind, payoff->kind, precision, M, l, block, ppt)) {
+    if (!tuned_shape(ctx, *model, payoff->kind, precision, M, l, block, ppt)) {
         *block = 0;
         *ppt = 0;
     }

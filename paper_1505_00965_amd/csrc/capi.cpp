@@ -80,12 +80,13 @@ LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_pa
     s.block = ctx->launch_block ? ctx->launch_block : 256;
     s.ppt = precision == 64 ? 1 : (ctx->launch_ppt ? ctx->launch_ppt : 2);
     int tb = 0, tp = 0;
-    const bool tuned = !ctx->launch_block && tuned_shape(ctx, m.kind, p.kind, precision, M, l, &tb, &tp);
-    if (tuned) {
+    if (!ctx->launch_block && tuned_shape(ctx, m, p.kind, precision, M, l, &tb, &tp)) {
         s.block = tb;
         s.ppt = tp;
-    } else if (!ctx->launch_block) {
+    }
+    if (!ctx->launch_block) {
         // few samples: fewer paths per thread so that more lanes take part
+        // (the tuner measures device-filling counts, so its ppt is for those)
         const uint64_t lanes = (N + s.ppt - 1) / s.ppt;
         if (lanes < (uint64_t)ctx->num_cu * 256) s.ppt = 1;
     }

@@ -98,7 +98,7 @@ void free_driver(mlmc_ctx* ctx);
 void free_persistent(mlmc_ctx* ctx);
 
 // Tuned shape of the level sampler for this problem, if the tuner ran.
-bool tuned_shape(const mlmc_ctx* ctx, int model, int payoff, int precision, int M, int l,
+bool tuned_shape(const mlmc_ctx* ctx, const mlmc_model& m, int payoff, int precision, int M, int l,
                  int* block, int* ppt);
 int level_class(int l, int M);
 

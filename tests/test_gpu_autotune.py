@@ -65,3 +65,34 @@ def test_autotune_persistent_cache_and_invariance(tmp_path):
     with mlmc.Context(0) as ctx:
         with pytest.raises(mlmc.MLMCError):
             ctx.autotune_persistent(gm, pays * 3, M=M, L=L)     # six payoffs
+
+
+def test_autotune_keys_separate_scheme_twin_and_payoff_mix(tmp_path):
+    """A shape tuned for Euler paths is not served to Milstein or antithetic
+    runs, and a persistent shape tuned for one payoff mix is not served to
+    another mix with the same first payoff."""
+    path = str(tmp_path / "tune_keys.json")
+    gp = mlmc.payoff(**W.CALL)
+    euler = mlmc.model(**W.GBM_MODEL)
+    milstein = mlmc.model(**dict(W.GBM_MODEL, scheme=1))
+    twin = mlmc.model(**dict(W.GBM_MODEL, antithetic=1))
+    with mlmc.Context(0) as ctx:
+        ctx.autotune(euler, gp, M=4, precision=32, cache_path=path)
+        assert ctx.tuned_shape(euler, gp, 3) != (0, 0)
+        assert ctx.tuned_shape(milstein, gp, 3) == (0, 0)
+        assert ctx.tuned_shape(twin, gp, 3) == (0, 0)
+        # a tuned shape still drops to one sample per lane for small counts:
+        # the sums equal the default shape's up to fp64 summation order
+        small = ctx.mlmc_level(euler, gp, 3, 4, 3000, 5)
+        ctx.set_launch(256, 1)
+        ref = ctx.mlmc_level(euler, gp, 3, 4, 3000, 5)
+        ctx.set_launch(0, 0)
+        assert abs(small["sum_y"] - ref["sum_y"]) <= 1e-12 * abs(ref["sum_y"]) + 1e-12
+    pays_a = [mlmc.payoff(**W.CALL), mlmc.payoff(**W.ASIAN)]
+    pays_b = [mlmc.payoff(**W.CALL), mlmc.payoff(**W.LOOKBACK)]
+    with mlmc.Context(0) as ctx:
+        ctx.autotune_persistent(euler, pays_a, M=4, L=3, cache_path=path)
+        ctx.autotune_persistent(euler, pays_b, M=4, L=3, cache_path=path)
+    entries = next(iter(json.load(open(path)).values()))
+    persist = [k for k in entries if k.startswith("persist:")]
+    assert len(persist) == 2 and len(set(persist)) == 2
