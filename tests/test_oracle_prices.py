@@ -21,9 +21,9 @@ from the sampler:
     configuration's strike 100 and at 120, where the sign of the correlation
     moves the price by 1.5;
   - arithmetic Asian (named in Sec. 7.1): no closed form; Vecer's
-    one-dimensional PDE for the continuous average, solved here by
-    Crank--Nicolson (checked against its exact K = 0 value and by grid
-    refinement), and the continuous geometric Asian as a strict lower bound
+    one-dimensional PDE for the continuous average, solved by the oracle's
+    Crank--Nicolson module (checked here against its exact K = 0 value, its
+    zero-volatility limit and by grid refinement), and the continuous geometric Asian as a strict lower bound
     (arithmetic >= geometric mean).
 Plausible slips fail: a bridge minimum without its correction term is off by
 about 0.6 sigma sqrt(h) S0 (0.7 at h = 1/256), the opposite correlation sign
@@ -98,46 +98,8 @@ def test_heston_telescopes_to_characteristic_function_price(orc, K):
     assert abs(orc.heston_call(K=K, rho=0.7) - price) > 5 * tol
 
 
-def vecer_asian_call(S0, K, r, sigma, T, nz=4000, nt=2000, zlo=-2.0, zhi=3.0, damp=4):
-    """Continuous arithmetic-average Asian call by Vecer's PDE.
-
-    With q(t) = (1 - e^{-r(T-t)})/(rT) shares held, a self-financing portfolio
-    X with X_0 = q(0) S0 - e^{-rT} K ends at X_T = A - K.  Z = X/S is a
-    martingale under the share measure with dZ = sigma (q(t) - Z) dW, so the
-    price is S0 u(0, Z_0), where u_t + sigma^2 (q(t) - z)^2 u_zz / 2 = 0,
-    u(T, z) = max(z, 0).  Crank--Nicolson on a uniform z grid, `damp` pairs
-    of half-size implicit steps first (Rannacher), u = 0 and u = z at the
-    ends of the grid."""
-    from scipy.linalg import solve_banded
-    z = np.linspace(zlo, zhi, nz + 1)
-    dz = z[1] - z[0]
-    zi = z[1:-1]
-    u = np.maximum(z, 0.0)
-
-    def q(t):
-        return (1.0 - math.exp(-r * (T - t))) / (r * T)
-
-    dt = T / nt
-    steps = [(dt / 2, 1.0)] * (2 * damp) + [(dt, 0.5)] * (nt - damp)
-    t = T
-    for k, th in steps:
-        tn = t - k
-        a_new = 0.5 * sigma**2 * (q(tn) - zi) ** 2 / dz**2
-        a_old = 0.5 * sigma**2 * (q(t) - zi) ** 2 / dz**2
-        rhs = u[1:-1] + (1 - th) * k * a_old * (u[:-2] - 2 * u[1:-1] + u[2:])
-        rhs[-1] += th * k * a_new[-1] * zhi
-        ab = np.zeros((3, nz - 1))
-        ab[0, 1:] = -th * k * a_new[:-1]
-        ab[1, :] = 1 + 2 * th * k * a_new
-        ab[2, :-1] = -th * k * a_new[1:]
-        u[1:-1] = solve_banded((1, 1), ab, rhs)
-        u[0], u[-1] = 0.0, zhi
-        t = tn
-    z0 = q(0.0) - math.exp(-r * T) * K / S0
-    return S0 * float(np.interp(z0, z, u))
-
-
-def test_vecer_pde_solver():
+def test_vecer_pde_solver(orc):
+    vecer_asian_call = orc.asian_arith_call_pde
     # K = 0: the discounted mean of the average, S0 (1 - e^{-rT}) / (rT)
     assert abs(vecer_asian_call(100.0, 0.0, 0.05, 0.2, 1.0) - 100 * (1 - math.exp(-0.05)) / 0.05) < 1e-9
     # grid refinement and a wider domain move the price by < 1e-4
@@ -153,7 +115,7 @@ def test_vecer_pde_solver():
 @pytest.mark.parametrize("M,L", [(2, 8), (4, 5)])
 def test_asian_telescopes_to_continuous_average_price(orc, M, L):
     m, p = orc.model(), orc.payoff(kind=orc.ASIAN)
-    price = vecer_asian_call(100.0, 100.0, 0.05, 0.2, 1.0)
+    price = orc.asian_arith_call_pde(100.0, 100.0, 0.05, 0.2, 1.0)
     geo = orc.geometric_asian_call()
     assert abs(geo - 5.546819) < 1e-6 and price > geo
     res = mlmc_fixed(orc, m, p, M, L, 0.003, seed=11)
