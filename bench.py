@@ -30,10 +30,13 @@ UNIT = "fine path-steps/s"
 # radius (6.5), the Euler step (2 fma), coarse increment sum and a quarter
 # coarse step (1.5); per sample, payoffs and fp64 sums.
 OPS_PER_FINE_STEP = 20.0
-# level 0: the one step plus payoff (3) and Y, Y^2 sums (3), the method's count
-# (the fp32 call kernel folds step and strike into one fma: it issues 2 fewer)
-OPS_PER_SAMPLE_L0 = 24.5
+# level 0: the one step plus payoff (3) and Y, Y^2 sums (3) is the method's
+# count, 24.5; the fp32 call kernel folds the step and the strike into one fma
+# and executes 22.5 of them.  The roofline counts what the kernel executes.
+OPS_PER_SAMPLE_L0_METHOD = 24.5
+OPS_PER_SAMPLE_L0 = 22.5
 OPS_PER_SAMPLE = 11.0         # levels >= 1: two payoffs, difference, sums
+FP32_PEAK_FLOPS = 157.3e12    # MI355X fp32 vector peak (an fma counts 2, packed fp32 2x)
 
 
 def algorithmic_ops(level, fine_steps, samples):
@@ -95,67 +98,123 @@ def fine_steps_of(res, M):
     return float(sum(n * M**l for l, n in enumerate(res["N"])))
 
 
+def host_info():
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    affinity = len(os.sched_getaffinity(0))
+    # the host share of one GPU: the box sets OMP_NUM_THREADS to it (16)
+    share = int(os.environ.get("OMP_NUM_THREADS") or affinity)
+    return {"nproc": os.cpu_count(), "affinity": affinity, "threads": max(1, min(affinity, share)),
+            "cpu_model": model}
+
+
+def oracle_rate(oracle, om, op, N, M, threads, budget_s):
+    """Fine path-steps/s of the oracle on passes over levels 0..L with counts
+    N_l (scaled down when a pass does not fit), run until the budget is used.
+
+    One untimed call first (thread start-up, first touch), then a probe sized
+    by time (>= 0.2 s of level-3 samples) for the first pass's scale; every
+    later pass is sized from the rate measured so far to the time left."""
+    costs = [M**l + (M ** (l - 1) if l else 0) for l in range(len(N))]
+    total = sum(n * c for n, c in zip(N, costs))
+    oracle.level(om, op, 1, M, 1000, 97, nthreads=threads)
+    n = 2000
+    while True:
+        t0 = time.perf_counter()
+        oracle.level(om, op, 3, M, n, 98, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.2:
+            break
+        n = int(n * min(10.0, max(2.0, 0.25 / max(dt, 1e-6))))
+    rate = n * (M**3 + M**2) / dt
+    fine = steps = 0.0
+    passes, scales = 0, []
+    t0 = time.perf_counter()
+    while passes < 1000:
+        left = budget_s - (time.perf_counter() - t0)
+        if left <= 0.05 * budget_s:
+            break
+        scale = min(1.0, left * rate / total)
+        for l, nl in enumerate(N):
+            nn = max(1, int(nl * scale))
+            oracle.level(om, op, l, M, nn, 1 + passes, nthreads=threads)
+            fine += nn * M**l
+            steps += nn * costs[l]
+        passes += 1
+        scales.append(scale)
+        rate = steps / (time.perf_counter() - t0)
+    dt = time.perf_counter() - t0
+    return {"fine_steps_per_s": fine / dt, "fine_steps": fine, "seconds": dt, "passes": passes,
+            "scales": [round(x, 4) for x in scales[:3]] + (["..."] if len(scales) > 3 else [])}
+
+
 def cpu_baseline(ref_run, M, budget_s):
-    """The oracle, as it stands, on a bounded sample of the same levels."""
+    """The oracle, as it stands, on a bounded sample of the same levels: on
+    the host threads one GPU gets and on one thread."""
     import oracle
     from paper_1505_00965_amd import workloads as W
     om, op = oracle.model(**W.GBM_MODEL), oracle.payoff(**W.CALL)
-    cores = min(len(os.sched_getaffinity(0)), 16)
-    # calibrate on a small sample, then scale each level's count to the budget
-    probe = 2000
-    t0 = time.perf_counter()
-    oracle.level(om, op, 3, M, probe, 1, nthreads=cores)
-    rate = probe * (M**3 + M**2) / max(time.perf_counter() - t0, 1e-6)
-    total_cost = sum(n * (M**l + (M ** (l - 1) if l else 0)) for l, n in enumerate(ref_run["N"]))
-    # a run that fits the budget is repeated (seeds 1, 2, ...), a larger one scaled down
-    scale = budget_s * rate / total_cost
-    whole = scale >= 1.0
-    scale = min(scale, 1.0)
-    fine = 0.0
-    t0 = time.perf_counter()
-    done = 0
-    # another pass only while the measured passes project within the budget
-    while done == 0 or (whole and done < 1000 and
-                        (time.perf_counter() - t0) * (done + 1) / done <= budget_s):
-        for l, n in enumerate(ref_run["N"]):
-            nn = max(1, int(n * scale))
-            oracle.level(om, op, l, M, nn, 1 + done, nthreads=cores)
-            fine += nn * M**l
-        done += 1
-    dt = time.perf_counter() - t0
-    what = (f"{done} pass(es) over levels 0..{len(ref_run['N']) - 1} of one adaptive run with its N_l"
-            if whole else
-            f"levels 0..{len(ref_run['N']) - 1} of one adaptive run with every N_l scaled by {scale:.3g}")
-    return {"value": fine / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
-            "sample": f"{what} ({fine:.3g} fine path steps, {dt:.1f} s, fp64)"}
+    info = host_info()
+    N = list(ref_run["N"])
+    many = oracle_rate(oracle, om, op, N, M, info["threads"], 0.7 * budget_s)
+    one = oracle_rate(oracle, om, op, N, M, 1, 0.3 * budget_s)
+    return {"value": many["fine_steps_per_s"], "unit": UNIT, "cores": info["threads"],
+            "kind": "oracle",
+            "sample": (f"levels 0..{len(N) - 1} of one adaptive run (its N_l, scaled to the time "
+                       f"budget), {many['passes']} pass(es), {many['fine_steps']:.3g} fine path "
+                       f"steps in {many['seconds']:.1f} s, fp64"),
+            "single_thread": {"value": one["fine_steps_per_s"], "passes": one["passes"],
+                              "fine_steps": one["fine_steps"], "seconds": one["seconds"]},
+            "scales": many["scales"], "nproc": info["nproc"], "affinity": info["affinity"],
+            "cpu_model": info["cpu_model"]}
 
 
-def median_run(ctx, m, p, eps, M, cv, seeds, cv_levels=0):
-    """Median wall seconds (measured inside mlmc_run) and the median run."""
-    runs = sorted((ctx.mlmc_run(m, p, eps, M=M, seed=s, precision=32, cv=cv, cv_levels=cv_levels)
-                   for s in seeds), key=lambda r: r["wall_s"])
-    mid = runs[len(runs) // 2]
-    return mid["wall_s"], mid
+def reference_prices():
+    """Continuous-time prices the accuracy runs are measured against
+    (tests/golden/prices.json, written from the oracle's closed forms)."""
+    with open(os.path.join(ROOT, "tests", "golden", "prices.json")) as f:
+        return {k: v["value"] for k, v in json.load(f).items()}
 
 
-def time_to_accuracy(ctx, mlmc, W, args):
-    """Seconds to RMSE eps, plain MLMC vs the learned control variate.
+def seeds_runs(ctx, m, p, eps, M, cv, seeds, exact, cv_levels=0):
+    """Runs over the seeds: median wall seconds, empirical RMSE against the
+    continuous price, and the median run."""
+    import statistics
+    runs = [ctx.mlmc_run(m, p, eps, M=M, seed=s, precision=32, cv=cv, cv_levels=cv_levels)
+            for s in seeds]
+    rmse = (sum((r["estimate"] - exact) ** 2 for r in runs) / len(runs)) ** 0.5
+    mid = sorted(runs, key=lambda r: r["wall_s"])[len(runs) // 2]
+    return statistics.median(r["wall_s"] for r in runs), rmse, mid
+
+
+def time_to_accuracy(ctx, mlmc, W, args, seeds=range(1, 33)):
+    """Seconds to RMSE eps, plain MLMC vs the learned control variate, for
+    the GBM arithmetic Asian and the Heston call, eps in {1e-3, 5e-4} S0,
+    32 seeds each; the empirical RMSE of the estimates against the
+    continuous-time price is reported beside the median time.
 
     The network is trained once per model (Adam, lr 1e-3, batch 16384 samples
-    per level on levels 0..3, i.e. 65536 per step) on the training streams;
-    its training time is reported separately and is not part of the
-    estimation timings, since a trained network is reused.
+    per level on levels 0..3, i.e. 65536 per step) on the training streams.
+    A trained network is reused across estimates, so the estimation times
+    exclude training; `with_training_s` adds it to one estimate.
     """
     import torch
+    ref = reference_prices()
     out = {}
-    cases = (("gbm_asian", W.GBM_MODEL, W.ASIAN, 2), ("heston_call", W.HESTON_MODEL, W.CALL, 3),
-             ("gbm_call", W.GBM_MODEL, W.CALL, 2))
-    seeds = range(1, 6)
-    for name, md, pd, d in cases:
+    cases = (("gbm_asian", W.GBM_MODEL, W.ASIAN, 2, ref["gbm_asian"]),
+             ("heston_call", W.HESTON_MODEL, W.CALL, 3, ref["heston_call"]))
+    for name, md, pd, d, exact in cases:
         m, p = mlmc.model(**md), mlmc.payoff(**pd)
-        entry = {}
+        entry = {"reference_price": exact, "seeds": len(seeds)}
         cv = None
-        if name != "gbm_call" and args.cv_steps > 0:
+        if args.cv_steps > 0:
             cv = mlmc.ControlVariate(ctx, d, init_seed=1)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -164,19 +223,21 @@ def time_to_accuracy(ctx, mlmc, W, args):
             entry["train_s"] = time.perf_counter() - t0
             entry["train_steps"] = args.cv_steps
             entry["loss_first_last"] = [float(hist[0]), float(hist[-1])]
-        for eps in (1e-3, 5e-4, 1e-4):
+        for eps in (1e-3, 5e-4):
             key = f"eps_{eps:g}_S0"
-            tp, rp = median_run(ctx, m, p, eps * W.S0, 4, None, seeds)
-            e = {"plain_s": tp, "plain_cost": rp["cost"], "plain_N": rp["N"],
-                 "plain_V": [round(v, 6) for v in rp["V"]]}
+            tp, ep, rp = seeds_runs(ctx, m, p, eps * W.S0, 4, None, seeds, exact)
+            e = {"target_rmse": eps * W.S0, "plain_s": tp, "plain_rmse": ep, "plain_cost": rp["cost"],
+                 "plain_N": rp["N"], "plain_V": [round(v, 6) for v in rp["V"]]}
             if cv is not None:
-                tc, rc = median_run(ctx, m, p, eps * W.S0, 4, cv, seeds)
-                e.update({"cv_s": tc, "cv_cost": rc["cost"], "cv_N": rc["N"],
-                          "cv_V": [round(v, 6) for v in rc["V"]], "speedup": tp / tc})
+                tc, ec, rc = seeds_runs(ctx, m, p, eps * W.S0, 4, cv, seeds, exact)
+                e.update({"cv_s": tc, "cv_rmse": ec, "cv_cost": rc["cost"], "cv_N": rc["N"],
+                          "cv_V": [round(v, 6) for v in rc["V"]], "speedup": tp / tc,
+                          "cv_with_training_s": tc + entry["train_s"]})
                 # the network on level 0 only: one evaluation per launch
-                t0, r0 = median_run(ctx, m, p, eps * W.S0, 4, cv, seeds, cv_levels=1)
-                e.update({"cv_level0_s": t0, "cv_level0_cost": r0["cost"], "cv_level0_N": r0["N"],
-                          "speedup_level0": tp / t0})
+                t0, e0, r0 = seeds_runs(ctx, m, p, eps * W.S0, 4, cv, seeds, exact, cv_levels=1)
+                e.update({"cv_level0_s": t0, "cv_level0_rmse": e0, "cv_level0_cost": r0["cost"],
+                          "cv_level0_N": r0["N"], "speedup_level0": tp / t0,
+                          "cv_level0_with_training_s": t0 + entry["train_s"]})
             entry[key] = e
         if cv is not None:
             cv.close()
@@ -239,34 +300,23 @@ def persistent_batch(ctx, mlmc, W, reps=3):
             "level8_launch_us": tail}
 
 
-def black_scholes_call(S0, K, r, sigma, T):
-    """Closed-form European call (the limit every level telescopes to)."""
-    import math
-    d1 = (math.log(S0 / K) + (r + 0.5 * sigma * sigma) * T) / (sigma * math.sqrt(T))
-    d2 = d1 - sigma * math.sqrt(T)
-    cdf = lambda x: 0.5 * math.erfc(-x / math.sqrt(2.0))
-    return S0 * cdf(d1) - K * math.exp(-r * T) * cdf(d2)
-
-
 def accuracy_targets(ctx, mlmc, W, seeds=range(1, 33)):
-    """The adaptive configuration's own accuracy targets: GBM call, M = 4,
-    eps in {2e-3, 1e-3, 5e-4} S0, 32 seeds; median wall seconds and the
-    empirical RMSE of the estimates against the Black--Scholes price."""
-    import statistics
-    m, p = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
-    md = W.GBM_MODEL
-    exact = black_scholes_call(md["S0"], W.CALL["K"], md["r"], md["sigma"], md["T"])
-    out = {"workload": "GBM European call, M=4, pilot 1e4, L_min 2, fp32 paths, 32 seeds",
-           "black_scholes": exact}
-    for eps in (2e-3, 1e-3, 5e-4):
-        runs = [ctx.mlmc_run(m, p, eps * W.S0, M=4, seed=s, precision=32) for s in seeds]
-        est = [r["estimate"] for r in runs]
-        rmse = (sum((e - exact) ** 2 for e in est) / len(est)) ** 0.5
-        out[f"eps_{eps:g}_S0"] = {
-            "median_s": statistics.median(r["wall_s"] for r in runs),
-            "rmse_vs_black_scholes": rmse, "target_rmse": eps * W.S0,
-            "L": [r["L"] for r in runs][len(runs) // 2],
-            "N_median_run": sorted(runs, key=lambda r: r["wall_s"])[len(runs) // 2]["N"]}
+    """The configurations' own accuracy targets, 32 seeds each: the adaptive
+    GBM call (M = 4, eps in {2e-3, 1e-3, 5e-4} S0, against Black--Scholes)
+    and the Heston call (M = 4, full-truncation Euler, eps = 1e-3 S0, against
+    the characteristic-function price); median wall seconds and the
+    empirical RMSE of the estimates."""
+    ref = reference_prices()
+    out = {"workload": "M=4, pilot 1e4, L_min 2, fp32 paths, 32 seeds",
+           "black_scholes": ref["gbm_call"], "heston_price": ref["heston_call"]}
+    cases = [("gbm_call", W.GBM_MODEL, eps) for eps in (2e-3, 1e-3, 5e-4)]
+    cases.append(("heston_call", W.HESTON_MODEL, 1e-3))
+    for name, md, eps in cases:
+        m, p = mlmc.model(**md), mlmc.payoff(**W.CALL)
+        t, rmse, mid = seeds_runs(ctx, m, p, eps * W.S0, 4, None, seeds, ref[name])
+        key = f"eps_{eps:g}_S0" if name == "gbm_call" else f"{name}_eps_{eps:g}_S0"
+        out[key] = {"median_s": t, "rmse": rmse, "target_rmse": eps * W.S0, "L": mid["L"],
+                    "N_median_run": mid["N"]}
     return out
 
 

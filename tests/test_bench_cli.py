@@ -22,13 +22,26 @@ def test_bench_help_lists_the_contract_flags():
         assert flag in r.stdout
 
 
-def test_cpu_baseline_fills_its_budget_with_whole_runs():
-    """The oracle leg of the bench line: a run that fits the time budget is
-    repeated, a larger one is scaled down; both report the oracle kind."""
+def test_cpu_baseline_uses_its_budget():
+    """The oracle leg of the bench line: passes over the run's levels, sized
+    from the measured rate, until most of the time budget is used -- both for
+    a run that fits the budget many times and for one far too large for it
+    (scaled down); the host threads, one thread, the CPU model and nproc are
+    reported."""
+    import time
     sys.path.insert(0, ROOT)
     import bench
-    small = bench.cpu_baseline({"N": [4000, 400, 100]}, 4, 0.3)
-    assert small["kind"] == "oracle" and small["cores"] >= 1 and small["value"] > 0
-    assert "pass(es)" in small["sample"] and not small["sample"].startswith("1 pass")
-    big = bench.cpu_baseline({"N": [10**10, 10**9, 10**8]}, 4, 0.3)
-    assert "scaled by" in big["sample"] and big["value"] > 0
+    for N, budget in (([4000, 400, 100], 1.0), ([10**10, 10**9, 10**8], 1.0)):
+        t0 = time.perf_counter()
+        r = bench.cpu_baseline({"N": N}, 4, budget)
+        wall = time.perf_counter() - t0
+        assert r["kind"] == "oracle" and r["cores"] >= 1 and r["value"] > 0
+        assert r["single_thread"]["value"] > 0 and r["nproc"] >= 1 and r["cpu_model"]
+        # both legs spend most of their share of the budget sampling
+        spent = r["single_thread"]["seconds"] + float(r["sample"].split(" in ")[1].split(" s")[0])
+        assert spent >= 0.8 * budget, (N, spent)
+        assert wall <= budget + 6.0, (N, wall)   # warm-up calls and probes
+        if N[0] == 4000:
+            assert r["single_thread"]["passes"] > 1
+        else:
+            assert r["scales"][0] < 0.1
