@@ -185,6 +185,30 @@ mlmc_status mlmc_level(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff
                        int l, int M, uint64_t N, uint64_t seed, uint64_t path_offset,
                        int precision, const mlmc_cv* cv, mlmc_level_result* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums of
+ * mlmc_level (same model, payoff, l, M, N, seed, path_offset, precision, no
+ * control variate) with no context and no allocation.  Runs on the CURRENT
+ * HIP device, enqueued on `hip_stream` (a hipStream_t of that device; NULL =
+ * its null stream), and does not wait: the result is written to d_out, a
+ * caller-owned DEVICE pointer to one mlmc_level_result, when the stream
+ * reaches it.  Non-finite samples are counted in d_out->n_nonfinite (no
+ * MLMC_ENONFINITE, the call does not read the result back).
+ * Scratch: the partial sums go to one group of 64 records (4 KiB) in a static
+ * device array, one per device, held until the process ends; that group
+ * serves any N <= 2^40 (MLMC_EINVAL beyond, as for mlmc_level).  Every call
+ * on a device uses the same array, cleared by a fill kernel at the start of
+ * the call: calls that overlap on one device (other streams, other host
+ * threads) race and must be ordered by the caller.  Kernel launches only (no
+ * memset or copy nodes), so the call can be captured into a graph.
+ * err (may be NULL): a caller buffer of err_len bytes that receives the
+ * reason of a failure ("" on success).  MLMC_EINVAL for bad arguments,
+ * MLMC_EDEVICE for a HIP error (no current device, launch failure).        */
+mlmc_status mlmc_level_noalloc(const mlmc_model* model, const mlmc_payoff* payoff, int l, int M,
+                               uint64_t N, uint64_t seed, uint64_t path_offset, int precision,
+                               void* hip_stream, mlmc_level_result* d_out, char* err,
+                               size_t err_len);
+
 /* Same samples as mlmc_level, per path: d_pf[i] = P_l and d_pc[i] = P_{l-1}
  * of sample path_offset + i, i < N (fp64 device arrays of N entries).
  * For testing; out may be NULL.                                             */

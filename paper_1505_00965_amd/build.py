@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlmc.so")
 SOURCES = ["capi.cpp", "level.hip", "level_gbm.hip", "level_gbm_mil.hip", "level_heston.hip",
-           "driver.hip", "persistent.hip", "cv.hip", "autotune.cpp", "rhee_glynn.hip"]
+           "driver.hip", "persistent.hip", "cv.hip", "autotune.cpp", "rhee_glynn.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -28,34 +28,34 @@ static int level_steps(int l, int M)
     return nf;
 }
 
+const char* level_args_error(const mlmc_model* m, const mlmc_payoff* p, int l, int M, int precision)
+{
+    if (!m || !p) return "model and payoff must not be NULL";
+    if (m->kind != MLMC_GBM && m->kind != MLMC_HESTON) return "unknown model kind";
+    if (p->kind < MLMC_CALL || p->kind > MLMC_DIGITAL_COND) return "unknown payoff kind";
+    if (M != 2 && M != 4) return "M must be 2 or 4";
+    if (l < 0) return "level must be >= 0";
+    if ((M == 2 && l > 18) || (M == 4 && l > 9)) return "level too deep: at most 262144 fine steps";
+    if (precision != 32 && precision != 64) return "precision must be 32 or 64";
+    if (!(m->T > 0) || !(m->S0 > 0) || !std::isfinite(m->r))
+        return "model needs T > 0, S0 > 0 and finite r";
+    if (m->kind == MLMC_GBM && !(m->sigma >= 0)) return "GBM needs sigma >= 0";
+    if (m->kind == MLMC_HESTON &&
+        (!(m->rho >= -1 && m->rho <= 1) || !(m->xi >= 0) || !(m->theta >= 0) || !(m->v0 >= 0)))
+        return "Heston needs |rho| <= 1 and xi, theta, v0 >= 0";
+    if (m->scheme != MLMC_EULER && m->scheme != MLMC_MILSTEIN) return "unknown scheme";
+    if (m->scheme == MLMC_MILSTEIN && m->kind != MLMC_GBM)
+        return "the Milstein scheme is implemented for GBM only";
+    if (m->antithetic != 0 && m->antithetic != 1) return "antithetic must be 0 or 1";
+    return nullptr;
+}
+
 mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payoff* p, int l, int M,
                              int precision)
 {
     if (!ctx) return MLMC_EINVAL;
-    if (!m || !p) return fail(ctx, MLMC_EINVAL, "model and payoff must not be NULL");
-    if (m->kind != MLMC_GBM && m->kind != MLMC_HESTON)
-        return fail(ctx, MLMC_EINVAL, "unknown model kind");
-    if (p->kind < MLMC_CALL || p->kind > MLMC_DIGITAL_COND)
-        return fail(ctx, MLMC_EINVAL, "unknown payoff kind");
-    if (M != 2 && M != 4) return fail(ctx, MLMC_EINVAL, "M must be 2 or 4");
-    if (l < 0) return fail(ctx, MLMC_EINVAL, "level must be >= 0");
-    if ((M == 2 && l > 18) || (M == 4 && l > 9))
-        return fail(ctx, MLMC_EINVAL, "level too deep: at most 262144 fine steps");
-    if (precision != 32 && precision != 64) return fail(ctx, MLMC_EINVAL, "precision must be 32 or 64");
-    if (!(m->T > 0) || !(m->S0 > 0) || !std::isfinite(m->r))
-        return fail(ctx, MLMC_EINVAL, "model needs T > 0, S0 > 0 and finite r");
-    if (m->kind == MLMC_GBM && !(m->sigma >= 0))
-        return fail(ctx, MLMC_EINVAL, "GBM needs sigma >= 0");
-    if (m->kind == MLMC_HESTON &&
-        (!(m->rho >= -1 && m->rho <= 1) || !(m->xi >= 0) || !(m->theta >= 0) || !(m->v0 >= 0)))
-        return fail(ctx, MLMC_EINVAL, "Heston needs |rho| <= 1 and xi, theta, v0 >= 0");
-    if (m->scheme != MLMC_EULER && m->scheme != MLMC_MILSTEIN)
-        return fail(ctx, MLMC_EINVAL, "unknown scheme");
-    if (m->scheme == MLMC_MILSTEIN && m->kind != MLMC_GBM)
-        return fail(ctx, MLMC_EINVAL, "the Milstein scheme is implemented for GBM only");
-    if (m->antithetic != 0 && m->antithetic != 1)
-        return fail(ctx, MLMC_EINVAL, "antithetic must be 0 or 1");
-    return MLMC_OK;
+    const char* why = level_args_error(m, p, l, M, precision);
+    return why ? fail(ctx, MLMC_EINVAL, why) : MLMC_OK;
 }
 
 // Path steps per sample of level l: n_f + n_c (2 n_f + n_c with the twin).
@@ -76,19 +76,30 @@ static bool split_eligible(const mlmc_model& m, const mlmc_payoff& p, int precis
 LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
                          int M, int precision, uint64_t N, uint64_t n_call)
 {
-    LaunchShape s;
-    s.block = ctx->launch_block ? ctx->launch_block : 256;
-    s.ppt = precision == 64 ? 1 : (ctx->launch_ppt ? ctx->launch_ppt : 2);
     int tb = 0, tp = 0;
-    if (!ctx->launch_block && tuned_shape(ctx, m, p.kind, precision, M, l, &tb, &tp)) {
-        s.block = tb;
-        s.ppt = tp;
+    if (ctx->launch_block || !tuned_shape(ctx, m, p.kind, precision, M, l, &tb, &tp)) tb = tp = 0;
+    LaunchShape s = default_shape(m, p, l, M, precision, N, n_call, ctx->num_cu, ctx->launch_block,
+                                  ctx->launch_ppt, tb, tp);
+    s.num_cu = ctx->num_cu;
+    return s;
+}
+
+LaunchShape default_shape(const mlmc_model& m, const mlmc_payoff& p, int l, int M, int precision,
+                          uint64_t N, uint64_t n_call, int num_cu, int fixed_block, int fixed_ppt,
+                          int tuned_block, int tuned_ppt)
+{
+    LaunchShape s;
+    s.block = fixed_block ? fixed_block : 256;
+    s.ppt = precision == 64 ? 1 : (fixed_ppt ? fixed_ppt : 2);
+    if (!fixed_block && tuned_block) {
+        s.block = tuned_block;
+        s.ppt = tuned_ppt;
     }
-    if (!ctx->launch_block) {
+    if (!fixed_block) {
         // few samples: fewer paths per thread so that more lanes take part
         // (the tuner measures device-filling counts, so its ppt is for those)
         const uint64_t lanes = (N + s.ppt - 1) / s.ppt;
-        if (lanes < (uint64_t)ctx->num_cu * 256) s.ppt = 1;
+        if (lanes < (uint64_t)num_cu * 256) s.ppt = 1;
     }
     const int nf = level_steps(l, M);
     uint64_t units = N;   // samples, or generator blocks for one/two-step levels
@@ -99,17 +110,16 @@ LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_pa
     }
     if (m.antithetic && l > 0 && s.ppt > 2) s.ppt = 2;   // the twin doubles the path state
     // GBM levels whose paths cannot fill the device: several lanes per path
-    s.split = split_lanes(nf, n_call ? n_call : N, ctx->num_cu, split_eligible(m, p, precision));
+    s.split = split_lanes(nf, n_call ? n_call : N, num_cu, split_eligible(m, p, precision));
     if (s.split > 1) {
         s.ppt = 1;
         units = N;   // paths, block / split per block at a time
     }
     const uint64_t chunk = s.split > 1 ? (uint64_t)s.block / s.split : (uint64_t)s.block * s.ppt;
     const uint64_t chunks = (units + chunk - 1) / chunk;
-    const uint64_t cap = (uint64_t)ctx->num_cu * (2048 / s.block);
+    const uint64_t cap = (uint64_t)num_cu * (2048 / s.block);
     s.grid = (int)std::max<uint64_t>(1, std::min(chunks, cap));
-    s.num_cu = ctx->num_cu;
-    (void)p;
+    s.num_cu = 0;   // no residency cap unless the caller sets it
     return s;
 }
 
@@ -266,21 +276,31 @@ static mlmc_status enqueue_segment(mlmc_ctx* ctx, const mlmc_model& m, const mlm
     hipEvent_t t0, t1;
     timed_kernel(ctx, l < 16 ? l : 15, (double)N * nf * twins,
                  (coupled && l > 0) ? (double)N * nf / M : 0.0, &t0, &t1);
-    hipError_t e;
+    const hipError_t e = launch_plain_segment(m, p, l, M, N, seed, offset, precision, stream, coupled,
+                                              acc, d_pf, d_pc, spread, shape, ctx->stream, t0, t1);
+    if (e != hipSuccess) return hip_fail(ctx, e, "level kernel launch");
+    return MLMC_OK;
+}
+
+hipError_t launch_plain_segment(const mlmc_model& m, const mlmc_payoff& p, int l, int M, uint64_t N,
+                                uint64_t seed, uint64_t offset, int precision, uint32_t stream,
+                                int coupled, LevelAcc* acc, double* d_pf, double* d_pc, bool spread,
+                                const LaunchShape& shape, hipStream_t st, hipEvent_t t0,
+                                hipEvent_t t1)
+{
+    const uint32_t mask = spread ? (uint32_t)(kSpread - 1) : 0u;
+    const int dim = m.kind == MLMC_HESTON ? 2 : 1;
     if (precision == 64) {
         auto a = make_args<double>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
         a.spread_mask = mask;
         set_counter_words(a, dim);
-        e = launch_level(m, p, M, 64, &a, shape, ctx->stream, t0, t1);
-    } else {
-        auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
-        a.spread_mask = mask;
-        a.split = (uint32_t)shape.split;
-        set_counter_words(a, dim);
-        e = launch_level(m, p, M, 32, &a, shape, ctx->stream, t0, t1);
+        return launch_level(m, p, M, 64, &a, shape, st, t0, t1);
     }
-    if (e != hipSuccess) return hip_fail(ctx, e, "level kernel launch");
-    return MLMC_OK;
+    auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
+    a.spread_mask = mask;
+    a.split = (uint32_t)shape.split;
+    set_counter_words(a, dim);
+    return launch_level(m, p, M, 32, &a, shape, st, t0, t1);
 }
 
 mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,

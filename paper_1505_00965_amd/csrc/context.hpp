@@ -68,11 +68,29 @@ mlmc_status hip_fail(mlmc_ctx* ctx, hipError_t e, const char* what);
 double level_cost(const mlmc_model& m, int l, int M);
 mlmc_status check_level_args(mlmc_ctx* ctx, const mlmc_model* m, const mlmc_payoff* p, int l, int M,
                              int precision);
+// The same checks without a context: the reason (a static string) or null.
+const char* level_args_error(const mlmc_model* m, const mlmc_payoff* p, int l, int M, int precision);
 // Launch shape for N samples at level l (honours mlmc_set_launch); paths
 // are split across lanes by the count of the whole call, n_call >= N (a call
 // may be cut into several launches at the counter's high word).
 LaunchShape choose_shape(const mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l,
                          int M, int precision, uint64_t N, uint64_t n_call = 0);
+// The rule behind choose_shape, from its inputs alone: a fixed shape
+// (fixed_block != 0), else a tuned one (tuned_block != 0), else 256 threads
+// and 2 samples per lane; one sample per lane when fewer than 256 lanes per
+// compute unit would be busy; one- and two-step levels at most 2 blocks per
+// lane; GBM paths split across lanes when too few fill the device.  The
+// returned shape has no residency cap (num_cu = 0).
+LaunchShape default_shape(const mlmc_model& m, const mlmc_payoff& p, int l, int M, int precision,
+                          uint64_t N, uint64_t n_call, int num_cu, int fixed_block, int fixed_ppt,
+                          int tuned_block, int tuned_ppt);
+// One plain-sampler launch over a range whose generator units share their
+// counter word 2 (no control variate): arguments as for enqueue_level.
+hipError_t launch_plain_segment(const mlmc_model& m, const mlmc_payoff& p, int l, int M, uint64_t N,
+                                uint64_t seed, uint64_t offset, int precision, uint32_t stream,
+                                int coupled, LevelAcc* acc, double* d_pf, double* d_pc, bool spread,
+                                const LaunchShape& shape, hipStream_t st, hipEvent_t t0 = nullptr,
+                                hipEvent_t t1 = nullptr);
 // Enqueue one level into record `acc`, or with `spread` into the spread
 // group of kSpread records at `acc` (no zeroing, no sync).
 mlmc_status enqueue_level(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,

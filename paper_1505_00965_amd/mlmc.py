@@ -25,7 +25,7 @@ EXPORTED = [
     "mlmc_cv_create", "mlmc_cv_destroy", "mlmc_cv_nparams", "mlmc_cv_get_params",
     "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train", "mlmc_autotune",
     "mlmc_autotune_persistent",
-    "mlmc_tuned_shape", "mlmc_rhee_glynn", "mlmc_set_timing_mask",
+    "mlmc_tuned_shape", "mlmc_rhee_glynn", "mlmc_set_timing_mask", "mlmc_level_noalloc",
 ]
 STAT_SLOTS = 20
 STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
@@ -152,6 +152,8 @@ def lib():
     L.mlmc_set_timing.argtypes = [vp, i32]
     L.mlmc_set_timing_mask.argtypes = [vp, u32]
     L.mlmc_kernel_stats.argtypes = [vp, C.POINTER(KernelStat)]
+    L.mlmc_level_noalloc.argtypes = [M_, P_, i32, i32, u64, u64, u64, i32, vp, vp, C.c_char_p,
+                                     C.c_size_t]
     for name in EXPORTED:
         if name != "mlmc_last_error":
             getattr(L, name).restype = i32
@@ -176,6 +178,27 @@ def _ptr(t):
     if isinstance(t, int):
         return t
     return t.data_ptr()
+
+
+def mlmc_level_noalloc(m, p, l, M, N, seed, d_out, path_offset=0, precision=32, stream=None):
+    """mlmc_level's sums with no context and no allocation, enqueued on
+    `stream` (a torch stream or raw handle; None = the null stream) of the
+    current device; d_out: a device tensor of at least 72 bytes (e.g. 9
+    float64) that receives the mlmc_level_result.  Does not synchronise."""
+    L = lib()
+    h = None if stream is None else getattr(stream, "cuda_stream", stream)
+    err = C.create_string_buffer(256)
+    st = L.mlmc_level_noalloc(C.byref(m), C.byref(p), l, M, N, seed, path_offset, precision, h,
+                              _ptr(d_out), err, len(err))
+    if st != MLMC_OK:
+        raise MLMCError(st, err.value.decode())
+
+
+def level_result_from(t):
+    """Decode the 72-byte mlmc_level_result held in a device tensor."""
+    raw = t.detach().cpu().contiguous().view(-1).numpy().tobytes()[:C.sizeof(LevelResult)]
+    r = LevelResult.from_buffer_copy(raw)
+    return r.as_dict()
 
 
 class Context:
