@@ -18,6 +18,7 @@ SOURCES = ["capi.cpp", "level.hip", "level_gbm.hip", "level_gbm_mil.hip", "level
            "driver.hip", "persistent.hip", "cv.hip", "autotune.cpp", "rhee_glynn.hip",
            "noalloc.hip"]
 ARCH = "gfx950"
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 
 def hipcc():
@@ -56,7 +57,9 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    # ROCTx ranges (trace.hpp): the ROCm profiler SDK's marker library
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + [
+        "-L", ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

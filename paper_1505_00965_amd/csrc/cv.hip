@@ -16,6 +16,7 @@
 #include "context.hpp"
 #include "cv.hpp"
 #include "sampler_impl.hpp"
+#include "trace.hpp"
 
 using namespace mlmc::cvnet;
 
@@ -717,6 +718,7 @@ mlmc_status mlmc_cv_train(mlmc_cv* cv, const mlmc_model* model, const mlmc_payof
     if (loss_hist && steps > 0) MLMC_HIP(ctx, hipMalloc(&d_hist, sizeof(double) * steps));
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     for (int k = 0; k < steps; ++k) {
+        const TraceRange step_range("mlmc_cv_train step");
         float* d_grad = nullptr;
         // each step draws fresh training samples: indices t * batch .. (t+1) * batch - 1
         st = enqueue_loss_grad(cv, *model, *payoff, M, lmax, batch, seed, (uint64_t)cv->adam_t, ctx->d_acc,

@@ -12,6 +12,7 @@
 #include "context.hpp"
 #include "driver.hpp"
 #include "driver_dev.hpp"
+#include "trace.hpp"
 
 namespace mlmc {
 
@@ -165,6 +166,7 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     if (model->antithetic && o.persistent)
         return fail(ctx, MLMC_EINVAL, "the antithetic estimator runs with per-level launches only");
     ctx->err.clear();
+    const TraceRange run_range("mlmc_run");
     const auto t0 = std::chrono::steady_clock::now();
     MLMC_HIP(ctx, hipSetDevice(ctx->device));
     st = ensure_driver(ctx);
@@ -219,6 +221,7 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
             // the mirror is not being written
             if (it > h->max_iterations + 1)
                 return fail(ctx, MLMC_EDEVICE, "driver state did not reach the host");
+            const TraceRange iter_range("mlmc_run driver iteration");
             // deepest level first: level 0's launch (the largest, and the
             // dearest for the host when its kernels are timed) is enqueued
             // last, while the deeper levels run

@@ -22,6 +22,7 @@
 #include "context.hpp"
 #include "driver.hpp"
 #include "sampler_impl.hpp"
+#include "trace.hpp"
 
 namespace mlmc {
 
@@ -505,6 +506,7 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     for (int it = 0;; ++it) {
         if (it > h_st->max_iterations + 1)
             return fail(ctx, MLMC_EDEVICE, "driver state did not reach the host");
+        const TraceRange iter_range("mlmc_run driver iteration (graph)");
         for (int k = it ? 1 : 0; k < 2; ++k) {
             const int tix = timed_begin(ctx, 16, 0.0, 0.0);
             if (first_tix < 0) first_tix = tix;
