@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB selects another build of the same sources (the sanitizer build)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 GBM, HESTON = 0, 1
 EULER, MILSTEIN = 0, 1
