@@ -91,7 +91,68 @@ def parse():
                     help="run a 256 MiB device copy first (scales HBM byte counters)")
     ap.add_argument("--persistent", type=int, default=0,
                     help="1: each driver iteration is one graph launch of the persistent kernel")
+    # kernel profiling mode (for rocprofv3 counter runs): only repeated
+    # launches of one level's sampler, with the tuned shape, then one JSON line
+    ap.add_argument("--profile-level", type=int, default=None,
+                    help="profile mode: time only mlmc_level launches at this level (M=4)")
+    ap.add_argument("--profile-samples", type=float, default=0,
+                    help="samples per profiled launch (0: the adaptive run's N_l at RMSE 2e-5*S0)")
+    ap.add_argument("--profile-launches", type=int, default=5)
+    ap.add_argument("--profile-model", choices=("gbm", "heston"), default="gbm")
+    ap.add_argument("--profile-payoff", choices=("call", "asian", "lookback", "digital"),
+                    default="call")
+    ap.add_argument("--profile-cv", action="store_true",
+                    help="profile the control-variate sampler (and one training gradient per "
+                         "launch) with a network trained for 50 steps")
     return ap.parse_args()
+
+
+# samples per level of the adaptive run at RMSE 2e-5*S0 (seed 1)
+ADAPTIVE_N = [200141355, 14852584, 3713146, 928287, 232072]
+
+
+def profile_mode(args):
+    """Launch one level's sampler `launches` times (the last launches of the
+    run are these: counter runs take them by kernel name from the end)."""
+    import torch
+    from paper_1505_00965_amd import mlmc, workloads as W
+    ctx = mlmc.Context(0)
+    ctx.set_stream(torch.cuda.current_stream())
+    md = W.GBM_MODEL if args.profile_model == "gbm" else W.HESTON_MODEL
+    m, p = mlmc.model(**md), mlmc.payoff(**W.PAYOFFS[args.profile_payoff])
+    l, M = args.profile_level, 4
+    N = int(args.profile_samples) or (ADAPTIVE_N[l] if l < len(ADAPTIVE_N) else 1 << 16)
+    cv = None
+    if args.profile_cv:
+        cv = mlmc.ControlVariate(ctx, 3 if args.profile_model == "heston" else 2, init_seed=1)
+        cv.train(m, p, M=M, lmax=3, steps=50, batch=16384, lr=1e-3, seed=2)
+    else:
+        ctx.autotune(m, p, M=M, precision=32)
+    torch.cuda.synchronize()
+    ctx.set_timing_slots([l])
+    t0 = time.perf_counter()
+    for r in range(args.profile_launches):
+        ctx.mlmc_level(m, p, l, M, N, 1 + r, cv=cv)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.kernel_stats()[l]
+    ctx.set_timing(False)
+    grads = 0
+    if cv is not None:
+        for r in range(args.profile_launches):
+            cv.loss_grad(m, p, M, 3, 16384, 7, r)
+            grads += 1
+        torch.cuda.synchronize()
+    nf = M**l
+    out = {"mode": "profile", "model": args.profile_model, "payoff": args.profile_payoff,
+           "level": l, "M": M, "samples_per_launch": N, "launches": args.profile_launches,
+           "fine_steps_per_launch": N * nf, "avg_launch_ms": st["ms"] / max(st["launches"], 1),
+           "wall_s": wall, "cv": bool(cv), "cv_gradients": grads,
+           "tuned_shape": None if cv else ctx.tuned_shape(m, p, l, M=M)}
+    if cv is not None:
+        cv.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def fine_steps_of(res, M):
@@ -382,6 +443,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.profile_level is not None:
+        return profile_mode(args)
     ctx = mlmc.Context(0)
     stream = torch.cuda.current_stream()
     ctx.set_stream(stream)
@@ -395,6 +458,26 @@ def main():
 
     for i in range(args.warmup):
         step(1 + i % max(args.steps, 1))   # same seeds, hence launch sizes, as timed steps
+    # context: the same steps with the default launch shapes, before tuning
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(1 + i)
+    torch.cuda.synchronize()
+    dt_default = time.perf_counter() - t0
+    # the launch-shape autotuner for this model, payoff and M (three level
+    # classes, block x samples per lane, measured on this device); every
+    # later launch takes the tuned shapes
+    tune = {}
+    t0 = time.perf_counter()
+    if args.persistent:
+        tune["persistent"] = ctx.autotune_persistent(gm, [gp], M=M, L=4)
+    else:
+        ctx.autotune(gm, gp, M=M, precision=32)
+        tune.update({f"level_{l}": ctx.tuned_shape(gm, gp, l, M=M) for l in (0, 1, 3)})
+    tune["tuning_s"] = time.perf_counter() - t0
+    for i in range(args.warmup):
+        step(1 + i % max(args.steps, 1))
     # Which kernel dominates: every slot timed over the same steps, untimed
     # by the clock.  The timed region then stamps only that kernel's launches
     # (each stamped launch costs the host ~10 us more than a plain one).
@@ -450,20 +533,38 @@ def main():
             achieved = ops_per_launch / (avg_ms * 1e-3)
             label = ("short_level_kernel<GBM,call,fp32,n_f=1>" if lv == 0
                      else f"level_kernel<GBM,call,fp32,M=4> at level {lv}")
+            samples_per_s = samples / s["launches"] / (avg_ms * 1e-3)
             roofline = {"bound": "alu", "achieved": achieved / 1e12,
                         "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
                         "frac": achieved / VALU_PEAK_OPS, "traffic": measured_traffic(label),
                         "kernel": label,
-                        # issued vector instructions x 4 cycles over SIMD cycles, from
-                        # SQ_INSTS_VALU and GRBM_GUI_ACTIVE (issue slots, not method ops)
-                        "valu_issue_frac_counters": profile_field(label, "valu_issue_frac"),
+                        # the target (half the vector-ALU peak) is judged by `frac`:
+                        # executed operations per sample over the issue peak
+                        "ops_per_sample": {"executed": OPS_PER_SAMPLE_L0 if lv == 0 else None,
+                                           "method": OPS_PER_SAMPLE_L0_METHOD if lv == 0 else None},
+                        "frac_method_ops": (achieved / VALU_PEAK_OPS * OPS_PER_SAMPLE_L0_METHOD
+                                            / OPS_PER_SAMPLE_L0 if lv == 0 else None),
                         "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_ms,
                         "launches": s["launches"],
                         "fine_steps_per_launch": s["fine_steps"] / s["launches"]}
+            # from the committed counter summaries of this kernel (profiles/):
+            # issued vector instructions x 4 cycles over SIMD cycles
+            # (SQ_INSTS_VALU, GRBM_GUI_ACTIVE); this run's rate against the
+            # ceiling those instructions allow; fp32 FLOPs (an fma counts 2,
+            # SQ_INSTS_VALU_FLOPS_FP32 + _TRANS) per second over the fp32 peak
+            roofline["valu_issue_frac_counters"] = profile_field(label, "valu_issue_frac")
+            ipsamp = profile_field(label, "valu_insts_per_sample")
+            roofline["valu_insts_per_sample"] = ipsamp
+            roofline["slot_ceiling_frac"] = (samples_per_s * ipsamp / VALU_PEAK_OPS
+                                             if ipsamp else None)
+            fps = profile_field(label, "fp32_flops_per_sample")
+            roofline["fp32_flops_per_sample"] = fps
+            roofline["fp32_flop_frac"] = samples_per_s * fps / FP32_PEAK_FLOPS if fps else None
 
     line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
             "ms_per_step_unstamped": 1e3 * dt_unstamped / args.steps,
+            "ms_per_step_default_shapes": 1e3 * dt_default / args.steps,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": f"adaptive MLMC, GBM European call S0=100 r=0.05 sigma=0.2 "
@@ -471,12 +572,16 @@ def main():
                                    + ("one graph launch per driver iteration" if args.persistent
                                       else "one level per launch"),
                        "levels": runs[-1]["L"] + 1, "N_l": runs[-1]["N"],
-                       "estimate": runs[-1]["estimate"]},
+                       "estimate": runs[-1]["estimate"], "tuned_shapes": tune},
             "roofline": roofline}
 
     if not args.persistent and not args.no_tta:
         # the same estimates with every driver iteration as one graph launch
-        # (plan, persistent all-levels sampler, driver update)
+        # (plan, persistent all-levels sampler, driver update), in the shape
+        # the persistent form's tuner picks for this payoff and depth
+        t0 = time.perf_counter()
+        pshape = ctx.autotune_persistent(gm, [gp], M=M, L=runs[-1]["L"])
+        ptune_s = time.perf_counter() - t0
         for i in range(args.warmup):
             ctx.mlmc_run(gm, gp, eps, M=M, L_min=2, L_max=9, n_pilot=10000,
                          seed=1 + i % max(args.steps, 1), precision=32, persistent=True)
@@ -488,6 +593,8 @@ def main():
         dtg = time.perf_counter() - t0
         line["adaptive_graph_form"] = {
             "ms_per_step": 1e3 * dtg / args.steps,
+            "tuned_shape": {"block": pshape[0], "ppt": pshape[1], "blocks_per_cu": pshape[2],
+                            "tuning_s": ptune_s},
             "fine_path_steps_per_s": sum(fine_steps_of(r, M) for r in gr) / dtg,
             "same_N_l": all(a["N"] == b["N"] for a, b in zip(runs, gr))}
     if not args.no_tta:
