@@ -130,11 +130,65 @@ static void forward(const orc_model *m, const orc_cv *cv, double t, double S, do
     c->y = y;
 }
 
+static double clamp(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+/* Interpolate the table at (t, S, v): the row of the last grid time at or
+ * before t, then linear in S (and in v) between the two grid points around
+ * the clamped coordinate. */
+static double table_value(const orc_model *m, const orc_cv_table *g, double t, double S, double v)
+{
+    int j = (int)floor(t / m->T * g->rows + 1e-9);
+    if (j > g->rows - 1) j = g->rows - 1;
+    double u = (S - g->s_lo) / ((g->s_hi - g->s_lo) / (g->ns - 1));
+    u = isnan(u) ? 0.0 : clamp(u, 0.0, g->ns - 1);
+    int i = (int)u < g->ns - 2 ? (int)u : g->ns - 2;
+    double f = u - i;
+    const double *row = g->values + (size_t)j * g->nv * g->ns;
+    if (g->nv == 1) return (1.0 - f) * row[i] + f * row[i + 1];
+    double w = (v - g->v_lo) / ((g->v_hi - g->v_lo) / (g->nv - 1));
+    w = isnan(w) ? 0.0 : clamp(w, 0.0, g->nv - 1);
+    int k = (int)w < g->nv - 2 ? (int)w : g->nv - 2;
+    double e = w - k;
+    const double *r0 = row + (size_t)k * g->ns, *r1 = r0 + g->ns;
+    double a = (1.0 - f) * r0[i] + f * r0[i + 1];
+    double b = (1.0 - f) * r1[i] + f * r1[i + 1];
+    return (1.0 - e) * a + e * b;
+}
+
 double orc_cv_phi(const orc_model *m, const orc_cv *cv, double t, double S, double v)
 {
+    if (cv->table) return table_value(m, cv->table, t, S, v);
     fwd_cache c;
     forward(m, cv, t, S, v, &c);
     return orc_cv_out_scale(m) * c.y;
+}
+
+void orc_cv_table_grid(const orc_model *m, orc_cv_table *g)
+{
+    int heston = m->kind == ORC_HESTON;
+    double spread = 6.0 * sref_of(m) * sqrt(m->T);
+    g->rows = heston ? 8 : 16;
+    g->ns = heston ? 128 : 512;
+    g->nv = heston ? 8 : 1;
+    g->s_lo = m->S0 * exp(-spread);
+    g->s_hi = m->S0 * exp(spread);
+    g->v_lo = 0.0;
+    g->v_hi = heston ? 5.0 * (m->theta > m->v0 ? m->theta : m->v0) : 1.0;
+    g->values = NULL;
+}
+
+void orc_cv_table_fill(const orc_model *m, const orc_cv *cv, const orc_cv_table *g,
+                       double *values)
+{
+    orc_cv net = *cv;
+    net.table = NULL;
+    double ds = (g->s_hi - g->s_lo) / (g->ns - 1);
+    double dv = g->nv > 1 ? (g->v_hi - g->v_lo) / (g->nv - 1) : 0.0;
+    for (int j = 0; j < g->rows; ++j)
+        for (int k = 0; k < g->nv; ++k)
+            for (int i = 0; i < g->ns; ++i)
+                values[((size_t)j * g->nv + k) * g->ns + i] =
+                    orc_cv_phi(m, &net, j * m->T / g->rows, g->s_lo + i * ds, g->v_lo + k * dv);
 }
 
 void orc_cv_phi_grad(const orc_model *m, const orc_cv *cv, double t, double S, double v,

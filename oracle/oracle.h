@@ -69,12 +69,27 @@ typedef struct {
  * Parameter vector layout (float64 here, fp32 master on the GPU):
  *   W1[H][D] (row-major), b1[H], W2[H][H] (row j = output unit), b2[H],
  *   w3[H], b3.   H = 64, D = 2 (GBM) or 3 (Heston).                      */
+/* Tabulated form of the network (a reading; the paper has no network):
+ * values[(j nv + k) ns + i] = phi(t_j, S_i, v_k) on the grid t_j = j T / rows,
+ * S_i = s_lo + i (s_hi - s_lo)/(ns - 1), v_k = v_lo + k (v_hi - v_lo)/(nv - 1)
+ * (nv = 1: no variance axis).  phi at a left point (t, S, v) is then read in
+ * row floor(t rows / T) and interpolated linearly in S (bilinearly in S, v),
+ * with S and v first clamped to the grid.  The grid for a model
+ * (orc_cv_table_grid): s_lo, s_hi = S0 exp(-+6 sref sqrt T); GBM rows 16,
+ * ns 512, nv 1; Heston rows 8, ns 128, nv 8, v in [0, 5 max(theta, v0)].    */
+typedef struct {
+    int rows, ns, nv;
+    double s_lo, s_hi, v_lo, v_hi;
+    const double *values;
+} orc_cv_table;
+
 typedef struct {
     int in_dim;           /* 2 or 3 */
     int hidden;           /* 64 */
     const double *params; /* in_dim*H + H + H*H + H + H + 1 values */
     int bf16_emulate;     /* 1: round W2 and the layer-1 activations to bf16
                              exactly where the GPU feeds its matrix cores     */
+    const orc_cv_table *table;  /* non-NULL: phi is read from this table   */
 } orc_cv;
 
 typedef struct {
@@ -200,8 +215,13 @@ void orc_cv_init(int in_dim, int hidden, uint64_t init_seed, double *params);
  * x[2] = (v - theta)/theta for Heston.                                       */
 void orc_cv_inputs(const orc_model *m, double t, double S, double v, double *x);
 double orc_cv_out_scale(const orc_model *m);
-/* phi(t, X) for one point (includes out_scale). */
+/* phi(t, X) for one point (includes out_scale); from cv->table if set. */
 double orc_cv_phi(const orc_model *m, const orc_cv *cv, double t, double S, double v);
+/* The grid of the tabulated form for model m (values left NULL). */
+void orc_cv_table_grid(const orc_model *m, orc_cv_table *g);
+/* Fill values (rows * nv * ns) with the network cv (its table ignored). */
+void orc_cv_table_fill(const orc_model *m, const orc_cv *cv, const orc_cv_table *g,
+                       double *values);
 /* Accumulate g * d phi / d params into grad (includes out_scale). */
 void orc_cv_phi_grad(const orc_model *m, const orc_cv *cv, double t, double S, double v,
                      double g, double *grad);

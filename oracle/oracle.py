@@ -31,9 +31,16 @@ class Payoff(C.Structure):
     _fields_ = [("kind", C.c_int), ("K", C.c_double), ("payout", C.c_double)]
 
 
+class CVTable(C.Structure):
+    _fields_ = [("rows", C.c_int), ("ns", C.c_int), ("nv", C.c_int), ("s_lo", C.c_double),
+                ("s_hi", C.c_double), ("v_lo", C.c_double), ("v_hi", C.c_double),
+                ("values", C.POINTER(C.c_double))]
+
+
 class CV(C.Structure):
     _fields_ = [("in_dim", C.c_int), ("hidden", C.c_int),
-                ("params", C.POINTER(C.c_double)), ("bf16_emulate", C.c_int)]
+                ("params", C.POINTER(C.c_double)), ("bf16_emulate", C.c_int),
+                ("table", C.POINTER(CVTable))]
 
 
 class LevelResult(C.Structure):
@@ -120,6 +127,8 @@ def lib():
         L.orc_cv_phi.argtypes = [C.POINTER(Model), C.POINTER(CV), d, d, d]
         L.orc_cv_phi.restype = d
         L.orc_cv_phi_grad.argtypes = [C.POINTER(Model), C.POINTER(CV), d, d, d, d, dp]
+        L.orc_cv_table_grid.argtypes = [C.POINTER(Model), C.POINTER(CVTable)]
+        L.orc_cv_table_fill.argtypes = [C.POINTER(Model), C.POINTER(CV), C.POINTER(CVTable), dp]
         L.orc_cv_loss_grad.argtypes = [C.POINTER(Model), C.POINTER(Payoff), i32, i32, u64, u64,
                                        u64, C.POINTER(CV), i32, dp, dp]
         L.orc_cv_loss_grad.restype = d
@@ -150,15 +159,38 @@ def payoff(kind=CALL, K=100.0, payout=1.0):
 
 
 class CVNet:
-    """Holds an FP64 parameter vector and the C view of it."""
+    """Holds an FP64 parameter vector and the C view of it.  With a table
+    (values shaped [rows, nv, ns] on the grid cv_table_grid gives for the
+    model) phi is read from the table instead of the network."""
 
-    def __init__(self, params, in_dim=2, hidden=64, bf16_emulate=False):
+    def __init__(self, params, in_dim=2, hidden=64, bf16_emulate=False, table=None, grid=None):
         self.params = np.ascontiguousarray(params, dtype=np.float64)
         self.in_dim, self.hidden = in_dim, hidden
-        self.c = CV(in_dim, hidden, _dp(self.params), int(bf16_emulate))
+        self.c = CV(in_dim, hidden, _dp(self.params), int(bf16_emulate), None)
+        self.table = None
+        if table is not None:
+            self.values = np.ascontiguousarray(table, dtype=np.float64).ravel()
+            g = grid
+            assert self.values.size == g.rows * g.nv * g.ns
+            self.table = CVTable(g.rows, g.ns, g.nv, g.s_lo, g.s_hi, g.v_lo, g.v_hi,
+                                 _dp(self.values))
+            self.c.table = C.pointer(self.table)
 
     def ref(self):
         return C.byref(self.c)
+
+
+def cv_table_grid(m):
+    g = CVTable()
+    lib().orc_cv_table_grid(C.byref(m), C.byref(g))
+    return g
+
+
+def cv_table_fill(m, cv, grid):
+    """The network cv on the grid: array [rows, nv, ns]."""
+    out = np.zeros(grid.rows * grid.nv * grid.ns)
+    lib().orc_cv_table_fill(C.byref(m), cv.ref(), C.byref(grid), _dp(out))
+    return out.reshape(grid.rows, grid.nv, grid.ns)
 
 
 def _cvref(cv):
