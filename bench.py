@@ -104,6 +104,8 @@ def parse():
     ap.add_argument("--profile-cv", action="store_true",
                     help="profile the control-variate sampler (and one training gradient per "
                          "launch) with a network trained for 50 steps")
+    ap.add_argument("--profile-cv-tab", action="store_true",
+                    help="with --profile-cv: the tabulated network in the sampler")
     return ap.parse_args()
 
 
@@ -126,6 +128,7 @@ def profile_mode(args):
     if args.profile_cv:
         cv = mlmc.ControlVariate(ctx, 3 if args.profile_model == "heston" else 2, init_seed=1)
         cv.train(m, p, M=M, lmax=3, steps=50, batch=16384, lr=1e-3, seed=2)
+        cv.set_tabulated(args.profile_cv_tab)
     else:
         ctx.autotune(m, p, M=M, precision=32)
     torch.cuda.synchronize()
@@ -299,6 +302,14 @@ def time_to_accuracy(ctx, mlmc, W, args, seeds=range(1, 33)):
                 e.update({"cv_level0_s": t0, "cv_level0_rmse": e0, "cv_level0_cost": r0["cost"],
                           "cv_level0_N": r0["N"], "speedup_level0": tp / t0,
                           "cv_level0_with_training_s": t0 + entry["train_s"]})
+                # the tabulated network on every level (built once per
+                # parameter change, interpolated by the samplers)
+                cv.set_tabulated(True)
+                tt, et, rt = seeds_runs(ctx, m, p, eps * W.S0, 4, cv, seeds, exact)
+                cv.set_tabulated(False)
+                e.update({"cv_tab_s": tt, "cv_tab_rmse": et, "cv_tab_cost": rt["cost"],
+                          "cv_tab_N": rt["N"], "cv_tab_V": [round(v, 6) for v in rt["V"]],
+                          "speedup_tab": tp / tt, "cv_tab_with_training_s": tt + entry["train_s"]})
             entry[key] = e
         if cv is not None:
             cv.close()

@@ -380,6 +380,27 @@ size_t mlmc_cv_nparams(const mlmc_cv* cv);
 mlmc_status mlmc_cv_get_params(const mlmc_cv* cv, float* host, size_t n);
 mlmc_status mlmc_cv_set_params(mlmc_cv* cv, const float* host, size_t n);
 
+/* Tabulated evaluation (on = 1) or the network itself (on = 0, the default)
+ * in the estimation samplers (mlmc_level and mlmc_run with this network).
+ * Tabulated: phi is evaluated once per parameter change and model on a grid
+ * -- rows t_j = j T / R, stock values S_i = s_lo + i (s_hi - s_lo) / (ns - 1)
+ * with s_lo, s_hi = S0 exp(-+4 sref sqrt T), and for Heston variances
+ * v_k = k v_hi / (nv - 1), v_hi = 4 max(theta, v0); GBM R = 256, ns = 32,
+ * nv = 1; Heston R = 16, ns = 16, nv = 32 -- and the samplers interpolate it
+ * linearly in S (bilinearly in S and v; points beyond the grid take its
+ * edge) in row floor(n R / n_f) for the left point of fine step n (coarse
+ * step m: n = m M).  Any function of (t_n, X_n) keeps the control variate's
+ * mean at zero, so the level means are unchanged; the table only changes the
+ * variance removed and the cost (a few operations per point instead of a
+ * network evaluation).  Training always evaluates the network itself.        */
+mlmc_status mlmc_cv_set_tabulated(mlmc_cv* cv, int on);
+/* The table of the tabulated form for `model` (built if needed), as
+ * host[(j nv + k) ns + i] = phi(t_j, S_i, v_k); dims (host, 3 ints, may be
+ * NULL) receives R, nv, ns.  host may be NULL (dims only); otherwise n must
+ * be R nv ns.                                                               */
+mlmc_status mlmc_cv_get_table(mlmc_cv* cv, const mlmc_model* model, float* host, size_t n,
+                              int* dims);
+
 /* Training objective on B samples per level l = 0..lmax from the training
  * streams (Philox streams 2 and 3, disjoint from estimation), sample indices
  * step * B .. step * B + B - 1:

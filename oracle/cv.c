@@ -166,14 +166,14 @@ double orc_cv_phi(const orc_model *m, const orc_cv *cv, double t, double S, doub
 void orc_cv_table_grid(const orc_model *m, orc_cv_table *g)
 {
     int heston = m->kind == ORC_HESTON;
-    double spread = 6.0 * sref_of(m) * sqrt(m->T);
-    g->rows = heston ? 8 : 16;
-    g->ns = heston ? 128 : 512;
-    g->nv = heston ? 8 : 1;
+    double spread = 4.0 * sref_of(m) * sqrt(m->T);
+    g->rows = heston ? 16 : 256;
+    g->ns = heston ? 16 : 32;
+    g->nv = heston ? 32 : 1;
     g->s_lo = m->S0 * exp(-spread);
     g->s_hi = m->S0 * exp(spread);
     g->v_lo = 0.0;
-    g->v_hi = heston ? 5.0 * (m->theta > m->v0 ? m->theta : m->v0) : 1.0;
+    g->v_hi = heston ? 4.0 * (m->theta > m->v0 ? m->theta : m->v0) : 1.0;
     g->values = NULL;
 }
 

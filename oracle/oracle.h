@@ -75,8 +75,8 @@ typedef struct {
  * (nv = 1: no variance axis).  phi at a left point (t, S, v) is then read in
  * row floor(t rows / T) and interpolated linearly in S (bilinearly in S, v),
  * with S and v first clamped to the grid.  The grid for a model
- * (orc_cv_table_grid): s_lo, s_hi = S0 exp(-+6 sref sqrt T); GBM rows 16,
- * ns 512, nv 1; Heston rows 8, ns 128, nv 8, v in [0, 5 max(theta, v0)].    */
+ * (orc_cv_table_grid): s_lo, s_hi = S0 exp(-+4 sref sqrt T); GBM rows 256,
+ * ns 32, nv 1; Heston rows 16, ns 16, nv 32, v in [0, 4 max(theta, v0)].   */
 typedef struct {
     int rows, ns, nv;
     double s_lo, s_hi, v_lo, v_hi;

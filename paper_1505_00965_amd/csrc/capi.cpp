@@ -250,21 +250,35 @@ static mlmc_status enqueue_segment(mlmc_ctx* ctx, const mlmc_model& m, const mlm
         auto a = make_args<float>(m, p, l, M, N, seed, offset, stream, coupled, acc, d_pf, d_pc);
         a.spread_mask = mask;
         set_counter_words(a, dim);
+        // estimation may read the network from its table; training evaluates it
+        const bool tab = cv_tabulated(cv) && stream != kStreamTrainNormal;
         hipError_t e;
         if (l == 0) {
             // one step from (0, S0): phi is the single value phi(0, S0)
-            e = cv_ensure_phi0(cv, m, ctx->stream);
+            e = cv_ensure_phi0(cv, m, ctx->stream, tab);
             if (e != hipSuccess) return hip_fail(ctx, e, "phi(0, S0) launch");
-            a.phi0 = cv_phi0_ptr(cv);
+            a.phi0 = cv_phi0_ptr(cv, tab);
             LaunchShape shape = choose_shape(ctx, m, p, l, M, 32, N);
             hipEvent_t t0, t1;
             timed_kernel(ctx, 0, (double)N, 0.0, &t0, &t1);
             e = launch_level(m, p, M, 32, &a, shape, ctx->stream, t0, t1);
         } else {
-            const uint64_t chunks = (N + 255) / 256;
-            const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, (uint64_t)ctx->num_cu * 8));
+            // the tabulated sampler: GBM paths too few to fill the device run
+            // on several lanes each (the plain sampler's rule on the call's
+            // count), two samples per lane when there are lanes to spare
+            int ppt = 1;
+            if (tab) {
+                a.split = split_lanes((int)nf, n_call ? n_call : N, ctx->num_cu, m.kind == MLMC_GBM);
+                if (a.split == 1 && nf >= 4 && N >= (uint64_t)ctx->num_cu * 512) ppt = 2;
+            }
+            const uint64_t per_chunk = a.split > 1 ? 256 / a.split : 256 * (uint64_t)ppt;
+            const uint64_t chunks = (N + per_chunk - 1) / per_chunk;
+            // the tabulated sampler copies its level's table rows (<= 32 KiB)
+            // into every block's LDS: four blocks per compute unit
+            const uint64_t cap = (uint64_t)ctx->num_cu * (tab ? 4 : 8);
+            const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, cap));
             const int tix = timed_begin(ctx, l < 16 ? l : 15, (double)N * nf, (double)N * nf / M);
-            e = cv_launch_level(cv, m, p, M, a, grid, ctx->stream);
+            e = cv_launch_level(cv, m, p, M, a, grid, ctx->stream, tab, ppt);
             timed_end(ctx, tix);
         }
         if (e != hipSuccess) return hip_fail(ctx, e, "control-variate level launch");

@@ -121,10 +121,13 @@ bool tuned_shape(const mlmc_ctx* ctx, const mlmc_model& m, int payoff, int preci
 int level_class(int l, int M);
 
 // Control variate (cv.hip).
-hipError_t cv_ensure_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st);
+// tab: the tabulated network (estimation launches of a network switched to
+// it); training launches always evaluate the network itself.
+hipError_t cv_ensure_phi0(const mlmc_cv* cv, const mlmc_model& m, hipStream_t st, bool tab);
+bool cv_tabulated(const mlmc_cv* cv);
 hipError_t cv_launch_level(const mlmc_cv* cv, const mlmc_model& m, const mlmc_payoff& p, int M,
-                           const LevelArgs<float>& a, int grid, hipStream_t st);
-const float* cv_phi0_ptr(const mlmc_cv* cv);
+                           const LevelArgs<float>& a, int grid, hipStream_t st, bool tab, int ppt = 1);
+const float* cv_phi0_ptr(const mlmc_cv* cv, bool tab);
 int cv_in_dim(const mlmc_cv* cv);
 
 hipError_t launch_philox_words(uint64_t seed, int level, uint64_t s0, uint32_t stream,

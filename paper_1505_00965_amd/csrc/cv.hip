@@ -29,12 +29,19 @@ struct mlmc_cv {
     float* d_m2 = nullptr;
     bf16x8* d_afwd = nullptr;     // bf16 W2 operands (forward), 8 x 64 entries
     bf16x8* d_abwd = nullptr;     // bf16 W2 operands (backward, permuted)
-    float* d_phi0 = nullptr;      // phi(0, S0), cached: see cv_ensure_phi0
+    float* d_phi0 = nullptr;      // [0] phi(0, S0), [1] its tabulated value: see cv_ensure_phi0
     int adam_t = 0;
     uint64_t version = 0;         // bumped by every parameter change
-    uint64_t phi0_version = ~0ull;
-    mlmc_model phi0_model{};
-    hipStream_t phi0_stream = nullptr;
+    uint64_t phi0_version[2] = {~0ull, ~0ull};
+    mlmc_model phi0_model[2]{};
+    hipStream_t phi0_stream[2] = {nullptr, nullptr};
+    // tabulated network (estimation launches only; training evaluates it)
+    int tabulated = 0;
+    float* d_table = nullptr;
+    size_t table_cap = 0;         // floats allocated
+    uint64_t table_version = ~0ull;
+    mlmc_model table_model{};
+    hipStream_t table_stream = nullptr;
     // training scratch
     float* d_gpart = nullptr;     // per-block gradient partials
     int gpart_blocks = 0;
@@ -116,6 +123,83 @@ struct CvKernelArgs {
     NetConsts nc;
     int D;
 };
+
+// Grid of the tabulated network for a model (host): 256 time rows x 32 stock
+// values for GBM; 16 rows x 16 stock values x 32 variances for Heston (32 KiB
+// of fp32 either way; a level's sampler copies the rows it reads into LDS).
+// Stock values span S0 exp(+-4 sref sqrt T) (sref = sigma, or sqrt(theta) for
+// Heston), variances [0, 4 max(theta, v0)].  The network varies slowly in S
+// at these scales; Heston's variance axis and the time rows of deep levels
+// decide how much of its variance reduction the table keeps.
+struct TableGrid {
+    int rows, ns, nv;
+    double s_lo, s_hi, v_lo, v_hi;
+};
+
+static TableGrid table_grid(const mlmc_model& m)
+{
+    TableGrid g;
+    const bool heston = m.kind == MLMC_HESTON;
+    const double sref = heston ? std::sqrt(m.theta) : m.sigma;
+    const double w = 4.0 * sref * std::sqrt(m.T);
+    g.rows = heston ? 16 : 256;
+    g.ns = heston ? 16 : 32;
+    g.nv = heston ? 32 : 1;
+    g.s_lo = m.S0 * std::exp(-w);
+    g.s_hi = m.S0 * std::exp(w);
+    g.v_lo = 0.0;
+    g.v_hi = heston ? 4.0 * std::max(m.theta, m.v0) : 1.0;
+    return g;
+}
+
+static TableSpec table_spec(const TableGrid& g)
+{
+    TableSpec t;
+    t.rows = g.rows;
+    t.ns = g.ns;
+    t.nv = g.nv;
+    t.s_lo = (float)g.s_lo;
+    t.s_inv = (float)((g.ns - 1) / (g.s_hi - g.s_lo));
+    t.v_lo = (float)g.v_lo;
+    t.v_inv = g.nv > 1 ? (float)((g.nv - 1) / (g.v_hi - g.v_lo)) : 0.0f;
+    return t;
+}
+
+static size_t table_size(const TableGrid& g) { return (size_t)g.rows * g.ns * g.nv; }
+
+// Fill the table: point p = (row j, variance k, stock i), p = (j nv + k) ns + i,
+// holds phi(j T / rows, S_i, v_k) from the network (64 points per wave
+// through phi_eval; every lane of a wave evaluates, lanes past the end drop
+// their value).
+template <int D>
+__global__ void cv_table_kernel(CvKernelArgs c, TableGrid g, float* tab)
+{
+    __shared__ NetShared sh;
+    __shared__ bf16x8 s_afwd[8 * 64];
+    load_shared<D>(sh, c.params, c.nc);
+    for (int i = threadIdx.x; i < 8 * 64; i += blockDim.x) s_afwd[i] = c.afwd[i];
+    __syncthreads();
+    const int npts = g.rows * g.nv * g.ns;
+    const double ds = (g.s_hi - g.s_lo) / (g.ns - 1);
+    const double dv = g.nv > 1 ? (g.v_hi - g.v_lo) / (g.nv - 1) : 0.0;
+    for (int base = blockIdx.x * blockDim.x; base < npts; base += gridDim.x * blockDim.x) {
+        const int p = min(base + (int)threadIdx.x, npts - 1);
+        const int i = p % g.ns, jk = p / g.ns;
+        const int k = jk % g.nv, j = jk / g.nv;
+        const float S = (float)(g.s_lo + i * ds);
+        const float v = (float)(g.v_lo + k * dv);
+        const float x0 = (float)j / (float)g.rows;
+        // a wave may span two time rows: every lane brings its own time
+        const float phi = phi_eval<D, true>(sh, s_afwd, x0, S, v);
+        if (base + (int)threadIdx.x < npts) tab[p] = phi;
+    }
+}
+
+// phi at (0, S0, v0) read from the table (level 0 of the tabulated form).
+__global__ void cv_table_point_kernel(const float* tab, TableSpec t, float S0, float v0, float* out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = table_phi(tab, t, 0, S0, v0);
+}
 
 template <int D>
 __global__ void cv_phi0_kernel(CvKernelArgs c, float S0, float v0, float* out)
@@ -236,6 +320,276 @@ __global__ __launch_bounds__(256, 2) void cv_level_kernel(LevelArgs<float> a, Cv
         const float pc = coupled
                              ? payoff_value<float, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H) - q.cvc
                              : 0.0f;
+        if (idx < a.N) accumulate(a, idx, pf, pc, sums, nonfinite);
+    }
+    block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
+}
+
+// ------------------------------------------------- sampler with the table
+// The rows of the table a level reads, in LDS: lr = min(n_f, rows) rows, LDS
+// row r being table row r rows / lr; step n of the level reads LDS row
+// floor(n lr / n_f), i.e. table row floor(n rows / n_f).
+struct TabView {
+    const float* tab;
+    TableSpec t;
+    int lr, nf;
+};
+
+__device__ __forceinline__ int tab_row(const TabView& v, int n)
+{
+    return (int)(((unsigned)n * (unsigned)v.lr) / (unsigned)v.nf);
+}
+
+// Copy the level's rows into s_tab and describe them.
+__device__ __forceinline__ TabView load_level_table(float* s_tab, const float* table,
+                                                    const TableSpec& t, int nf)
+{
+    const int lr = nf < t.rows ? nf : t.rows;
+    const int rstep = t.rows / lr, rowlen4 = t.ns * t.nv / 4;   // rows hold whole float4s
+    const float4* src = reinterpret_cast<const float4*>(table);
+    float4* dst = reinterpret_cast<float4*>(s_tab);
+    // unrolled so that a thread's loads are in flight together (one L2
+    // round trip for the whole copy, not one per element)
+#pragma unroll 8
+    for (int i = threadIdx.x; i < lr * rowlen4; i += blockDim.x) {
+        const int r = i / rowlen4, c = i - r * rowlen4;
+        dst[i] = src[r * rstep * rowlen4 + c];
+    }
+    __syncthreads();
+    return TabView{s_tab, t, lr, nf};
+}
+
+// Generator block g (four fine steps) of a coupled pair with the tabulated
+// control variate: the steps as in advance_group, then phi at the left point
+// of each of the four fine steps and of each coarse step the block opens,
+// read in one go (the lookups wait on LDS once per block, not once per step)
+// and added to the pair's sums in step order.
+template <int MODEL, int PAYOFF, int M>
+__device__ __forceinline__ void advance_group_tab(const StepParams<float>& P, const PathKey& key,
+                                                  const PathKey& bkey, uint32_t g, PathPair<float>& q,
+                                                  const TabView& tv)
+{
+    float dw1[4], dwp[4], e[4];
+    if (one_factor(MODEL)) {
+        const u32x4 w = path_block(key, g);
+        brownian_pair(w.x, w.y, P, dw1[0], dw1[1]);
+        brownian_pair(w.z, w.w, P, dw1[2], dw1[3]);
+        dwp[0] = dwp[1] = dwp[2] = dwp[3] = 0.0f;
+    } else {
+        const u32x4 wa = path_block(key, 2 * g);
+        const u32x4 wb = path_block(key, 2 * g + 1);
+        brownian_pair(wa.x, wa.y, P, dw1[0], dwp[0]);
+        brownian_pair(wa.z, wa.w, P, dw1[1], dwp[1]);
+        brownian_pair(wb.x, wb.y, P, dw1[2], dwp[2]);
+        brownian_pair(wb.z, wb.w, P, dw1[3], dwp[3]);
+    }
+    if (PAYOFF == kLookback) {
+        const u32x4 u = path_block(bkey, g);
+        e[0] = P.lnu_scale * flog2<float>(u01f(u.x));
+        e[1] = P.lnu_scale * flog2<float>(u01f(u.y));
+        e[2] = P.lnu_scale * flog2<float>(u01f(u.z));
+        e[3] = P.lnu_scale * flog2<float>(u01f(u.w));
+    } else {
+        e[0] = e[1] = e[2] = e[3] = 0.0f;
+    }
+    constexpr int NC = 4 / M;
+    float sf[4], vf[4], sc[NC], vc[NC], wc[NC];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sf[k] = q.S;
+        vf[k] = q.v;
+        if (k % M == 0) {
+            sc[k / M] = q.Sc;
+            vc[k / M] = q.vc;
+        }
+        fine_step<float, MODEL, PAYOFF>(q, P, dw1[k], dwp[k], e[k], k % M, true);
+        if ((k + 1) % M == 0) {
+            wc[k / M] = q.dw1c;
+            coarse_step<float, MODEL, PAYOFF>(q, P);
+        }
+    }
+    const int n0 = 4 * (int)g;
+    float pf[4], pcs[NC];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pf[k] = table_phi(tv.tab, tv.t, tab_row(tv, n0 + k), sf[k], vf[k]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) pcs[c] = table_phi(tv.tab, tv.t, tab_row(tv, n0 + c * M), sc[c], vc[c]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q.cvf = __builtin_fmaf(pf[k], dw1[k], q.cvf);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q.cvc = __builtin_fmaf(pcs[c], wc[c], q.cvc);
+}
+
+// Levels with n_f >= 4: PPT samples per lane, blocks walk the chunks.
+template <int MODEL, int PAYOFF, int M, int PPT>
+__global__ __launch_bounds__(256) void cv_tab_level_kernel(LevelArgs<float> a, const float* table,
+                                                           TableSpec t)
+{
+    extern __shared__ __attribute__((aligned(16))) float s_tab[];
+    const TabView tv = load_level_table(s_tab, table, t, a.nf);
+    const StepParams<float>& P = a.P;
+    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+    unsigned nonfinite = 0;
+    const uint64_t chunk = (uint64_t)blockDim.x * PPT;
+    const uint64_t nchunks = (a.N + chunk - 1) / chunk;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        uint64_t idx[PPT];
+        PathKey key[PPT], bkey[PPT];
+        PathPair<float> q[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            idx[p] = ch * chunk + (uint64_t)p * blockDim.x + threadIdx.x;
+            const uint32_t s = (uint32_t)(a.offset + idx[p]);
+            key[p] = PathKey{k0, k1, s, a.c2, a.stream};
+            bkey[p] = PathKey{k0, k1, s, a.c2b, a.stream + 1u};
+            init_pair<float, MODEL, PAYOFF>(q[p], P);
+        }
+        for (uint32_t g = 0; g < a.ngroups; ++g) {
+#pragma unroll
+            for (int p = 0; p < PPT; ++p)
+                advance_group_tab<MODEL, PAYOFF, M>(P, key[p], bkey[p], g, q[p], tv);
+        }
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const float pf = payoff_value<float, PAYOFF>(P, q[p].S, q[p].asum, q[p].acomp, q[p].mn, P.h) -
+                             q[p].cvf;
+            const float pc =
+                payoff_value<float, PAYOFF>(P, q[p].Sc, q[p].csum, q[p].ccomp, q[p].mnc, P.H) - q[p].cvc;
+            if (idx[p] < a.N) accumulate(a, idx[p], pf, pc, sums, nonfinite);
+        }
+    }
+    block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
+}
+
+// GBM levels whose paths are too few to fill the device: G = a.split lanes
+// per path.  Pass 1 is process_split's: every lane runs its segment of n_f/G
+// fine steps from a unit start and the segment summaries (product, sum of S,
+// bridge minimum; fine and coarse) are composed, here by an inclusive scan in
+// path order, so lane j also learns the product of the segments before it,
+// i.e. its segment's true start.  Pass 2: each lane runs its segment again
+// from that start (the same generator blocks) for the control-variate terms;
+// their sums over the path's lanes complete the two control-variate sums,
+// and the last lane forms the payoffs.
+template <int PAYOFF, int M>
+__device__ __forceinline__ void process_split_tab(const LevelArgs<float>& a, uint64_t base,
+                                                  const TabView& tv, double (&sums)[kNumSums],
+                                                  unsigned& nonfinite)
+{
+    const int G = (int)a.split;
+    const int seg = (int)threadIdx.x & (G - 1);
+    const uint64_t idx = base + threadIdx.x / (uint32_t)G;
+    const uint64_t s = a.offset + idx;
+    const StepParams<float>& P = a.P;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const PathKey key{k0, k1, (uint32_t)s, a.c2, a.stream};
+    const PathKey bkey{k0, k1, (uint32_t)s, a.c2b, a.stream + 1u};
+    PathPair<float> q, qa;
+    init_pair<float, kGBM, PAYOFF>(q, P);
+    q.S = 1.0f;
+    q.Sc = 1.0f;
+    const uint32_t per = a.ngroups / (uint32_t)G;
+    const uint32_t g0 = (uint32_t)seg * per;
+    for (uint32_t g = g0; g < g0 + per; ++g)
+        advance_group<kGBM, PAYOFF, float, M, false>(P, key, bkey, g, q, qa);
+    double pf = q.S, sf = (double)q.asum - (double)q.acomp, mf = q.mn;
+    double pc = q.Sc, sc = (double)q.csum - (double)q.ccomp, mc = q.mnc;
+    // inclusive scan: lane j holds the composition of segments 0..j
+    for (int off = 1; off < G; off <<= 1) {
+        const double pf2 = __shfl_up(pf, off, G), pc2 = __shfl_up(pc, off, G);
+        double sf2 = 0, sc2 = 0, mf2 = 0, mc2 = 0;
+        if (PAYOFF == kAsian) {
+            sf2 = __shfl_up(sf, off, G);
+            sc2 = __shfl_up(sc, off, G);
+        }
+        if (PAYOFF == kLookback) {
+            mf2 = __shfl_up(mf, off, G);
+            mc2 = __shfl_up(mc, off, G);
+        }
+        if (seg >= off) {      // (earlier segments) o (this one)
+            if (PAYOFF == kAsian) {
+                sf = __builtin_fma(pf2, sf, sf2);
+                sc = __builtin_fma(pc2, sc, sc2);
+            }
+            if (PAYOFF == kLookback) {
+                const double a1 = pf2 * mf, a2 = pc2 * mc;
+                mf = a1 < mf2 ? a1 : mf2;
+                mc = a2 < mc2 ? a2 : mc2;
+            }
+            pf *= pf2;
+            pc *= pc2;
+        }
+    }
+    // start of this lane's segment: the product of the segments before it
+    const double before_f = __shfl_up(pf, 1, G), before_c = __shfl_up(pc, 1, G);
+    const double S0 = (double)P.S0;
+    PathPair<float> r;
+    init_pair<float, kGBM, kCall>(r, P);
+    r.S = (float)(S0 * (seg ? before_f : 1.0));
+    r.Sc = (float)(S0 * (seg ? before_c : 1.0));
+    for (uint32_t g = g0; g < g0 + per; ++g) advance_group_tab<kGBM, kCall, M>(P, key, bkey, g, r, tv);
+    double cf = r.cvf, cc = r.cvc;
+    for (int off = 1; off < G; off <<= 1) {
+        cf += __shfl_xor(cf, off, G);
+        cc += __shfl_xor(cc, off, G);
+    }
+    if (seg != G - 1) return;
+    const float vf = payoff_value<float, PAYOFF>(P, (float)(S0 * pf), (float)(S0 * sf), 0.0f,
+                                                 (float)(S0 * mf), P.h) - (float)cf;
+    const float vc = payoff_value<float, PAYOFF>(P, (float)(S0 * pc), (float)(S0 * sc), 0.0f,
+                                                 (float)(S0 * mc), P.H) - (float)cc;
+    if (idx < a.N) accumulate(a, idx, vf, vc, sums, nonfinite);
+}
+
+template <int PAYOFF, int M>
+__global__ __launch_bounds__(256) void cv_tab_split_kernel(LevelArgs<float> a, const float* table,
+                                                           TableSpec t)
+{
+    extern __shared__ __attribute__((aligned(16))) float s_tab[];
+    const TabView tv = load_level_table(s_tab, table, t, a.nf);
+    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+    unsigned nonfinite = 0;
+    const uint64_t per_block = blockDim.x / a.split;
+    const uint64_t nchunks = (a.N + per_block - 1) / per_block;
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+        process_split_tab<PAYOFF, M>(a, c * per_block, tv, sums, nonfinite);
+    block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
+}
+
+// Levels with n_f < 4 (level 1 at M = 2): samples share generator blocks
+// (fetch_group); one sample per lane, the level's table rows in LDS.
+template <int MODEL, int PAYOFF, int M>
+__global__ __launch_bounds__(256) void cv_tab_short_kernel(LevelArgs<float> a, const float* table,
+                                                           TableSpec t)
+{
+    extern __shared__ __attribute__((aligned(16))) float s_tab[];
+    const TabView tv = load_level_table(s_tab, table, t, a.nf);
+    const StepParams<float>& P = a.P;
+    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+    unsigned nonfinite = 0;
+    const uint64_t nchunks = (a.N + blockDim.x - 1) / blockDim.x;
+    for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const uint64_t idx = ch * blockDim.x + threadIdx.x;
+        const uint64_t s = a.offset + idx;
+        PathPair<float> q;
+        init_pair<float, MODEL, PAYOFF>(q, P);
+        float phic = 0.0f;
+        float dw1[4], dwp[4], e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        fetch_group<MODEL, PAYOFF>(a, s, 0, dw1, dwp, e);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            if (n >= a.nf) break;
+            const int row = tab_row(tv, n);
+            q.cvf = __builtin_fmaf(table_phi(tv.tab, tv.t, row, q.S, q.v), dw1[n], q.cvf);
+            if ((n & (M - 1)) == 0) phic = table_phi(tv.tab, tv.t, row, q.Sc, q.vc);
+            fine_step<float, MODEL, PAYOFF>(q, P, dw1[n], dwp[n], e[n], n & (M - 1), true);
+            if (((n + 1) & (M - 1)) == 0) {
+                q.cvc = __builtin_fmaf(phic, q.dw1c, q.cvc);
+                coarse_step<float, MODEL, PAYOFF>(q, P);
+            }
+        }
+        const float pf = payoff_value<float, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h) - q.cvf;
+        const float pc = payoff_value<float, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H) - q.cvc;
         if (idx < a.N) accumulate(a, idx, pf, pc, sums, nonfinite);
     }
     block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
@@ -429,6 +783,31 @@ static CvFn pick_cv_payoff(int payoff, int M)
     }
 }
 
+using CvTabFn = void (*)(LevelArgs<float>, const float*, TableSpec);
+
+// Tabulated sampler for one payoff: the short-level kernel (n_f < 4), the
+// split kernel (GBM, split > 1) or the per-lane kernel with ppt samples.
+template <int MODEL, int PAYOFF, int M>
+static CvTabFn pick_tab_m(int nf, int split, int ppt)
+{
+    if (nf < 4) return cv_tab_short_kernel<MODEL, PAYOFF, M>;
+    if constexpr (MODEL == kGBM)
+        if (split > 1) return cv_tab_split_kernel<PAYOFF, M>;
+    return ppt == 2 ? cv_tab_level_kernel<MODEL, PAYOFF, M, 2> : cv_tab_level_kernel<MODEL, PAYOFF, M, 1>;
+}
+
+template <int MODEL>
+static CvTabFn pick_tab_payoff(int payoff, int M, int nf, int split, int ppt)
+{
+    switch (payoff) {
+    case kCall: return M == 2 ? pick_tab_m<MODEL, kCall, 2>(nf, split, ppt) : pick_tab_m<MODEL, kCall, 4>(nf, split, ppt);
+    case kAsian: return M == 2 ? pick_tab_m<MODEL, kAsian, 2>(nf, split, ppt) : pick_tab_m<MODEL, kAsian, 4>(nf, split, ppt);
+    case kLookback:
+        return M == 2 ? pick_tab_m<MODEL, kLookback, 2>(nf, split, ppt) : pick_tab_m<MODEL, kLookback, 4>(nf, split, ppt);
+    default: return M == 2 ? pick_tab_m<MODEL, kDigital, 2>(nf, split, ppt) : pick_tab_m<MODEL, kDigital, 4>(nf, split, ppt);
+    }
+}
+
 NetConsts net_consts(const mlmc_model& m)
 {
     NetConsts c;
@@ -450,34 +829,94 @@ static bool same_model(const mlmc_model& a, const mlmc_model& b)
            a.kappa == b.kappa && a.theta == b.theta && a.xi == b.xi && a.rho == b.rho && a.v0 == b.v0;
 }
 
-// phi(0, S0) for level 0 in cv->d_phi0.  The value depends only on the
-// parameters and the model, so it is computed once per parameter change,
-// model and stream (a launch on another stream would not be ordered after
-// the write) and level-0 launches reuse it.
-hipError_t cv_ensure_phi0(const mlmc_cv* ccv, const mlmc_model& m, hipStream_t st)
+// The table of the current parameters for model m in cv->d_table, rebuilt
+// when the parameters, the model or the stream changed (the same caching rule
+// as phi(0, S0)).
+static hipError_t cv_ensure_table(mlmc_cv* cv, const mlmc_model& m, hipStream_t st)
 {
-    mlmc_cv* cv = const_cast<mlmc_cv*>(ccv);
-    if (cv->phi0_version == cv->version && cv->phi0_stream == st && same_model(cv->phi0_model, m))
+    if (cv->table_version == cv->version && cv->table_stream == st && same_model(cv->table_model, m))
         return hipSuccess;
+    const TableGrid g = table_grid(m);
+    const size_t n = table_size(g);
+    if (cv->table_cap < n) {
+        // the previous table may still be read by queued launches
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (cv->d_table) hipFree(cv->d_table);
+        cv->d_table = nullptr;
+        cv->table_cap = 0;
+        e = hipMalloc(&cv->d_table, sizeof(float) * n);
+        if (e != hipSuccess) return e;
+        cv->table_cap = n;
+    }
     CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
+    const int blocks = (int)((n + 255) / 256);
     if (cv->D == 2)
-        hipLaunchKernelGGL(cv_phi0_kernel<2>, dim3(1), dim3(64), 0, st, c, (float)m.S0,
-                           (float)m.v0, cv->d_phi0);
+        hipLaunchKernelGGL(cv_table_kernel<2>, dim3(blocks), dim3(256), 0, st, c, g, cv->d_table);
     else
-        hipLaunchKernelGGL(cv_phi0_kernel<3>, dim3(1), dim3(64), 0, st, c, (float)m.S0,
-                           (float)m.v0, cv->d_phi0);
+        hipLaunchKernelGGL(cv_table_kernel<3>, dim3(blocks), dim3(256), 0, st, c, g, cv->d_table);
     const hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-        cv->phi0_version = cv->version;
-        cv->phi0_stream = st;
-        cv->phi0_model = m;
+        cv->table_version = cv->version;
+        cv->table_stream = st;
+        cv->table_model = m;
     }
     return e;
 }
 
-hipError_t cv_launch_level(const mlmc_cv* cv, const mlmc_model& m, const mlmc_payoff& p, int M,
-                           const LevelArgs<float>& a, int grid, hipStream_t st)
+// phi(0, S0) for level 0 in cv->d_phi0[0] (from the network) or, for the
+// tabulated form, cv->d_phi0[1] (from the table).  The value depends only on
+// the parameters and the model, so it is computed once per parameter change,
+// model and stream (a launch on another stream would not be ordered after
+// the write) and level-0 launches reuse it.
+hipError_t cv_ensure_phi0(const mlmc_cv* ccv, const mlmc_model& m, hipStream_t st, bool tab)
 {
+    mlmc_cv* cv = const_cast<mlmc_cv*>(ccv);
+    const int w = tab ? 1 : 0;
+    if (cv->phi0_version[w] == cv->version && cv->phi0_stream[w] == st &&
+        same_model(cv->phi0_model[w], m))
+        return hipSuccess;
+    if (tab) {
+        hipError_t e = cv_ensure_table(cv, m, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(cv_table_point_kernel, dim3(1), dim3(64), 0, st, (const float*)cv->d_table,
+                           table_spec(table_grid(m)), (float)m.S0, (float)m.v0, cv->d_phi0 + 1);
+    } else {
+        CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
+        if (cv->D == 2)
+            hipLaunchKernelGGL(cv_phi0_kernel<2>, dim3(1), dim3(64), 0, st, c, (float)m.S0,
+                               (float)m.v0, cv->d_phi0);
+        else
+            hipLaunchKernelGGL(cv_phi0_kernel<3>, dim3(1), dim3(64), 0, st, c, (float)m.S0,
+                               (float)m.v0, cv->d_phi0);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        cv->phi0_version[w] = cv->version;
+        cv->phi0_stream[w] = st;
+        cv->phi0_model[w] = m;
+    }
+    return e;
+}
+
+bool cv_tabulated(const mlmc_cv* cv) { return cv->tabulated != 0; }
+
+hipError_t cv_launch_level(const mlmc_cv* ccv, const mlmc_model& m, const mlmc_payoff& p, int M,
+                           const LevelArgs<float>& a, int grid, hipStream_t st, bool tab, int ppt)
+{
+    mlmc_cv* cv = const_cast<mlmc_cv*>(ccv);
+    if (tab) {
+        hipError_t e = cv_ensure_table(cv, m, st);
+        if (e != hipSuccess) return e;
+        const TableGrid g = table_grid(m);
+        const int lr = a.nf < g.rows ? a.nf : g.rows;    // rows the level reads
+        const size_t lds = sizeof(float) * (size_t)lr * g.ns * g.nv;
+        CvTabFn fn = m.kind == MLMC_GBM ? pick_tab_payoff<kGBM>(p.kind, M, a.nf, (int)a.split, ppt)
+                                        : pick_tab_payoff<kHeston>(p.kind, M, a.nf, 1, ppt);
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(256), lds, st, a, (const float*)cv->d_table,
+                           table_spec(g));
+        return hipGetLastError();
+    }
     CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
     CvFn fn = m.kind == MLMC_GBM ? pick_cv_payoff<kGBM>(p.kind, M) : pick_cv_payoff<kHeston>(p.kind, M);
     hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, st, a, c);
@@ -582,7 +1021,7 @@ static mlmc_status check_train_args(mlmc_cv* cv, const mlmc_model* m, const mlmc
     return MLMC_OK;
 }
 
-const float* cv_phi0_ptr(const mlmc_cv* cv) { return cv->d_phi0; }
+const float* cv_phi0_ptr(const mlmc_cv* cv, bool tab) { return cv->d_phi0 + (tab ? 1 : 0); }
 int cv_in_dim(const mlmc_cv* cv) { return cv->D; }
 
 static hipError_t cv_prepare(mlmc_cv* cv, hipStream_t st)
@@ -597,6 +1036,10 @@ static hipError_t cv_prepare(mlmc_cv* cv, hipStream_t st)
 
 using namespace mlmc;
 
+namespace {
+const mlmc_payoff kAnyPayoff{MLMC_CALL, 100.0, 1.0};
+}
+
 extern "C" {
 
 mlmc_status mlmc_cv_destroy(mlmc_cv* cv)
@@ -605,7 +1048,7 @@ mlmc_status mlmc_cv_destroy(mlmc_cv* cv)
     if (cv->ctx) hipSetDevice(cv->ctx->device);
     for (void* p : {(void*)cv->d_params, (void*)cv->d_m1, (void*)cv->d_m2, (void*)cv->d_afwd,
                     (void*)cv->d_abwd, (void*)cv->d_phi0, (void*)cv->d_gpart, (void*)cv->d_y,
-                    (void*)cv->d_w, (void*)cv->d_loss})
+                    (void*)cv->d_w, (void*)cv->d_loss, (void*)cv->d_table})
         if (p) hipFree(p);
     delete cv;
     return MLMC_OK;
@@ -676,6 +1119,39 @@ mlmc_status mlmc_cv_set_params(mlmc_cv* cv, const float* host, size_t n)
 }
 
 size_t mlmc_cv_nparams(const mlmc_cv* cv) { return cv ? (size_t)cv->np : 0; }
+
+mlmc_status mlmc_cv_set_tabulated(mlmc_cv* cv, int on)
+{
+    if (!cv) return MLMC_EINVAL;
+    if (on != 0 && on != 1) return fail(cv->ctx, MLMC_EINVAL, "on must be 0 or 1");
+    cv->tabulated = on;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_cv_get_table(mlmc_cv* cv, const mlmc_model* model, float* host, size_t n,
+                              int* dims)
+{
+    if (!cv) return MLMC_EINVAL;
+    mlmc_ctx* ctx = cv->ctx;
+    mlmc_status st = check_level_args(ctx, model, &kAnyPayoff, 0, 2, 32);
+    if (st) return st;
+    if (cv->D != (model->kind == MLMC_HESTON ? 3 : 2))
+        return fail(ctx, MLMC_EINVAL, "network inputs do not match the model (2: GBM, 3: Heston)");
+    const TableGrid g = table_grid(*model);
+    if (dims) {
+        dims[0] = g.rows;
+        dims[1] = g.nv;
+        dims[2] = g.ns;
+    }
+    if (!host) return MLMC_OK;
+    if (n != table_size(g)) return fail(ctx, MLMC_EINVAL, "need a host array of rows * nv * ns floats");
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    MLMC_HIP(ctx, cv_ensure_table(cv, *model, ctx->stream));
+    MLMC_HIP(ctx, hipMemcpyAsync(host, cv->d_table, sizeof(float) * n, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return MLMC_OK;
+}
 
 mlmc_status mlmc_cv_loss_grad(mlmc_cv* cv, const mlmc_model* model, const mlmc_payoff* payoff,
                               int M, int lmax, uint64_t batch, uint64_t seed, uint64_t step,

@@ -112,9 +112,12 @@ __device__ __forceinline__ float input_x1(const NetShared& sh, float S)
 
 // Layer-1 activations of the lane's two samples, packed as B operands.
 // h1f (optional, 64 floats) receives the fp32 values: h1f[nt * 32 + s].
-template <int D, bool KEEP>
+// x0 is the time input of both samples (wave-uniform in the samplers); with
+// X0LANE the two samples have their own, x0p[nt].
+template <int D, bool KEEP, bool X0LANE = false>
 __device__ __forceinline__ void layer1(const NetShared& sh, float x0, const float (&x1)[2],
-                                       const float (&x2)[2], bf16x8 (&b)[2][4], float* h1f)
+                                       const float (&x2)[2], bf16x8 (&b)[2][4], float* h1f,
+                                       const float* x0p = nullptr)
 {
     const int h = (threadIdx.x & 63) >> 5;
 #pragma unroll
@@ -123,7 +126,8 @@ __device__ __forceinline__ void layer1(const NetShared& sh, float x0, const floa
         const float c = __builtin_fmaf(sh.w1[u][0], x0, sh.w1[u][3]);
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-            float a = __builtin_fmaf(sh.w1[u][1], x1[nt], c);
+            const float cn = X0LANE ? __builtin_fmaf(sh.w1[u][0], x0p[nt], sh.w1[u][3]) : c;
+            float a = __builtin_fmaf(sh.w1[u][1], x1[nt], cn);
             if (D == 3) a = __builtin_fmaf(sh.w1[u][2], x2[nt], a);
             const float v = tanh_fast(a);
             if (KEEP) h1f[nt * 32 + s] = v;
@@ -175,7 +179,7 @@ __device__ __forceinline__ void pair_inputs(const NetShared& sh, float S, float 
 // afwd: the bf16 W2 operands in lane order (in LDS in the sampler).  Layer 2
 // and layer 3 run one 32-row tile at a time, so only half of the matrix
 // accumulators are live.
-template <int D>
+template <int D, bool X0LANE = false>
 __device__ __forceinline__ float phi_eval(const NetShared& sh, const bf16x8* afwd, float x0,
                                           float S, float v)
 {
@@ -189,7 +193,14 @@ __device__ __forceinline__ float phi_eval(const NetShared& sh, const bf16x8* afw
     float x1[2], x2[2];
     pair_inputs<D>(sh, S, v, x1, x2);
     bf16x8 b[2][4];
-    layer1<D, false>(sh, x0, x1, x2, b, nullptr);
+    float x0p[2] = {x0, x0};
+    if (X0LANE) {
+        // this lane's sample and lane l ^ 32's, in B-column order
+        const float oth = __shfl_xor(x0, 32);
+        x0p[0] = h == 0 ? x0 : oth;
+        x0p[1] = h == 0 ? oth : x0;
+    }
+    layer1<D, false, X0LANE>(sh, x0, x1, x2, b, nullptr, x0p);
     float part[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) {
@@ -213,6 +224,48 @@ __device__ __forceinline__ float phi_eval(const NetShared& sh, const bf16x8* afw
     const float recv = __shfl_xor(send, 32);
     const float mine = h == 0 ? part[0] : part[1];
     return sh.scale * (mine + recv + sh.b3);
+}
+
+// ------------------------------------------------------------ tabulated
+// The sampler may read phi from a table instead of evaluating the network at
+// every point: phi on a grid of `rows` times t_j = j T / rows, ns stock values
+// S_i = s_lo + i dS (and nv variances v_k = v_lo + k dv for Heston), filled by
+// the network itself (cv_table_kernel), and interpolated linearly in S (and v)
+// within the row of the last grid time at or before the evaluation time.  Any
+// function of (t_n, X_n) keeps the control variate's mean at zero, so the
+// table changes only how much variance it removes, not the level means.
+struct TableSpec {
+    int rows, ns, nv;
+    float s_lo, s_inv;    // u = (S - s_lo) s_inv, grid index in S
+    float v_lo, v_inv;    // w = (v - v_lo) v_inv (nv > 1)
+};
+
+// Row of step n of a path with nf fine steps: floor(n rows / nf).
+__device__ __forceinline__ int table_row(int n, int nf, int rows)
+{
+    return (int)(((unsigned)n * (unsigned)rows) / (unsigned)nf);
+}
+
+// Linear (bilinear for nv > 1) interpolation in one row; points outside the
+// grid take the nearest edge of it (a non-finite S or v reads the low edge:
+// fmin/fmax return the other operand of a NaN, so the index stays in range).
+__device__ __forceinline__ float table_phi(const float* tab, const TableSpec& t, int row, float S,
+                                           float v)
+{
+    const float u = __builtin_fminf(__builtin_fmaxf((S - t.s_lo) * t.s_inv, 0.0f), (float)(t.ns - 1));
+    const int i = min((int)u, t.ns - 2);
+    const float f = u - (float)i;
+    if (t.nv == 1) {
+        const float* r = tab + row * t.ns + i;
+        return __builtin_fmaf(f, r[1] - r[0], r[0]);
+    }
+    const float w = __builtin_fminf(__builtin_fmaxf((v - t.v_lo) * t.v_inv, 0.0f), (float)(t.nv - 1));
+    const int k = min((int)w, t.nv - 2);
+    const float g = w - (float)k;
+    const float* r = tab + (row * t.nv + k) * t.ns + i;
+    const float a = __builtin_fmaf(f, r[1] - r[0], r[0]);
+    const float b = __builtin_fmaf(f, r[t.ns + 1] - r[t.ns], r[t.ns]);
+    return __builtin_fmaf(g, b - a, a);
 }
 
 // ------------------------------------------------------------- backward

@@ -26,6 +26,7 @@ EXPORTED = [
     "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train", "mlmc_autotune",
     "mlmc_autotune_persistent",
     "mlmc_tuned_shape", "mlmc_rhee_glynn", "mlmc_set_timing_mask", "mlmc_level_noalloc",
+    "mlmc_cv_set_tabulated", "mlmc_cv_get_table",
 ]
 STAT_SLOTS = 20
 STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
@@ -145,6 +146,8 @@ def lib():
     L.mlmc_cv_loss_grad.argtypes = [vp, M_, P_, i32, i32, u64, u64, u64, C.POINTER(C.c_float),
                                     C.POINTER(d), C.POINTER(d)]
     L.mlmc_cv_train.argtypes = [vp, M_, P_, i32, i32, i32, u64, d, u64, C.POINTER(C.c_float)]
+    L.mlmc_cv_set_tabulated.argtypes = [vp, i32]
+    L.mlmc_cv_get_table.argtypes = [vp, M_, C.POINTER(C.c_float), C.c_size_t, C.POINTER(i32)]
     L.mlmc_autotune.argtypes = [vp, M_, P_, i32, i32, C.c_char_p]
     L.mlmc_autotune_persistent.argtypes = [vp, M_, P_, i32, i32, i32, C.c_char_p,
                                            C.POINTER(C.c_int)]
@@ -419,6 +422,21 @@ class ControlVariate:
             self.h, C.byref(m), C.byref(p), M, lmax, steps, batch, lr, seed,
             hist.ctypes.data_as(C.POINTER(C.c_float))))
         return hist[:steps]
+
+    def set_tabulated(self, on=True):
+        """Estimation samplers read phi from its table (True) or evaluate the
+        network (False)."""
+        self.ctx._check(self._lib.mlmc_cv_set_tabulated(self.h, int(bool(on))))
+
+    def get_table(self, m):
+        """The table of the tabulated form for model m: array [R, nv, ns]."""
+        import numpy as np
+        dims = (C.c_int * 3)()
+        self.ctx._check(self._lib.mlmc_cv_get_table(self.h, C.byref(m), None, 0, dims))
+        out = np.zeros(dims[0] * dims[1] * dims[2], dtype=np.float32)
+        self.ctx._check(self._lib.mlmc_cv_get_table(
+            self.h, C.byref(m), out.ctypes.data_as(C.POINTER(C.c_float)), out.size, dims))
+        return out.reshape(dims[0], dims[1], dims[2])
 
     def set_params(self, values):
         import numpy as np

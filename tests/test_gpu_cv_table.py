@@ -1,0 +1,124 @@
+"""Tabulated control variate on the GPU vs the oracle.
+
+The table is the network on a (time, S[, v]) grid; the GPU fills it with
+its bf16 matrix-core network, the oracle fills its own with the network in
+bf16-emulation mode, and both samplers interpolate their table in the row of
+the last grid time at or before each left point.  Table entries: a layer-1
+activation that rounds to another bf16 neighbour (see test_gpu_cv.py) moves
+an entry by ~1e-3 relative; the bar is |d phi| <= 1e-3 S0 for every entry
+and <= 1e-4 S0 for all but 1% of them.  Per path: |dP| <= 1e-4 S0 except
+for paths that cross a cell with such an entry (budget: 1.5% of the samples,
+and |dP| <= 1e-3 S0 for all).  The control-variate sums keep mean zero, and
+after training the table removes about as much variance as the network.
+"""
+import numpy as np
+import pytest
+
+from paper_1505_00965_amd import mlmc, workloads as W
+
+pytestmark = pytest.mark.gpu
+S0 = 100.0
+
+
+def random_net(orc, in_dim, seed=3, scale=2.0):
+    p = orc.cv_init(in_dim, 64, seed) * scale
+    rng = np.random.default_rng(seed)
+    p = p + 0.1 * rng.standard_normal(p.size) * (p == 0)
+    return p.astype(np.float32)
+
+
+def gpu_paths(gctx, m, p, l, M, N, seed, cv, offset=0):
+    import torch
+    pf = torch.empty(N, dtype=torch.float64, device="cuda")
+    pc = torch.empty(N, dtype=torch.float64, device="cuda")
+    gctx.mlmc_level_paths(m, p, l, M, N, seed, pf, pc, path_offset=offset, cv=cv)
+    return pf.cpu().numpy(), pc.cpu().numpy()
+
+
+def setup(gctx, orc, kind, seed=3):
+    md = W.GBM_MODEL if kind == 0 else W.HESTON_MODEL
+    gm, om = mlmc.model(**md), orc.model(**md)
+    d = 3 if kind else 2
+    params = random_net(orc, d, seed=seed)
+    cv = mlmc.ControlVariate(gctx, d)
+    cv.set_params(params)
+    cv.set_tabulated(True)
+    emu = orc.CVNet(params.astype(np.float64), d, 64, bf16_emulate=True)
+    g = orc.cv_table_grid(om)
+    otab = orc.cv_table_fill(om, emu, g)
+    ocv = orc.CVNet(params.astype(np.float64), d, 64, bf16_emulate=True, table=otab, grid=g)
+    return gm, om, cv, g, otab, ocv
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_table_entries_match_oracle(gctx, orc, kind):
+    gm, om, cv, g, otab, _ = setup(gctx, orc, kind)
+    gt = cv.get_table(gm).astype(np.float64)
+    assert gt.shape == otab.shape == (g.rows, g.nv, g.ns)
+    d = np.abs(gt - otab)
+    beyond = int((d > 1e-4 * S0).sum())
+    print(f"TABLE kind={kind} entries={d.size} beyond={beyond} max={d.max():.3e} "
+          f"median={np.median(d):.2e}", flush=True)
+    assert d.max() <= 1e-3 * S0 and beyond <= 0.005 * d.size
+    cv.close()
+
+
+@pytest.mark.parametrize("kind,pname,M", [(0, "asian", 4), (0, "call", 4), (0, "lookback", 2),
+                                          (1, "call", 4)])
+def test_tabulated_paths_match_oracle(gctx, orc, kind, pname, M):
+    gm, om, cv, g, otab, ocv = setup(gctx, orc, kind)
+    gp, op = mlmc.payoff(**W.PAYOFFS[pname]), orc.payoff(**W.PAYOFFS[pname])
+    N = 4096
+    for l in (0, 1, 2, 3, 5):
+        if M == 4 and l == 5:
+            continue
+        for off in (0, 5):
+            print(f"case kind={kind} payoff={pname} M={M} l={l} off={off}", flush=True)
+            pf, pc = gpu_paths(gctx, gm, gp, l, M, N, 11, cv, offset=off)
+            rf, rc = orc.level_paths(om, op, l, M, N, 11, off, cv=ocv, nthreads=8)
+            dd = np.maximum(np.abs(pf - rf), np.abs(pc - rc))
+            beyond = int((dd > 1e-4 * S0).sum())
+            print(f"CVTABFLIPS kind={kind} payoff={pname} M={M} l={l} off={off} N={N} "
+                  f"beyond={beyond} max={dd.max():.3e}", flush=True)
+            assert dd.max() <= 1e-3 * S0 and beyond <= int(np.ceil(0.005 * N)), (l, off)
+    cv.close()
+
+
+def test_tabulated_control_variate_keeps_the_mean(gctx, orc):
+    gm, om, cv, g, otab, ocv = setup(gctx, orc, 0, seed=9)
+    gp = mlmc.payoff(**W.ASIAN)
+    N = 200000
+    for l in (0, 2, 3):
+        pf0, pc0 = gpu_paths(gctx, gm, gp, l, 4, N, 4, None)
+        pf1, pc1 = gpu_paths(gctx, gm, gp, l, 4, N, 4, cv)
+        for dlt in (pf0 - pf1, pc0 - pc1):     # the control-variate sums themselves
+            if np.all(dlt == 0):
+                continue
+            assert abs(dlt.mean()) < 4.5 * dlt.std() / np.sqrt(N), (l, dlt.mean(), dlt.std())
+    cv.close()
+
+
+@pytest.mark.parametrize("kind,pname", [(0, "asian"), (1, "call")])
+def test_trained_table_removes_the_networks_variance(gctx, kind, pname):
+    """What the table costs in variance reduction: level variances with the
+    trained network itself and with its table, on the same samples."""
+    md = W.GBM_MODEL if kind == 0 else W.HESTON_MODEL
+    gm, gp = mlmc.model(**md), mlmc.payoff(**W.PAYOFFS[pname])
+    cv = mlmc.ControlVariate(gctx, 3 if kind else 2, init_seed=1)
+    cv.train(gm, gp, M=4, lmax=3, steps=300, batch=8192, lr=3e-3, seed=2)
+    ratios = []
+    for l in range(4):
+        out = []
+        for tab in (False, True):
+            cv.set_tabulated(tab)
+            r = gctx.mlmc_level(gm, gp, l, 4, 1 << 17, 77, cv=cv)
+            out.append(r["sum_y2"] / r["n"] - (r["sum_y"] / r["n"]) ** 2)
+        a = gctx.mlmc_level(gm, gp, l, 4, 1 << 17, 77)
+        plain = a["sum_y2"] / a["n"] - (a["sum_y"] / a["n"]) ** 2
+        ratios.append(out[1] / out[0])
+        print(f"level {l}: plain V {plain:.5g}, network V {out[0]:.5g}, table V {out[1]:.5g}",
+              flush=True)
+    # the grid's time rows and stock/variance spacing cost some of the
+    # network's reduction (coarsest on Heston's three-input grid)
+    assert all(r < 1.25 for r in ratios), ratios
+    cv.close()

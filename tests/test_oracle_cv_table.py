@@ -35,10 +35,10 @@ def test_grid_of_the_model(orc, kind):
     m = orc.model(kind=kind)
     g = orc.cv_table_grid(m)
     sref = 0.2                                  # sigma, or sqrt(theta) = 0.2
-    assert (g.rows, g.ns, g.nv) == ((16, 512, 1) if kind == 0 else (8, 128, 8))
-    assert abs(g.s_lo - S0 * np.exp(-6 * sref)) < 1e-12 and abs(g.s_hi - S0 * np.exp(6 * sref)) < 1e-9
+    assert (g.rows, g.ns, g.nv) == ((256, 32, 1) if kind == 0 else (16, 16, 32))
+    assert abs(g.s_lo - S0 * np.exp(-4 * sref)) < 1e-12 and abs(g.s_hi - S0 * np.exp(4 * sref)) < 1e-9
     if kind == 1:
-        assert g.v_lo == 0.0 and abs(g.v_hi - 0.2) < 1e-15
+        assert g.v_lo == 0.0 and abs(g.v_hi - 0.16) < 1e-15
 
 
 @pytest.mark.parametrize("kind", [0, 1])
@@ -92,8 +92,7 @@ def test_network_table_matches_the_network(orc, kind):
             curv = abs(orc.cv_phi(m, exact, t, s + h, 0.04) - 2 * b + orc.cv_phi(m, exact, t, s - h, 0.04))
             errs.append(abs(a - b))
             assert abs(a - b) <= curv / 8 * 2 + 1e-9, (s, a, b, curv)
-    if errs:
-        assert max(errs) < 1e-2
+    assert len(errs) == (37 if kind == 0 else 0)
 
 
 @pytest.mark.parametrize("kind,pk", [(0, 1), (0, 0), (1, 0)])
@@ -115,8 +114,8 @@ def test_tabulated_control_variate_has_mean_zero(orc, kind, pk):
 
 def test_tabulated_level_sample_written_out(orc):
     """One coupled GBM sample at level 2 (M = 4) with the table, recomputed
-    from the oracle's normals: fine steps 0..15 read rows 0..15, the coarse
-    steps rows 0, 4, 8, 12."""
+    from the oracle's normals: fine step n reads row n rows / 16, coarse step
+    c row 4 c rows / 16."""
     m, p = orc.model(), orc.payoff(kind=0)
     g = orc.cv_table_grid(m)
     exact = orc.CVNet(net(orc, 2), 2, 64)
@@ -138,11 +137,11 @@ def test_tabulated_level_sample_written_out(orc):
         dw = np.sqrt(h) * z
         S, cvf = S0, 0.0
         for n in range(16):
-            cvf += interp(n, S) * dw[n]
+            cvf += interp(n * g.rows // 16, S) * dw[n]
             S = S + S * (0.05 * h + 0.2 * dw[n])
         Sc, cvc = S0, 0.0
         for c in range(4):
             dwc = dw[4 * c:4 * c + 4].sum()
-            cvc += interp(4 * c, Sc) * dwc
+            cvc += interp(4 * c * g.rows // 16, Sc) * dwc
             Sc = Sc + Sc * (0.05 * 4 * h + 0.2 * dwc)
         assert abs(cf - cvf) < 1e-10 and abs(cc - cvc) < 1e-10, (s, cf, cvf, cc, cvc)
