@@ -183,21 +183,26 @@ def oracle_rate(oracle, om, op, N, M, threads, budget_s):
     """Fine path-steps/s of the oracle on passes over levels 0..L with counts
     N_l (scaled down when a pass does not fit), run until the budget is used.
 
-    One untimed call first (thread start-up, first touch), then a probe sized
-    by time (>= 0.2 s of level-3 samples) for the first pass's scale; every
-    later pass is sized from the rate measured so far to the time left."""
+    One untimed call first (thread start-up, first touch), then a probe: a
+    pass over the same levels at a small scale, grown until it takes >= 0.2 s
+    (the levels' per-sample costs differ, so the probe has the run's mix); its
+    rate sizes the first pass, the rate measured so far every later one."""
     costs = [M**l + (M ** (l - 1) if l else 0) for l in range(len(N))]
     total = sum(n * c for n, c in zip(N, costs))
     oracle.level(om, op, 1, M, 1000, 97, nthreads=threads)
-    n = 2000
+    scale = min(1.0, 2e5 / total)
     while True:
         t0 = time.perf_counter()
-        oracle.level(om, op, 3, M, n, 98, nthreads=threads)
+        steps = 0.0
+        for l, nl in enumerate(N):
+            nn = max(1, int(nl * scale))
+            oracle.level(om, op, l, M, nn, 98, nthreads=threads)
+            steps += nn * costs[l]
         dt = time.perf_counter() - t0
-        if dt >= 0.2:
+        if dt >= 0.2 or scale >= 1.0:
             break
-        n = int(n * min(10.0, max(2.0, 0.25 / max(dt, 1e-6))))
-    rate = n * (M**3 + M**2) / dt
+        scale = min(1.0, scale * min(10.0, max(2.0, 0.25 / max(dt, 1e-6))))
+    rate = steps / dt
     fine = steps = 0.0
     passes, scales = 0, []
     t0 = time.perf_counter()
