@@ -1,11 +1,15 @@
 """Benchmark: adaptive MLMC on one MI355X, fine path-steps per second.
 
-One step = one complete adaptive MLMC estimate (every level sampled by the
-HIP level sampler, the fp64 driver update on the device) of the GBM European
-call (S0=100, r=0.05, sigma=0.2, T=1, K=100), M=4, fp32 paths with fp64 sums,
-one level per launch.  The target RMSE defaults to 2e-5*S0: with it the driver
-reaches about 10^8 samples at level 0, the scale that workload is described
-at (its listed RMSEs of 2e-3..5e-4*S0 need only 1.4e4..2.2e5 there).
+One step = one complete adaptive MLMC estimate (every level sampled on the
+GPU, the fp64 driver update on the device) of the GBM European call (S0=100,
+r=0.05, sigma=0.2, T=1, K=100), M=4, fp32 paths with fp64 sums.  By default
+the estimate runs device-planned: per driver iteration one launch of the
+all-levels sampler and one of the update-and-plan block, enqueued by the host
+one iteration ahead (--form per-level: one launch per level and iteration,
+with the host reading each update before it launches).  The target RMSE
+defaults to 2e-5*S0: with it the driver reaches about 10^8 samples at level
+0, the scale that workload is described at (its listed RMSEs of
+2e-3..5e-4*S0 need only 1.4e4..2.2e5 there).
 
 value = fine path steps computed by all steps / wall time of the K timed
 steps.  The JSON line also carries the roofline of the dominant kernel, timed
@@ -47,17 +51,36 @@ def algorithmic_ops(level, fine_steps, samples):
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
+# The sources each profiled kernel is compiled from: a committed counter
+# summary is used only while their digest is the one it was taken with.
+# The digest covers them and the compile flags.
+KERNEL_SOURCES = {
+    "level": ("philox.hpp", "sampler.hpp", "sampler_impl.hpp", "reduce.hpp", "level.hip",
+              "level.hpp", "level_kernels.hpp", "level_gbm.hip"),
+    "persistent": ("philox.hpp", "sampler.hpp", "sampler_impl.hpp", "reduce.hpp", "level.hpp",
+                   "driver.hpp", "driver_dev.hpp", "persistent.hpp", "persistent.hip",
+                   "persistent_gbm.hip"),
+}
+
+
+def kernel_sources_digest(kernel_label):
+    import hashlib
+    from paper_1505_00965_amd import build
+    h = hashlib.sha256()
+    family = "persistent" if kernel_label.startswith("persistent") else "level"
+    for f in KERNEL_SOURCES[family]:
+        with open(os.path.join(ROOT, "paper_1505_00965_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    flags = [f for f in build.COMMON if not f.startswith("-I") and "include" not in f]
+    h.update(" ".join(flags).encode())
+    return h.hexdigest()[:16]
+
+
 def profile_field(kernel_label, field):
     """A figure from the committed rocprofv3 summaries (profiles/*.md) of this
     kernel, or None if the kernel sources changed since they were taken."""
     import glob
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("philox.hpp", "sampler.hpp", "sampler_impl.hpp", "reduce.hpp", "level.hip",
-              "level.hpp", "level_kernels.hpp", "level_gbm.hip", "../build.py"):
-        with open(os.path.join(ROOT, "paper_1505_00965_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    digest = h.hexdigest()[:16]
+    digest = kernel_sources_digest(kernel_label)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         fields = {}
         for line in open(path):
@@ -89,8 +112,12 @@ def parse():
                     help="Adam steps for the control-variate networks (0: plain only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (scales HBM byte counters)")
-    ap.add_argument("--persistent", type=int, default=0,
-                    help="1: each driver iteration is one graph launch of the persistent kernel")
+    ap.add_argument("--stamp-stride", type=int, default=4,
+                    help="timed region: stamp one launch in this many of the dominant kernel")
+    ap.add_argument("--form", choices=("planned", "per-level"), default="planned",
+                    help="planned: per driver iteration one all-levels sampler launch and one "
+                         "update-and-plan launch, enqueued ahead by the host; per-level: one "
+                         "launch per level and iteration")
     # kernel profiling mode (for rocprofv3 counter runs): only repeated
     # launches of one level's sampler, with the tuned shape, then one JSON line
     ap.add_argument("--profile-level", type=int, default=None,
@@ -106,6 +133,9 @@ def parse():
                          "launch) with a network trained for 50 steps")
     ap.add_argument("--profile-cv-tab", action="store_true",
                     help="with --profile-cv: the tabulated network in the sampler")
+    ap.add_argument("--profile-run", type=int, default=0,
+                    help="profile mode: this many device-planned adaptive estimates of the "
+                         "benchmark workload (after tuning), then one JSON line")
     return ap.parse_args()
 
 
@@ -154,6 +184,37 @@ def profile_mode(args):
            "tuned_shape": None if cv else ctx.tuned_shape(m, p, l, M=M)}
     if cv is not None:
         cv.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def profile_run_mode(args):
+    """The benchmark's device-planned estimates, `profile_run` of them after
+    the tuners and a warm-up, untimed (counter runs take the last
+    `sampler_launches` persistent-sampler dispatches)."""
+    import torch
+    from paper_1505_00965_amd import mlmc, workloads as W
+    ctx = mlmc.Context(0)
+    ctx.set_stream(torch.cuda.current_stream())
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    M, eps = 4, args.eps * W.S0
+    run_kw = dict(M=M, L_min=2, L_max=9, n_pilot=10000, precision=32)
+    ctx.autotune(gm, gp, M=M, precision=32)
+    shape = ctx.autotune_run(gm, gp, eps, seed=1, **run_kw)
+    for i in range(2):
+        ctx.mlmc_run(gm, gp, eps, seed=1 + i, persistent=True, **run_kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [ctx.mlmc_run(gm, gp, eps, seed=1 + i, persistent=True, **run_kw)
+            for i in range(args.profile_run)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"mode": "profile-run", "runs": len(runs), "eps": args.eps,
+           "sampler_launches": sum(r["iterations"] + 1 for r in runs),
+           "fine_steps": sum(fine_steps_of(r, M) for r in runs),
+           "samples": float(sum(sum(r["N"]) for r in runs)), "ops": run_ops(runs, M),
+           "shape": list(shape), "wall_s": wall,
+           "kernel": f"persistent_kernel<GBM,M=4,ppt={shape[1]},call>"}
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -377,6 +438,32 @@ def persistent_batch(ctx, mlmc, W, reps=3):
             "level8_launch_us": tail}
 
 
+def level_rates(ctx, gm, gp, M, all_slots, steps, target_fine=1 << 30, reps=3):
+    """Each level's launches in the adaptive run (every slot timed) against the
+    same level's sampler saturated: one launch of about 2^30 fine steps."""
+    out = {}
+    for l in range(16):
+        s = all_slots[l]
+        if not s["launches"]:
+            continue
+        N = max(target_fine // M**l, 1 << 14)
+        ctx.set_timing_slots([l])
+        for r in range(reps):
+            ctx.mlmc_level(gm, gp, l, M, N, 1000 + r)
+        st = ctx.kernel_stats()[l]
+        ctx.set_timing(False)
+        run_rate = s["fine_steps"] / (s["ms"] * 1e-3)
+        sat_rate = st["fine_steps"] / (st["ms"] * 1e-3)
+        out[f"level_{l}"] = {"launches_per_step": s["launches"] / steps,
+                             "avg_launch_us": 1e3 * s["ms"] / s["launches"],
+                             "samples_per_launch": s["fine_steps"] / M**l / s["launches"],
+                             "fine_steps_per_s": run_rate,
+                             "saturated_samples_per_launch": N,
+                             "saturated_fine_steps_per_s": sat_rate,
+                             "frac_of_saturated": run_rate / sat_rate}
+    return out
+
+
 def accuracy_targets(ctx, mlmc, W, seeds=range(1, 33)):
     """The configurations' own accuracy targets, 32 seeds each: the adaptive
     GBM call (M = 4, eps in {2e-3, 1e-3, 5e-4} S0, against Black--Scholes)
@@ -442,6 +529,47 @@ def fig3(ctx, mlmc, W):
     return out
 
 
+def per_level_roofline(stats, lv, M, label):
+    """Roofline of one level's sampler from stamped launches (per-level form)."""
+    s = stats[lv]
+    if not s["launches"]:
+        return None
+    avg_ms = s["ms"] / s["launches"]
+    samples = s["fine_steps"] / M**lv
+    ops_per_launch = algorithmic_ops(lv, s["fine_steps"], samples) / s["launches"]
+    achieved = ops_per_launch / (avg_ms * 1e-3)
+    samples_per_s = samples / s["launches"] / (avg_ms * 1e-3)
+    r = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+         "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS,
+         "traffic": measured_traffic(label), "kernel": label,
+         "ops_per_sample": {"executed": OPS_PER_SAMPLE_L0 if lv == 0 else None,
+                            "method": OPS_PER_SAMPLE_L0_METHOD if lv == 0 else None},
+         "frac_method_ops": (achieved / VALU_PEAK_OPS * OPS_PER_SAMPLE_L0_METHOD
+                             / OPS_PER_SAMPLE_L0 if lv == 0 else None),
+         "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_ms, "launches": s["launches"],
+         "fine_steps_per_launch": s["fine_steps"] / s["launches"]}
+    # from the committed counter summaries of this kernel (profiles/):
+    # issued vector instructions x 4 cycles over SIMD cycles; this run's rate
+    # against the ceiling those instructions allow; fp32 FLOPs over the peak
+    r["valu_issue_frac_counters"] = profile_field(label, "valu_issue_frac")
+    ipsamp = profile_field(label, "valu_insts_per_sample")
+    r["valu_insts_per_sample"] = ipsamp
+    r["slot_ceiling_frac"] = samples_per_s * ipsamp / VALU_PEAK_OPS if ipsamp else None
+    fps = profile_field(label, "fp32_flops_per_sample")
+    r["fp32_flops_per_sample"] = fps
+    r["fp32_flop_frac"] = samples_per_s * fps / FP32_PEAK_FLOPS if fps else None
+    return r
+
+
+def run_ops(runs, M):
+    """Algorithmic vector-ALU operations of the runs' samples (all levels)."""
+    ops = 0.0
+    for r in runs:
+        for l, n in enumerate(r["N"]):
+            ops += algorithmic_ops(l, n * M**l, n)
+    return ops
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -461,122 +589,111 @@ def main():
         del src, dst
     if args.profile_level is not None:
         return profile_mode(args)
+    if args.profile_run:
+        return profile_run_mode(args)
     ctx = mlmc.Context(0)
     stream = torch.cuda.current_stream()
     ctx.set_stream(stream)
     gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
     M = 4
     eps = args.eps * W.S0
+    planned = args.form == "planned"
+    run_kw = dict(M=M, L_min=2, L_max=9, n_pilot=10000, precision=32)
 
-    def step(seed):
-        return ctx.mlmc_run(gm, gp, eps, M=M, L_min=2, L_max=9, n_pilot=10000, seed=seed,
-                            precision=32, persistent=bool(args.persistent))
+    def step(seed, persistent=planned):
+        return ctx.mlmc_run(gm, gp, eps, seed=seed, persistent=persistent, **run_kw)
 
-    for i in range(args.warmup):
-        step(1 + i % max(args.steps, 1))   # same seeds, hence launch sizes, as timed steps
+    def timed_pass(persistent=planned):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [step(1 + i, persistent) for i in range(args.steps)]
+        torch.cuda.synchronize()
+        return rs, time.perf_counter() - t0
+
+    def warm(persistent=planned):
+        for i in range(args.warmup):
+            step(1 + i % max(args.steps, 1), persistent)   # the timed steps' seeds, hence sizes
+
+    warm()
     # context: the same steps with the default launch shapes, before tuning
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(1 + i)
-    torch.cuda.synchronize()
-    dt_default = time.perf_counter() - t0
-    # the launch-shape autotuner for this model, payoff and M (three level
-    # classes, block x samples per lane, measured on this device); every
-    # later launch takes the tuned shapes
+    _, dt_default = timed_pass()
+    # launch-shape autotuners: the per-level sampler's shape per level (block
+    # x samples per lane, on this device) and, for the device-planned form,
+    # the persistent sampler's shape timed on this run configuration itself
     tune = {}
     t0 = time.perf_counter()
-    if args.persistent:
-        tune["persistent"] = ctx.autotune_persistent(gm, [gp], M=M, L=4)
-    else:
-        ctx.autotune(gm, gp, M=M, precision=32)
-        tune.update({f"level_{l}": ctx.tuned_shape(gm, gp, l, M=M) for l in (0, 1, 3)})
+    ctx.autotune(gm, gp, M=M, precision=32)
+    tune.update({f"level_{l}": ctx.tuned_shape(gm, gp, l, M=M) for l in range(7)})
+    if planned:
+        tune["planned_run"] = ctx.autotune_run(gm, gp, eps, seed=1, **run_kw)
     tune["tuning_s"] = time.perf_counter() - t0
-    for i in range(args.warmup):
-        step(1 + i % max(args.steps, 1))
+    warm()
     # Which kernel dominates: every slot timed over the same steps, untimed
-    # by the clock.  The timed region then stamps only that kernel's launches
-    # (each stamped launch costs the host ~10 us more than a plain one).
+    # by the clock.  The timed region then stamps one launch in
+    # --stamp-stride of that kernel only (a stamped launch costs ~10 us of
+    # queue time more than a plain one).
     ctx.set_timing(True)
-    for i in range(args.steps):
-        step(1 + i)
+    all_runs = [step(1 + i) for i in range(args.steps)]
     all_slots = ctx.kernel_stats()
     ctx.set_timing(False)
-    dom = mlmc.STAT_PERSISTENT if args.persistent else max(range(16), key=lambda l: all_slots[l]["ms"])
+    dom = mlmc.STAT_PERSISTENT if planned else max(range(16), key=lambda l: all_slots[l]["ms"])
     ctx.set_timing_slots([dom])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    runs = [step(1 + i) for i in range(args.steps)]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    ctx.set_timing_stride(args.stamp_stride)
+    runs, dt = timed_pass()
     stats = ctx.kernel_stats()
     ctx.set_timing(False)
-    # context: the same steps with no kernel stamped (a stamped launch costs
-    # the host ~10 us of event handling); `value` stays the timed region's
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(1 + i)
-    torch.cuda.synchronize()
-    dt_unstamped = time.perf_counter() - t0
+    ctx.set_timing_stride(1)
+    # context: the same steps with no kernel stamped
+    _, dt_unstamped = timed_pass()
 
     fine = sum(fine_steps_of(r, M) for r in runs)
     value = fine / dt
     roofline = None
-    if args.persistent:
-        # one graph launch (plan, persistent sampler, driver update) per iteration
-        s = stats[mlmc.STAT_PERSISTENT]
-        if s["launches"]:
-            avg_ms = s["ms"] / s["launches"]
-            samples = sum(sum(r["N"]) for r in runs) / s["launches"]
-            ops_per_launch = (OPS_PER_FINE_STEP * s["fine_steps"] / s["launches"]
-                              + OPS_PER_SAMPLE * samples)
-            achieved = ops_per_launch / (avg_ms * 1e-3)
-            roofline = {"bound": "alu", "achieved": achieved / 1e12,
-                        "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
-                        "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                        "kernel": "persistent_kernel<GBM,M=4> graph (plan + sampler + update)",
-                        "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_ms,
-                        "launches": s["launches"]}
-    else:
-        # dominant kernel: the level whose launches took the most time
-        lv = dom
-        s = stats[lv]
-        if s["launches"]:
-            avg_ms = s["ms"] / s["launches"]
-            samples = s["fine_steps"] / M**lv
-            ops_per_launch = algorithmic_ops(lv, s["fine_steps"], samples) / s["launches"]
-            achieved = ops_per_launch / (avg_ms * 1e-3)
-            label = ("short_level_kernel<GBM,call,fp32,n_f=1>" if lv == 0
-                     else f"level_kernel<GBM,call,fp32,M=4> at level {lv}")
-            samples_per_s = samples / s["launches"] / (avg_ms * 1e-3)
-            roofline = {"bound": "alu", "achieved": achieved / 1e12,
-                        "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
-                        "frac": achieved / VALU_PEAK_OPS, "traffic": measured_traffic(label),
-                        "kernel": label,
-                        # the target (half the vector-ALU peak) is judged by `frac`:
-                        # executed operations per sample over the issue peak
-                        "ops_per_sample": {"executed": OPS_PER_SAMPLE_L0 if lv == 0 else None,
-                                           "method": OPS_PER_SAMPLE_L0_METHOD if lv == 0 else None},
-                        "frac_method_ops": (achieved / VALU_PEAK_OPS * OPS_PER_SAMPLE_L0_METHOD
-                                            / OPS_PER_SAMPLE_L0 if lv == 0 else None),
-                        "ops_per_launch": ops_per_launch, "avg_launch_ms": avg_ms,
-                        "launches": s["launches"],
-                        "fine_steps_per_launch": s["fine_steps"] / s["launches"]}
-            # from the committed counter summaries of this kernel (profiles/):
-            # issued vector instructions x 4 cycles over SIMD cycles
-            # (SQ_INSTS_VALU, GRBM_GUI_ACTIVE); this run's rate against the
-            # ceiling those instructions allow; fp32 FLOPs (an fma counts 2,
-            # SQ_INSTS_VALU_FLOPS_FP32 + _TRANS) per second over the fp32 peak
-            roofline["valu_issue_frac_counters"] = profile_field(label, "valu_issue_frac")
-            ipsamp = profile_field(label, "valu_insts_per_sample")
-            roofline["valu_insts_per_sample"] = ipsamp
-            roofline["slot_ceiling_frac"] = (samples_per_s * ipsamp / VALU_PEAK_OPS
-                                             if ipsamp else None)
-            fps = profile_field(label, "fp32_flops_per_sample")
-            roofline["fp32_flops_per_sample"] = fps
-            roofline["fp32_flop_frac"] = samples_per_s * fps / FP32_PEAK_FLOPS if fps else None
+    s = stats[dom]
+    if planned and s["launches"]:
+        # the device-planned form: one persistent all-levels sampler launch
+        # per driver iteration (and the empty one queued past the last
+        # update).  The host sees only whole runs, so the operations of all
+        # the timed runs are spread over all their sampler launches, and the
+        # stamped launches (every --stamp-stride-th) give the average time.
+        launches = sum(r["iterations"] + 1 for r in runs)
+        ops = run_ops(runs, M)
+        avg_ms = s["ms"] / s["launches"]
+        achieved = ops / launches / (avg_ms * 1e-3)
+        shape = tune.get("planned_run") or (256, 1, 4)
+        label = f"persistent_kernel<GBM,M=4,ppt={shape[1]},call>"
+        a = all_slots[dom]
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                    "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS,
+                    "traffic": measured_traffic(label), "kernel": label,
+                    "launch_shape": {"block": shape[0], "ppt": shape[1], "blocks_per_cu": shape[2]},
+                    "ops_per_launch": ops / launches, "avg_launch_ms": avg_ms,
+                    "launches": s["launches"], "launches_in_timed_region": launches,
+                    "stamp_stride": args.stamp_stride,
+                    # every sampler launch of the same steps stamped (the
+                    # all-slots pass): the sampled average's cross-check
+                    "avg_launch_ms_all_stamped": a["ms"] / a["launches"] if a["launches"] else None,
+                    "share_of_step": launches * avg_ms * 1e-3 / dt}
+        # from the committed counter summary of this kernel (profiles/): its
+        # issue fraction under the counters, this run's rate against the
+        # ceiling its instructions per fine step allow, and its fp32 FLOPs
+        # over the fp32 peak
+        fine_per_s = fine / launches / (avg_ms * 1e-3)
+        roofline["valu_issue_frac_counters"] = profile_field(label, "valu_issue_frac")
+        ipf = profile_field(label, "valu_insts_per_fine_step")
+        roofline["valu_insts_per_fine_step"] = ipf
+        roofline["slot_ceiling_frac"] = fine_per_s * ipf / VALU_PEAK_OPS if ipf else None
+        fpf = profile_field(label, "fp32_flops_per_fine_step")
+        roofline["fp32_flops_per_fine_step"] = fpf
+        roofline["fp32_flop_frac"] = fine_per_s * fpf / FP32_PEAK_FLOPS if fpf else None
+    elif s["launches"]:
+        label = ("short_level_kernel<GBM,call,fp32,n_f=1>" if dom == 0
+                 else f"level_kernel<GBM,call,fp32,M=4> at level {dom}")
+        roofline = per_level_roofline(stats, dom, M, label)
+        roofline["launches_in_timed_region"] = all_slots[dom]["launches"]
+        roofline["stamp_stride"] = args.stamp_stride
 
+    upd = all_slots[mlmc.STAT_DRIVER]
     line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
             "ms_per_step_unstamped": 1e3 * dt_unstamped / args.steps,
@@ -585,34 +702,42 @@ def main():
             "data": "synthetic",
             "config": {"workload": f"adaptive MLMC, GBM European call S0=100 r=0.05 sigma=0.2 "
                                    f"T=1 K=100, M=4, RMSE {args.eps:g}*S0, fp32 paths fp64 sums, "
-                                   + ("one graph launch per driver iteration" if args.persistent
+                                   + ("device-planned: per driver iteration one all-levels "
+                                      "sampler launch and one update-and-plan launch, enqueued "
+                                      "ahead of the host" if planned
                                       else "one level per launch"),
                        "levels": runs[-1]["L"] + 1, "N_l": runs[-1]["N"],
+                       "iterations": runs[-1]["iterations"],
                        "estimate": runs[-1]["estimate"], "tuned_shapes": tune},
-            "roofline": roofline}
+            "roofline": roofline,
+            "update_kernel_us": 1e3 * upd["ms"] / upd["launches"] if upd["launches"] else None}
 
-    if not args.persistent and not args.no_tta:
-        # the same estimates with every driver iteration as one graph launch
-        # (plan, persistent all-levels sampler, driver update), in the shape
-        # the persistent form's tuner picks for this payoff and depth
-        t0 = time.perf_counter()
-        pshape = ctx.autotune_persistent(gm, [gp], M=M, L=runs[-1]["L"])
-        ptune_s = time.perf_counter() - t0
-        for i in range(args.warmup):
-            ctx.mlmc_run(gm, gp, eps, M=M, L_min=2, L_max=9, n_pilot=10000,
-                         seed=1 + i % max(args.steps, 1), precision=32, persistent=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        gr = [ctx.mlmc_run(gm, gp, eps, M=M, L_min=2, L_max=9, n_pilot=10000, seed=1 + i,
-                           precision=32, persistent=True) for i in range(args.steps)]
-        torch.cuda.synchronize()
-        dtg = time.perf_counter() - t0
-        line["adaptive_graph_form"] = {
-            "ms_per_step": 1e3 * dtg / args.steps,
-            "tuned_shape": {"block": pshape[0], "ppt": pshape[1], "blocks_per_cu": pshape[2],
-                            "tuning_s": ptune_s},
-            "fine_path_steps_per_s": sum(fine_steps_of(r, M) for r in gr) / dtg,
-            "same_N_l": all(a["N"] == b["N"] for a, b in zip(runs, gr))}
+    if planned:
+        # context: the per-level form of the same estimates (one launch per
+        # level and iteration, the tuned per-level shapes), its per-level
+        # rates against each level saturated, and its dominant kernel
+        warm(False)
+        pl_runs, pl_dt = timed_pass(False)
+        ctx.set_timing(True)
+        for i in range(args.steps):
+            step(1 + i, False)
+        pl_slots = ctx.kernel_stats()
+        ctx.set_timing(False)
+        ctx.set_timing_slots([0])
+        ctx.set_timing_stride(args.stamp_stride)
+        timed_pass(False)
+        pl_stats = ctx.kernel_stats()
+        ctx.set_timing(False)
+        ctx.set_timing_stride(1)
+        line["per_level_form"] = {
+            "ms_per_step": 1e3 * pl_dt / args.steps,
+            "fine_path_steps_per_s": sum(fine_steps_of(r, M) for r in pl_runs) / pl_dt,
+            "same_N_l": all(a["N"] == b["N"] for a, b in zip(runs, pl_runs)),
+            "level0_roofline": per_level_roofline(pl_stats, 0, M,
+                                                  "short_level_kernel<GBM,call,fp32,n_f=1>"),
+            "per_level": level_rates(ctx, gm, gp, M, pl_slots, args.steps)}
+    else:
+        line["per_level"] = level_rates(ctx, gm, gp, M, all_slots, args.steps)
     if not args.no_tta:
         line["persistent_batch"] = persistent_batch(ctx, mlmc, W)
         line["seconds_to_rmse"] = time_to_accuracy(ctx, mlmc, W, args)

@@ -138,9 +138,14 @@ mlmc_status mlmc_set_launch(mlmc_ctx* ctx, int block, int ppt);
 
 /* Kernel timing with HIP events on the context's stream.  Slots:
  *   0..15  level sampler launches at level l (per-level entry points and
- *          per-level driver iterations), 16 persistent all-levels launches,
- *   17     driver update kernel, 18 control-variate training steps.
- * fine_steps / coarse_steps: path steps those launches computed.          */
+ *          per-level driver iterations), 16 persistent all-levels launches
+ *          (the batch graph of mlmc_levels_batch; the sampler kernel of the
+ *          device-planned mlmc_run),
+ *   17     driver update kernel (with the plan in the device-planned run),
+ *   18     control-variate training steps.
+ * fine_steps / coarse_steps: path steps those launches computed (a
+ * device-planned run charges all of its steps to its first stamped sampler
+ * launch: the host does not see the per-iteration batches).              */
 #define MLMC_STAT_SLOTS 20
 typedef struct {
     uint64_t launches;
@@ -155,16 +160,24 @@ mlmc_status mlmc_set_timing(mlmc_ctx* ctx, int on);
  * kernel's duration without slowing the rest times that slot alone.
  * MLMC_EINVAL for bits at or above MLMC_STAT_SLOTS.                          */
 mlmc_status mlmc_set_timing_mask(mlmc_ctx* ctx, uint32_t slot_mask);
+/* Time one launch in `stride` of each timed slot (the 1st, (stride+1)-th,
+ * ... launch of the slot since the mask was last set; 1, the default, times
+ * every launch).  A timed launch costs ~10 us of queue time, so a caller that
+ * wants a slot's average duration over a long run without slowing it in
+ * proportion samples it.  MLMC_EINVAL for 0.                               */
+mlmc_status mlmc_set_timing_stride(mlmc_ctx* ctx, uint32_t stride);
 /* Copy MLMC_STAT_SLOTS statistics into out (host array). */
 mlmc_status mlmc_kernel_stats(mlmc_ctx* ctx, mlmc_kernel_stat* out);
 
 /* Autotuner: times every block size {64..1024} x samples-per-lane {1,2,4}
- * (fp64: 1) of the level sampler on a device-filling sample count for three
- * level classes (one-step levels, 2..16 fine steps, longer paths) and keeps
- * the fastest for this (model kind, scheme, antithetic flag, payoff,
- * precision, M); later launches use it unless mlmc_set_launch fixed a shape
- * (a launch with fewer samples than 256 lanes per compute unit at the tuned
- * ppt still takes ppt 1).  Results are cached in the JSON file
+ * (fp64: 1) of the level sampler on 2^25 fine path steps (median of five
+ * launches) for seven level classes (levels 0..5 each, deeper levels at
+ * level 6) and keeps the fastest for this (model kind, scheme,
+ * antithetic flag, payoff, precision, M); later launches use it unless
+ * mlmc_set_launch fixed a shape.  A launch with fewer samples than 256 lanes
+ * per compute unit at the tuned ppt takes ppt 1, and a smaller launch halves
+ * ppt, then the block, until it has a block per compute unit and two waves
+ * per SIMD.  Results are cached in the JSON file
  * cache_path (or $MLMC_TUNE_CACHE; NULL/"" and no variable: no cache) under
  * a key of GPU architecture, compute-unit count and HIP runtime version, and
  * read back instead of measured when present.                             */
@@ -286,8 +299,11 @@ typedef struct {
     uint64_t seed;
     int precision;       /* 32 or 64                                         */
     int persistent;      /* 0: one launch per level and iteration; 1: every
-                            iteration is one graph launch of the persistent
-                            all-levels kernel (plan, sampler, update)        */
+                            iteration is one launch of the persistent
+                            all-levels sampler and one of a block that
+                            absorbs the batch and plans the next; the host
+                            enqueues each iteration before the previous
+                            update is read (the device plans every batch)  */
     double alpha, beta;  /* assumed weak and variance rates (<= 0: 1 and 1) */
     const mlmc_cv* cv;   /* NULL: plain MLMC.  Needs precision 32 and
                             persistent 0 (MLMC_EINVAL otherwise).             */
@@ -324,6 +340,19 @@ typedef struct {
  * is reached first (result still filled).                                    */
 mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
                      const mlmc_run_opts* opts, mlmc_run_result* out);
+
+/* Autotuner of the device-planned run (mlmc_run with opts->persistent = 1):
+ * times whole runs of this model, payoff and opts (a warm-up, then the
+ * median of three, all with opts->seed) for every persistent launch shape
+ * of mlmc_autotune_persistent's candidate set and sets the fastest with
+ * mlmc_set_persistent_launch.  The runs' batches are the tuned workload, so
+ * the shape suits that configuration's launch sizes.  Cached like
+ * mlmc_autotune's under the machine key and (model kind, scheme, payoff
+ * kind, M, eps, L_min, L_max, precision, n_pilot, alpha, beta); a cached
+ * shape is set without measuring.  shape (host, 3 ints, may be NULL)
+ * receives block, ppt, blocks_per_cu.  MLMC_EINVAL unless persistent = 1. */
+mlmc_status mlmc_autotune_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                              const mlmc_run_opts* opts, const char* cache_path, int* shape);
 
 /* ----------------------------------------------- randomised estimator
  * Rhee and Glynn's randomised multilevel estimator (cited in Sec. 7): each

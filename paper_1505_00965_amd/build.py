@@ -15,8 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlmc.so")
 SOURCES = ["capi.cpp", "level.hip", "level_gbm.hip", "level_gbm_mil.hip", "level_heston.hip",
-           "driver.hip", "persistent.hip", "cv.hip", "autotune.cpp", "rhee_glynn.hip",
-           "noalloc.hip"]
+           "driver.hip", "persistent.hip", "persistent_gbm.hip", "persistent_gbm_mil.hip",
+           "persistent_heston.hip", "cv.hip", "autotune.cpp", "rhee_glynn.hip", "noalloc.hip"]
 ARCH = "gfx950"
 ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 

@@ -23,15 +23,14 @@
 
 namespace mlmc {
 
-// Level classes: one-step levels (shared generator blocks), short paths
-// (2..16 fine steps) and long paths.
+// Level classes: levels 0..5 each (an adaptive run's launch sizes differ by
+// level: N_l falls about as fast as the fine steps M^l grow, so each level's
+// launches have a size of their own) and the deeper levels together.
+constexpr int kTuneClasses = 7;
 int level_class(int l, int M)
 {
-    int nf = 1;
-    for (int i = 0; i < l; ++i) nf *= M;
-    if (nf < 4) return 0;
-    if (nf <= 16) return 1;
-    return 2;
+    (void)M;
+    return l < kTuneClasses - 1 ? l : kTuneClasses - 1;
 }
 
 // The scheme and the antithetic twin change the kernel (register use, work
@@ -143,7 +142,7 @@ bool tuned_shape(const mlmc_ctx* ctx, const mlmc_model& m, int payoff, int preci
     return true;
 }
 
-// Time one level launch shape (median of 3 after a warm-up), milliseconds.
+// Time one level launch shape (median of 5 after a warm-up), milliseconds.
 static float time_shape(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p, int l, int M,
                         uint64_t N, int precision, int block, int ppt, mlmc_status* st)
 {
@@ -153,8 +152,8 @@ static float time_shape(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
-    float best[3] = {1e30f, 1e30f, 1e30f};
-    for (int rep = 0; rep < 4 && !*st; ++rep) {
+    float best[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+    for (int rep = 0; rep < 6 && !*st; ++rep) {
         hipEventRecord(a, ctx->stream);
         *st = enqueue_level(ctx, m, p, l, M, N, 12345, 0, precision, kStreamNormal, 1, ctx->d_acc,
                             nullptr, nullptr, nullptr, true);
@@ -168,8 +167,8 @@ static float time_shape(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p
     hipEventDestroy(b);
     ctx->launch_block = saved_b;
     ctx->launch_ppt = saved_p;
-    std::sort(best, best + 3);
-    return best[1];
+    std::sort(best, best + 5);
+    return best[2];
 }
 
 }  // namespace mlmc
@@ -194,19 +193,21 @@ mlmc_status mlmc_autotune(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_pay
     bool dirty = false;
     const int blocks[] = {64, 128, 256, 512, 1024};
     const int ppts32[] = {1, 2, 4};
-    // representative levels and sizes per class: saturate the device
-    const int reps[3] = {0, M == 4 ? 2 : 3, M == 4 ? 4 : 7};
-    for (int cls = 0; cls < 3; ++cls) {
+    // each class at its first level, on 2^25 fine path steps per launch:
+    // N_l M^l is about level-independent in an adaptive run, and 2^25 is its
+    // size near RMSE 2e-5 S0 (smaller launches are cut down further by the
+    // fill rule of the default shape)
+    for (int cls = 0; cls < kTuneClasses; ++cls) {
         const std::string key = tune_key(*model, payoff->kind, precision, M, cls);
         auto mit = cache.find(mk);
         if (mit != cache.end() && mit->second.count(key)) {
             ctx->tuned[key] = mit->second[key];
             continue;
         }
-        const int l = reps[cls];
+        const int l = cls;
         double nf = 1.0;
         for (int i = 0; i < l; ++i) nf *= M;
-        const uint64_t N = (uint64_t)std::max(1.0, (double)(1ull << 27) / nf);
+        const uint64_t N = (uint64_t)std::max(1.0, (double)(1ull << 25) / nf);
         float best = 1e30f;
         int bb = 256, bp = precision == 64 ? 1 : 2;
         for (int b : blocks)
@@ -294,6 +295,76 @@ mlmc_status mlmc_autotune_persistent(mlmc_ctx* ctx, const mlmc_model* model,
         }
     cache[mk][key] = {bb, bp, bc};
     const mlmc_status st = mlmc_set_persistent_launch(ctx, bb, bp, bc);
+    if (st) return st;
+    if (shape) {
+        shape[0] = bb;
+        shape[1] = bp;
+        shape[2] = bc;
+    }
+    if (!path.empty() && !write_cache(path, cache))
+        return fail(ctx, MLMC_EINVAL, "could not write the tuning cache " + path);
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_autotune_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* payoff,
+                              const mlmc_run_opts* opts, const char* cache_path, int* shape)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (!model || !payoff || !opts) return fail(ctx, MLMC_EINVAL, "model, payoff and opts must not be NULL");
+    if (opts->persistent != 1)
+        return fail(ctx, MLMC_EINVAL, "the run autotuner tunes the device-planned form (persistent = 1)");
+    mlmc_status st = check_level_args(ctx, model, payoff, 0, opts->M, opts->precision);
+    if (st) return st;
+    ctx->err.clear();
+    MLMC_HIP(ctx, hipSetDevice(ctx->device));
+    std::string path;
+    if (cache_path && *cache_path) path = cache_path;
+    else if (const char* e = std::getenv("MLMC_TUNE_CACHE")) path = e;
+    const std::string mk = machine_key(ctx);
+    auto cache = path.empty() ? decltype(read_cache(path)){} : read_cache(path);
+    // the run's whole configuration is the key: it sets the batches
+    char kb[192];
+    std::snprintf(kb, sizeof kb, "run:%d:%d:%d:%d:%.9g:%d:%d:%d:%llu:%.9g:%.9g", model->kind,
+                  model->scheme, payoff->kind, opts->M, opts->eps, opts->L_min, opts->L_max,
+                  opts->precision, (unsigned long long)opts->n_pilot, opts->alpha, opts->beta);
+    const std::string key = kb;
+    auto mit = cache.find(mk);
+    if (mit != cache.end() && mit->second.count(key) && mit->second[key].size() == 3) {
+        const auto& v = mit->second[key];
+        if (shape) std::memcpy(shape, v.data(), 3 * sizeof(int));
+        return mlmc_set_persistent_launch(ctx, v[0], v[1], v[2]);
+    }
+    const int blocks[] = {128, 256, 512};
+    const int bpcs[] = {2, 4, 8};
+    const int ppts[] = {1, 2, 4};
+    double best = 1e30;
+    int bb = 256, bp = 1, bc = 4;
+    mlmc_run_result res;
+    for (int b : blocks)
+        for (int c : bpcs) {
+            if (b * c > 2048) continue;   // resident: at most 2048 threads per compute unit
+            for (int p : ppts) {
+                st = mlmc_set_persistent_launch(ctx, b, p, c);
+                double t[3] = {0, 0, 0};
+                // a warm-up run, then the median of three (the same seed: the
+                // same batches for every shape)
+                for (int rep = 0; rep < 4 && !st; ++rep) {
+                    const auto t0 = std::chrono::steady_clock::now();
+                    st = mlmc_run(ctx, model, payoff, opts, &res);
+                    if (st == MLMC_ENOTCONV) st = MLMC_OK;   // timed all the same
+                    const auto t1 = std::chrono::steady_clock::now();
+                    if (rep > 0) t[rep - 1] = std::chrono::duration<double>(t1 - t0).count();
+                }
+                if (st) {
+                    mlmc_set_persistent_launch(ctx, 0, 0, 0);
+                    return st;
+                }
+                std::sort(t, t + 3);
+                if (t[1] < best) { best = t[1]; bb = b; bp = p; bc = c; }
+            }
+        }
+    cache[mk][key] = {bb, bp, bc};
+    st = mlmc_set_persistent_launch(ctx, bb, bp, bc);
     if (st) return st;
     if (shape) {
         shape[0] = bb;

@@ -114,6 +114,18 @@ LaunchShape default_shape(const mlmc_model& m, const mlmc_payoff& p, int l, int 
     if (s.split > 1) {
         s.ppt = 1;
         units = N;   // paths, block / split per block at a time
+    } else if (!fixed_block) {
+        // a tuned shape is measured at device-filling counts: for a smaller
+        // launch halve the samples per lane, then the block, until the launch
+        // has a block per compute unit and two waves per SIMD (or is 64 x 1)
+        for (;;) {
+            const uint64_t c = (uint64_t)s.block * s.ppt, blocks = (units + c - 1) / c;
+            if ((blocks >= (uint64_t)num_cu && blocks * (uint64_t)(s.block / 64) >= 8ull * num_cu) ||
+                (s.ppt == 1 && s.block == 64))
+                break;
+            if (s.ppt > 1) s.ppt /= 2;
+            else s.block /= 2;
+        }
     }
     const uint64_t chunk = s.split > 1 ? (uint64_t)s.block / s.split : (uint64_t)s.block * s.ppt;
     const uint64_t chunks = (units + chunk - 1) / chunk;
@@ -175,9 +187,17 @@ static hipEvent_t pool_event(mlmc_ctx* ctx)
     return e;
 }
 
+// Timing on for this launch of the slot: its bit is set and, with a stride
+// k, it is the first, (k+1)-th, (2k+1)-th ... launch since the mask was set.
+static bool time_this(mlmc_ctx* ctx, int slot)
+{
+    if (!(ctx->timing >> slot & 1u)) return false;
+    return ctx->timing_seen[slot]++ % ctx->timing_stride == 0;
+}
+
 int timed_begin(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_steps)
 {
-    if (!(ctx->timing >> slot & 1u)) return -1;
+    if (!time_this(ctx, slot)) return -1;
     mlmc_ctx::Timed t;
     t.start = pool_event(ctx);
     t.stop = pool_event(ctx);
@@ -194,7 +214,7 @@ void timed_kernel(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_step
                   hipEvent_t* start, hipEvent_t* stop)
 {
     *start = *stop = nullptr;
-    if (!(ctx->timing >> slot & 1u)) return;
+    if (!time_this(ctx, slot)) return;
     mlmc_ctx::Timed t;
     t.start = pool_event(ctx);
     t.stop = pool_event(ctx);
@@ -213,21 +233,34 @@ void timed_end(mlmc_ctx* ctx, int idx)
     hipEventRecord(ctx->pending[idx].stop, ctx->stream);
 }
 
+static void harvest_one(mlmc_ctx* ctx, const mlmc_ctx::Timed& t)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+        mlmc_kernel_stat& s = ctx->stats[t.slot];
+        s.launches += 1;
+        s.ms += ms;
+        s.fine_steps += t.fine_steps;
+        s.coarse_steps += t.coarse_steps;
+    }
+    ctx->event_pool.push_back(t.start);
+    ctx->event_pool.push_back(t.stop);
+}
+
 void harvest_timing(mlmc_ctx* ctx)
 {
-    for (auto& t : ctx->pending) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
-            mlmc_kernel_stat& s = ctx->stats[t.slot];
-            s.launches += 1;
-            s.ms += ms;
-            s.fine_steps += t.fine_steps;
-            s.coarse_steps += t.coarse_steps;
-        }
-        ctx->event_pool.push_back(t.start);
-        ctx->event_pool.push_back(t.stop);
-    }
+    for (auto& t : ctx->pending) harvest_one(ctx, t);
     ctx->pending.clear();
+}
+
+void harvest_ready(mlmc_ctx* ctx)
+{
+    // the events of one stream complete in order: stop at the first one
+    // still outstanding
+    size_t k = 0;
+    while (k < ctx->pending.size() && hipEventQuery(ctx->pending[k].stop) == hipSuccess)
+        harvest_one(ctx, ctx->pending[k++]);
+    ctx->pending.erase(ctx->pending.begin(), ctx->pending.begin() + k);
 }
 
 // One launch over a range whose generator units share their counter word 2.
@@ -441,8 +474,18 @@ mlmc_status mlmc_set_timing_mask(mlmc_ctx* ctx, uint32_t slot_mask)
     if (ctx->stream) MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     harvest_timing(ctx);
     ctx->timing = slot_mask;
+    for (auto& n : ctx->timing_seen) n = 0;
     if (slot_mask)
         for (auto& s : ctx->stats) s = mlmc_kernel_stat{};
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_set_timing_stride(mlmc_ctx* ctx, uint32_t stride)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (stride < 1) return fail(ctx, MLMC_EINVAL, "stride must be >= 1");
+    ctx->timing_stride = stride;
+    for (auto& n : ctx->timing_seen) n = 0;
     return MLMC_OK;
 }
 

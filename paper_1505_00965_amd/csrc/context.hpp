@@ -39,6 +39,8 @@ struct mlmc_ctx {
         double fine_steps, coarse_steps;
     };
     uint32_t timing = 0;                    // bit s: time launches of slot s
+    uint32_t timing_stride = 1;             // time one launch in this many of a slot
+    uint64_t timing_seen[MLMC_STAT_SLOTS] = {};   // launches of each slot since the mask was set
     std::vector<hipEvent_t> event_pool;
     std::vector<Timed> pending;
     mlmc_kernel_stat stats[MLMC_STAT_SLOTS] = {};
@@ -110,6 +112,9 @@ void timed_kernel(mlmc_ctx* ctx, int slot, double fine_steps, double coarse_step
                   hipEvent_t* start, hipEvent_t* stop);
 // After the stream has been synchronised: fold finished events into stats.
 void harvest_timing(mlmc_ctx* ctx);
+// Fold in the stamped launches that have finished, without waiting for the
+// stream (the rest stay pending until a later harvest).
+void harvest_ready(mlmc_ctx* ctx);
 
 // Release the driver state and the persistent batch buffers (idempotent).
 void free_driver(mlmc_ctx* ctx);

@@ -34,8 +34,9 @@ __global__ void driver_init_kernel(DriverState* st, LevelAcc* spread, DriverInit
 
 // has_init: the run's first update, which builds the state itself (the
 // spread groups hold the pilot's sums and nothing else).
-__global__ void driver_update_kernel(DriverState* st, DriverState* mirror, LevelAcc* spread,
-                                     DriverInit c, int has_init)
+__global__ __launch_bounds__(512) void driver_update_kernel(DriverState* st, DriverState* mirror,
+                                                            LevelAcc* spread, DriverInit c,
+                                                            int has_init)
 {
     __shared__ DriverState s;
     driver_update_block(st, mirror, s, spread, has_init ? &c : nullptr);
@@ -73,10 +74,10 @@ hipError_t launch_driver_update(DriverState* st, DriverState* mirror, LevelAcc* 
     const DriverInit c = init ? *init : DriverInit{};
     const int has_init = init ? 1 : 0;
     if (start || stop)
-        hipExtLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, start, stop, 0, st,
+        hipExtLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(512), 0, stream, start, stop, 0, st,
                               mirror, spread, c, has_init);
     else
-        hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(256), 0, stream, st, mirror, spread, c,
+        hipLaunchKernelGGL(driver_update_kernel, dim3(1), dim3(512), 0, stream, st, mirror, spread, c,
                            has_init);
     return hipGetLastError();
 }
@@ -108,9 +109,11 @@ static mlmc_status ensure_driver(mlmc_ctx* ctx)
     return MLMC_OK;
 }
 
-// persistent.hip: one iteration as one graph launch
+// persistent.hip: the device-planned form (start kernel, then the sampler
+// and the update-and-plan block per iteration)
 mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p,
-                           const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st);
+                           const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st,
+                           const DriverInit& init);
 
 }  // namespace mlmc
 
@@ -203,17 +206,19 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     init.pad = 0;
     // The per-level form lets its first update build the state when the
     // spread groups are known to hold zeros (one launch fewer on the pilot's
-    // path); otherwise, and for the graph form, a kernel clears both first.
+    // path); otherwise a kernel clears both first (in the device-planned
+    // form, its start kernel).
     // Until this run ends normally the groups are not known to be clear.
     const bool fused_init = ctx->drv_clean && !o.persistent;
     ctx->drv_clean = false;
-    if (!fused_init) {
+    if (!fused_init && !o.persistent) {
         hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d,
                            ctx->d_drv_spread, init);
         MLMC_HIP(ctx, hipGetLastError());
     }
     if (o.persistent) {
-        st = run_persistent(ctx, *model, *payoff, o, d, h);
+        // its start kernel builds the state and clears the groups
+        st = run_persistent(ctx, *model, *payoff, o, d, h, init);
         if (st) return st;
     } else {
         for (int it = 0;; ++it) {
@@ -241,12 +246,10 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
             MLMC_HIP(ctx, wait_update(ctx->stream, h, (unsigned long long)it + 1));
             if (mirror_done(h)) break;
         }
-        // the mirror holds the final state; the stream is waited for only to
-        // read timing events (later work on it is ordered after this run)
-        if (!ctx->pending.empty()) {
-            MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            harvest_timing(ctx);
-        }
+        // the mirror holds the final state; stamped launches that have
+        // finished are read now, the rest (the last update's, usually) by a
+        // later harvest: the run does not wait for the stream
+        if (!ctx->pending.empty()) harvest_ready(ctx);
     }
     ctx->drv_clean = true;
     const auto t1 = std::chrono::steady_clock::now();

@@ -246,7 +246,9 @@ __device__ __forceinline__ void driver_update_wave(DriverState& s)
 // to the host's pinned mirror (if any): everything before the batch records
 // but `seq` first, then a system-scope fence, then `seq` (there 2 x the
 // update count + the done flag), so a host that sees the new word sees the
-// whole update, and the done flag of that same update.  Once the state is done the call
+// whole update, and the done flag of that same update.  With mirror_each
+// false only the finishing update writes the whole mirror; the others write
+// `seq` alone (for a host that reads the state at the end only).  Once the state is done the call
 // does nothing (no write, `seq` unchanged), so launches queued past the last
 // update are harmless.  With `spread` (kMaxLevels spread
 // groups, one per level) the block first folds each sampled level's group
@@ -256,7 +258,8 @@ __device__ __forceinline__ void driver_update_wave(DriverState& s)
 // pilot's sums).  Every thread of the block must call it; `s` is
 // the block's LDS copy of the state.
 __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s,
-                                                    LevelAcc* spread, const DriverInit* init = nullptr)
+                                                    LevelAcc* spread, const DriverInit* init = nullptr,
+                                                    bool mirror_each = true)
 {
     static_assert(sizeof(DriverState) % 8 == 0, "state is copied in 8-byte words");
     static_assert(offsetof(DriverState, seq) % 8 == 0, "seq is one word");
@@ -306,10 +309,12 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
         constexpr int kMirrorWords = offsetof(DriverState, batch) / 8;
         static_assert(kSeq < kMirrorWords, "seq precedes the batch records");
         volatile unsigned long long* h = (volatile unsigned long long*)mirror;
-        for (int i = threadIdx.x; i < kMirrorWords; i += blockDim.x)
-            if (i != kSeq) h[i] = w[i];
-        __threadfence_system();
-        __syncthreads();
+        if (mirror_each || s.done) {    // block-uniform (LDS after a barrier)
+            for (int i = threadIdx.x; i < kMirrorWords; i += blockDim.x)
+                if (i != kSeq) h[i] = w[i];
+            __threadfence_system();
+            __syncthreads();
+        }
         // the published word carries the done flag beside the update count
         if (threadIdx.x == 0) h[kSeq] = 2ull * w[kSeq] + (s.done ? 1ull : 0ull);
     }

@@ -12,7 +12,10 @@
 // device run each path on several lanes (process_split), with the per-level
 // launch's rule on the level's count.  Every parameter the launches read lives in
 // device memory and is rewritten between launches (by the driver kernel or
-// by host copies), so the graph is captured once and replayed.
+// by host copies): a batch of levels is a graph captured once and replayed,
+// and the adaptive driver's run is two plain launches per iteration (the
+// sampler, then one block that absorbs the batch and plans the next).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -21,144 +24,119 @@
 
 #include "context.hpp"
 #include "driver.hpp"
-#include "sampler_impl.hpp"
+#include "driver_dev.hpp"
+#include "persistent.hpp"
 #include "trace.hpp"
 
 namespace mlmc {
 
-constexpr int kMaxSlots = 4;          // payoffs per batch
-constexpr int kItemsPerBlock = 4;     // target items per resident block
-constexpr unsigned kItemsPerPair = 1024;
-constexpr unsigned kMaxItems = kMaxSlots * kMaxLevels * kItemsPerPair;
-
-struct WorkItem {
-    uint64_t first;     // first sample index of the range
-    uint32_t n;         // number of samples
-    uint16_t level;
-    uint8_t slot;       // payoff slot
-    uint8_t pad;
-};
-
-// Device-resident batch description (rewritten before each launch).
-struct BatchDesc {
-    int nslots, L, M, pad;
-    int payoff_kind[kMaxSlots];
-    StepParams<float> params[kMaxSlots][kMaxLevels];
-    uint64_t seed;
-    // outstanding samples and their first index, per (slot, level); for the
-    // driver these alias DriverState::dN / n (slot 0 only)
-    const double* dN;
-    const double* offset;
-    LevelAcc* acc;                    // spread groups [slot][level][kSpread]
-    WorkItem* items;
-    unsigned* head;                   // dispenser of the items past the first gridDim.x
-    unsigned* count;                  // number of items
-    unsigned resident_blocks;         // grid size of the sampler
-    unsigned chunk;                   // blockDim * PPT of the sampler
-    unsigned block;                   // blockDim of the sampler
-    unsigned* split;                  // lanes per path per (slot, level), set by the plan
-    int split_ok;                     // the model's paths are linear in their start (GBM)
-    int num_cu;
-};
-
 // Plan: the first wave sizes the (slot, level) pairs, one lane each, in
 // processing order (deepest level first, then slot), so the independent
 // global reads and the 64-bit divisions run side by side; a wave scan gives
-// each pair its first item, and the block then writes the items in parallel.
-// Every thread of the block must call it.
+// each pair its first item, and each lane writes its pair's row of the plan
+// table (the sampler decodes the items from it).  Only the first wave works;
+// every thread of the block may call it.
 __device__ __forceinline__ void plan_body(const BatchDesc* d)
 {
-    constexpr int kPairs = kMaxSlots * kMaxLevels;
     static_assert(kPairs == 64, "one lane of the first wave per (slot, level) pair");
-    __shared__ uint64_t s_first[kPairs], s_left[kPairs], s_per[kPairs];
-    __shared__ unsigned s_start[kPairs + 1];
-    __shared__ int s_slot[kPairs], s_level[kPairs];
-    __shared__ int s_npairs;
-    if (threadIdx.x < 64) {
-        const int L = d->L, M = d->M, nslots = d->nslots;
-        const int p = (int)threadIdx.x;
-        const bool valid = p < (L + 1) * nslots;
-        const int l = valid ? L - p / nslots : 0, s = valid ? p % nslots : 0;
-        double nf = 1.0;
-        for (int i = 0; i < l; ++i) nf *= M;   // M^l, exact
-        const double per = nf + (l ? nf / M : 0.0);
-        const double dn = valid ? d->dN[s * kMaxLevels + l] : 0.0;
-        // samples x steps over the batch (lane 0's sum: the rotations leave
-        // other lanes with other association orders)
-        const double total = __shfl(wave_sum(valid ? dn * per : 0.0), 0);
-        const double target = total / ((double)d->resident_blocks * kItemsPerBlock);
-        const uint64_t left = (uint64_t)dn;
-        unsigned items = 0;
-        uint64_t per_item = 0;
-        if (valid) {
-            // lanes per path: the per-level launch's rule on the same count
-            const uint32_t G = split_lanes((int)nf, left, d->num_cu,
-                                           d->split_ok && d->payoff_kind[s] != kDigitalCond);
-            d->split[s * kMaxLevels + l] = G;
-            if (left) {
-                uint64_t paths = (uint64_t)(target / per);
-                if (G > 1) {
-                    // split paths: whole block passes of block / G paths
-                    const uint64_t pass = d->block / G;
-                    paths = paths < pass ? pass : (paths / pass) * pass;
-                } else if (paths >= d->chunk) {
-                    paths = (paths / d->chunk) * d->chunk;   // whole chunks where possible
-                } else if (paths < d->block) {
-                    paths = d->block;                        // one sample per lane at least
-                }
-                if (paths > (1ull << 31)) paths = 1ull << 31;   // item counts fit 32 bits
-                // at most kItemsPerPair items per pair: the table never fills
-                const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
-                per_item = paths > min_items ? paths : min_items;
-                items = (unsigned)((left + per_item - 1) / per_item);
+    if (threadIdx.x >= 64) return;
+    const int L = d->L, M = d->M, nslots = d->nslots;
+    const int p = (int)threadIdx.x;
+    const bool valid = p < (L + 1) * nslots;
+    const int l = valid ? L - p / nslots : 0, s = valid ? p % nslots : 0;
+    double nf = 1.0;
+    for (int i = 0; i < l; ++i) nf *= M;   // M^l, exact
+    const double per = nf + (l ? nf / M : 0.0);
+    const double dn = valid ? d->dN[s * kMaxLevels + l] : 0.0;
+    // samples x steps over the batch (lane 0's sum: the rotations leave
+    // other lanes with other association orders)
+    const double total = __shfl(wave_sum(valid ? dn * per : 0.0), 0);
+    const double target = total / ((double)d->resident_blocks * kItemsPerBlock);
+    const uint64_t left = (uint64_t)dn;
+    unsigned items = 0;
+    uint64_t per_item = 0;
+    if (valid) {
+        // lanes per path: the per-level launch's rule on the same count
+        const uint32_t G = split_lanes((int)nf, left, d->num_cu,
+                                       d->split_ok && d->payoff_kind[s] != kDigitalCond);
+        d->split[s * kMaxLevels + l] = G;
+        if (left) {
+            uint64_t paths = (uint64_t)(target / per);
+            if (G > 1) {
+                // split paths: whole block passes of block / G paths
+                const uint64_t pass = d->block / G;
+                paths = paths < pass ? pass : (paths / pass) * pass;
+            } else if (paths >= d->chunk) {
+                paths = (paths / d->chunk) * d->chunk;   // whole chunks where possible
+            } else if (paths < d->block) {
+                paths = d->block;                        // one sample per lane at least
             }
-        }
-        // exclusive scan of the item counts over the lanes (pair order)
-        unsigned incl = items;
-#pragma unroll
-        for (int k = 1; k < 64; k <<= 1) {
-            const unsigned v = __shfl_up(incl, k);
-            if (p >= k) incl += v;
-        }
-        // pairs with samples, packed in order
-        const uint64_t active = __ballot(items > 0);
-        const int rank = __popcll(active & ((1ull << p) - 1ull));
-        if (items) {
-            s_first[rank] = (uint64_t)d->offset[s * kMaxLevels + l];
-            s_left[rank] = left;
-            s_per[rank] = per_item;
-            s_slot[rank] = s;
-            s_level[rank] = l;
-            s_start[rank] = incl - items;
-        }
-        if (p == 63) {
-            const int np = __popcll(active);
-            s_start[np] = incl;
-            s_npairs = np;
-            *d->count = incl;
-            *d->head = 0;
+            if (paths > (1ull << 31)) paths = 1ull << 31;   // item sizes fit 32 bits
+            // at most kItemsPerPair items per pair: item indices stay small
+            const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
+            per_item = paths > min_items ? paths : min_items;
+            items = (unsigned)((left + per_item - 1) / per_item);
         }
     }
-    __syncthreads();
-    const int np = s_npairs;
-    const unsigned count = s_start[np];
-    for (unsigned k = threadIdx.x; k < count; k += blockDim.x) {
-        int q = 0;
-        while (q + 1 < np && s_start[q + 1] <= k) ++q;
-        const uint64_t i = k - s_start[q];
-        const uint64_t done = i * s_per[q];
-        const uint64_t n = s_left[q] - done < s_per[q] ? s_left[q] - done : s_per[q];
-        WorkItem w;
-        w.first = s_first[q] + done;
-        w.n = (uint32_t)n;
-        w.level = (uint16_t)s_level[q];
-        w.slot = (uint8_t)s_slot[q];
-        w.pad = 0;
-        d->items[k] = w;
+    // inclusive scan of the item counts over the lanes (pair order)
+    unsigned incl = items;
+#pragma unroll
+    for (int k = 1; k < 64; k <<= 1) {
+        const unsigned v = __shfl_up(incl, k);
+        if (p >= k) incl += v;
+    }
+    // pairs with samples, packed in order
+    const uint64_t active = __ballot(items > 0);
+    const int rank = __popcll(active & ((1ull << p) - 1ull));
+    PlanTable* t = d->plan;
+    if (items) {
+        t->first[rank] = (uint64_t)d->offset[s * kMaxLevels + l];
+        t->left[rank] = left;
+        t->per[rank] = per_item;
+        t->slot[rank] = (uint8_t)s;
+        t->level[rank] = (uint8_t)l;
+        t->start[rank] = incl - items;
+    }
+    if (p == 63) {
+        const int np = __popcll(active);
+        t->start[np] = incl;
+        t->npairs = np;
+        *d->head = 0;
     }
 }
 
 __global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d) { plan_body(d); }
+
+// The adaptive run's first kernel: the spread groups cleared, a fresh state
+// (n_pilot samples outstanding on levels 0..L_min), the run's seed into the
+// descriptor, and the pilot batch planned.  The plan reads the state's dN and
+// n, which this block has just written (a barrier orders them).
+__global__ __launch_bounds__(256) void driver_start_kernel(DriverState* st, LevelAcc* spread,
+                                                           DriverInit c, BatchDesc* d, uint64_t seed)
+{
+    unsigned long long* g = (unsigned long long*)spread;
+    constexpr int kSpreadWords = kMaxLevels * kSpread * (int)sizeof(LevelAcc) / 8;
+    for (int i = threadIdx.x; i < kSpreadWords; i += blockDim.x) g[i] = 0ull;
+    init_state(*st, c);
+    if (threadIdx.x == 0) d->seed = seed;
+    __syncthreads();
+    plan_body(d);
+}
+
+// One iteration's end: fold the spread groups, absorb the batch, re-plan
+// (driver_update_block), then plan the next batch's items.  The host reads
+// the update count every iteration and the state once, at the end: the
+// mirror is written whole by the finishing update only.  A finished state
+// has no outstanding samples, so its plan is empty and a sampler launched
+// after it does nothing.
+__global__ __launch_bounds__(512) void driver_update_plan_kernel(DriverState* st, DriverState* mirror,
+                                                                 LevelAcc* spread, const BatchDesc* d)
+{
+    __shared__ DriverState s;
+    driver_update_block(st, mirror, s, spread, nullptr, false);
+    __syncthreads();
+    plan_body(d);
+}
 
 // Fold each spread group (kSpread records) into one record, group g by
 // block g, in record order; clears the groups for the next replay.
@@ -181,151 +159,36 @@ __global__ __launch_bounds__(64) void fold_groups_kernel(LevelAcc* groups, Level
     }
 }
 
-// The samples [a.offset, a.offset + a.N) of one item part (a.c2, a.c2b set).
-template <int MODEL, int PAYOFF, int M, int PPT>
-__device__ __forceinline__ void run_range(const LevelArgs<float>& a, double (&sums)[kNumSums],
-                                          unsigned& nonfinite)
+extern template PersistentFn pick_persistent_variant<kGBM>(int, int, int);
+extern template PersistentFn pick_persistent_variant<kGBMMil>(int, int, int);
+extern template PersistentFn pick_persistent_variant<kHeston>(int, int, int);
+
+// variant: sampler_variant() of the model (GBM Euler, GBM Milstein, Heston);
+// payoff: the kind every slot holds, or kAnyPayoff.
+static PersistentFn pick_persistent(int variant, int M, int ppt, int payoff)
 {
-    if constexpr (MODEL != kHeston && PAYOFF != kDigitalCond) {
-        if (a.split > 1) {
-            const uint64_t pass = blockDim.x / a.split;
-            for (uint64_t base = 0; base < a.N; base += pass)
-                process_split<MODEL, PAYOFF, M>(a, base, sums, nonfinite);
-            return;
-        }
-    }
-    if (a.nf < 4) {
-        // one or two steps: samples share generator blocks
-        constexpr int D = one_factor(MODEL) ? 1 : 2;
-        const int q = 4 / (a.nf * D);
-        const uint64_t nblk = short_blocks(a.offset, a.N, q);
-        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
-        const FullChunks f = full_chunks(a.offset, a.N, q, chunk);
-        const uint32_t lo = __builtin_amdgcn_readfirstlane(f.lo), hi = __builtin_amdgcn_readfirstlane(f.hi);
-        // one counter segment: chunk indices fit 32 bits (a scalar loop test)
-        const uint32_t nch = __builtin_amdgcn_readfirstlane((uint32_t)((nblk + chunk - 1) / chunk));
-        for (uint32_t c = 0; c < nch; ++c) {
-            const uint64_t base = (uint64_t)c * chunk;
-            const bool full = c >= lo && c < hi;
-            if (a.nf == 1) process_short<MODEL, PAYOFF, float, 1, M, PPT, false>(a, base, full, sums, nonfinite);
-            else process_short<MODEL, PAYOFF, float, 2, M, PPT, false>(a, base, full, sums, nonfinite);
-        }
-    } else if (a.N <= blockDim.x) {
-        // fewer samples than lanes: one per lane
-        process_chunk<MODEL, PAYOFF, float, M, 1, false>(a, 0, sums, nonfinite);
-    } else {
-        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
-        for (uint64_t base = 0; base < a.N; base += chunk)
-            process_chunk<MODEL, PAYOFF, float, M, PPT, false>(a, base, sums, nonfinite);
-    }
+    if (variant == kGBM) return pick_persistent_variant<kGBM>(M, ppt, payoff);
+    if (variant == kGBMMil) return pick_persistent_variant<kGBMMil>(M, ppt, payoff);
+    return pick_persistent_variant<kHeston>(M, ppt, payoff);
 }
-
-template <int MODEL, int PAYOFF, int M, int PPT>
-__device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[kNumSums],
-                         unsigned& nonfinite)
-{
-    LevelArgs<float> a;
-    a.P = d->params[w.slot][w.level];
-    a.seed = d->seed;
-    a.l = w.level;
-    int nf = 1;
-    for (int i = 0; i < a.l; ++i) nf *= M;
-    a.nf = nf;
-    a.ngroups = (uint32_t)((nf + 3) / 4);
-    a.stream = kStreamNormal;
-    a.acc = nullptr;
-    a.pf_out = a.pc_out = nullptr;
-    a.coupled = 1;
-    a.phi0 = nullptr;
-    a.split = d->split[w.slot * kMaxLevels + w.level];
-    constexpr int D = one_factor(MODEL) ? 1 : 2;
-    // one pass per part of the item whose generator units share counter word 2
-    const uint64_t q = samples_per_unit(nf, D), end = w.first + w.n;
-    for (uint64_t first = w.first; first < end;) {
-        const uint64_t stop = counter_segment_end(first, end, q);
-        a.offset = first;
-        a.N = stop - first;
-        set_counter_words(a, D);
-        run_range<MODEL, PAYOFF, M, PPT>(a, sums, nonfinite);
-        first = stop;
-    }
-}
-
-// Block b takes item b first; later items come from the dispenser until
-// none are left, so a launch with no more items than blocks (an empty one
-// included) makes no atomics on it.  Each item ends with a block reduction
-// into its (payoff, level) spread group.
-template <int MODEL, int M, int PPT>
-__device__ __forceinline__ void sample_items(const BatchDesc* d)
-{
-    __shared__ unsigned s_item;
-    const unsigned count = *d->count;
-    for (unsigned it = blockIdx.x; it < count;) {   // block-uniform
-        const WorkItem w = d->items[it];
-        double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
-        unsigned nonfinite = 0;
-        switch (d->payoff_kind[w.slot]) {
-        case kCall: run_item<MODEL, kCall, M, PPT>(d, w, sums, nonfinite); break;
-        case kAsian: run_item<MODEL, kAsian, M, PPT>(d, w, sums, nonfinite); break;
-        case kLookback: run_item<MODEL, kLookback, M, PPT>(d, w, sums, nonfinite); break;
-        case kDigitalCond: run_item<MODEL, kDigitalCond, M, PPT>(d, w, sums, nonfinite); break;
-        default: run_item<MODEL, kDigital, M, PPT>(d, w, sums, nonfinite); break;
-        }
-        if (w.level == 0) copy_y_sums(sums);
-        block_reduce_add(sums, nonfinite, &d->acc[(w.slot * kMaxLevels + w.level) * kSpread +
-                                                  (blockIdx.x & (kSpread - 1))]);
-        if (count <= gridDim.x) break;
-        if (threadIdx.x == 0) s_item = gridDim.x + atomicAdd(d->head, 1u);
-        __syncthreads();
-        it = s_item;
-        __syncthreads();
-    }
-}
-
-template <int MODEL, int M, int PPT>
-__global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
-{
-    sample_items<MODEL, M, PPT>(d);
-}
-
-using PersistentFn = void (*)(const BatchDesc*);
-
-template <int MODEL, int M>
-static PersistentFn pick_ppt(int ppt)
-{
-    switch (ppt) {
-    case 1: return persistent_kernel<MODEL, M, 1>;
-    case 2: return persistent_kernel<MODEL, M, 2>;
-    default: return persistent_kernel<MODEL, M, 4>;
-    }
-}
-
-// variant: sampler_variant() of the model (GBM Euler, GBM Milstein, Heston)
-static PersistentFn pick_persistent(int variant, int M, int ppt)
-{
-    if (variant == kGBM) return M == 2 ? pick_ppt<kGBM, 2>(ppt) : pick_ppt<kGBM, 4>(ppt);
-    if (variant == kGBMMil) return M == 2 ? pick_ppt<kGBMMil, 2>(ppt) : pick_ppt<kGBMMil, 4>(ppt);
-    return M == 2 ? pick_ppt<kHeston, 2>(ppt) : pick_ppt<kHeston, 4>(ppt);
-}
-
 
 // Device buffers of the persistent form, owned by the context.
 struct PersistentBufs {
     BatchDesc* d_desc = nullptr;
     BatchDesc* h_desc = nullptr;
-    WorkItem* d_items = nullptr;
-    unsigned* d_counters = nullptr;   // head, count
+    PlanTable* d_plan = nullptr;
+    unsigned* d_counters = nullptr;   // head
     LevelAcc* d_acc = nullptr;        // batch spread groups [kMaxSlots][kMaxLevels][kSpread]
     LevelAcc* d_rec = nullptr;        // their folds [kMaxSlots][kMaxLevels]
     unsigned* d_split = nullptr;      // lanes per path [kMaxSlots][kMaxLevels]
     double* d_req = nullptr;          // dN[kMaxSlots][kMaxLevels], offset[...]
     double* h_req = nullptr;
     hipGraphExec_t graph = nullptr;   // cached batch graph
-    int graph_key[5] = {-1, -1, -1, -1, -1};
-    hipGraphExec_t run_graph = nullptr;   // cached driver-iteration graph
-    int run_key[5] = {-1, -1, -1, -1, -1};
+    int graph_key[6] = {-1, -1, -1, -1, -1, -1};
     BatchDesc last_desc;              // the bytes of the last descriptor upload
-    bool last_ok = false;
+    // 0: unknown; 1: the device descriptor holds last_desc; 2: it does but for
+    // its seed (the adaptive run's start kernel writes the seed)
+    int desc_state = 0;
 };
 
 static PersistentBufs* bufs_of(mlmc_ctx* ctx);
@@ -351,7 +214,7 @@ static mlmc_status ensure_bufs(mlmc_ctx* ctx)
     ctx->persist = b;
     hipError_t e = hipMalloc(&b->d_desc, sizeof(BatchDesc));
     if (e == hipSuccess) e = hipHostMalloc(&b->h_desc, sizeof(BatchDesc));
-    if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(WorkItem) * kMaxItems);
+    if (e == hipSuccess) e = hipMalloc(&b->d_plan, sizeof(PlanTable));
     if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(unsigned) * 4);
     if (e == hipSuccess)
         e = hipMalloc(&b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels * kSpread);
@@ -375,10 +238,9 @@ void free_persistent(mlmc_ctx* ctx)
     auto* b = bufs_of(ctx);
     if (!b) return;
     if (b->graph) hipGraphExecDestroy(b->graph);
-    if (b->run_graph) hipGraphExecDestroy(b->run_graph);
     if (b->d_desc) hipFree(b->d_desc);
     if (b->h_desc) hipHostFree(b->h_desc);
-    if (b->d_items) hipFree(b->d_items);
+    if (b->d_plan) hipFree(b->d_plan);
     if (b->d_counters) hipFree(b->d_counters);
     if (b->d_acc) hipFree(b->d_acc);
     if (b->d_rec) hipFree(b->d_rec);
@@ -408,9 +270,8 @@ static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const ml
     h->dN = dN;
     h->offset = off;
     h->acc = acc;
-    h->items = b->d_items;
+    h->plan = b->d_plan;
     h->head = b->d_counters;
-    h->count = b->d_counters + 1;
     h->resident_blocks = (unsigned)(ctx->num_cu * s.blocks_per_cu);
     h->chunk = (unsigned)(s.block * s.ppt);
     h->split = b->d_split;
@@ -421,21 +282,24 @@ static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const ml
 
 // Copy the host descriptor to the device unless the last upload from this
 // context carried the same bytes (repeated runs of one problem skip it).
-static mlmc_status upload_desc(mlmc_ctx* ctx, PersistentBufs* b)
+// any_seed: the caller sets the seed on the device itself, so a device copy
+// that differs in its seed only is as good.
+static mlmc_status upload_desc(mlmc_ctx* ctx, PersistentBufs* b, bool any_seed)
 {
-    if (b->last_ok && std::memcmp(&b->last_desc, b->h_desc, sizeof(BatchDesc)) == 0)
+    if (b->desc_state != 0 && (b->desc_state == 1 || any_seed) &&
+        std::memcmp(&b->last_desc, b->h_desc, sizeof(BatchDesc)) == 0)
         return MLMC_OK;
-    b->last_ok = false;
+    b->desc_state = 0;
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
                                  ctx->stream));
     std::memcpy(&b->last_desc, b->h_desc, sizeof(BatchDesc));
-    b->last_ok = true;
+    b->desc_state = 1;
     return MLMC_OK;
 }
 
-// Capture [prologue?] -> plan -> persistent -> [epilogue] into a graph.
-static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
-                           DriverState* driver, hipGraphExec_t* out)
+// Capture zero -> plan -> persistent -> fold into a graph (payoff: the kind
+// of every slot, or kAnyPayoff).
+static mlmc_status capture(mlmc_ctx* ctx, int model, int M, int payoff, hipGraphExec_t* out)
 {
     auto* b = bufs_of(ctx);
     const PersistentShape s = persistent_shape(ctx);
@@ -443,24 +307,21 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
     MLMC_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess && zero_batch)
-        e = zero_records(b->d_acc, kMaxSlots * kMaxLevels * kSpread, cs);
+    if (e == hipSuccess) e = zero_records(b->d_acc, kMaxSlots * kMaxLevels * kSpread, cs);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, cs, (const BatchDesc*)b->d_desc);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(pick_persistent(model, M, s.ppt), dim3(ctx->num_cu * s.blocks_per_cu),
+        hipLaunchKernelGGL(pick_persistent(model, M, s.ppt, payoff), dim3(ctx->num_cu * s.blocks_per_cu),
                            dim3(s.block), 0, cs, (const BatchDesc*)b->d_desc);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && zero_batch) {
+    if (e == hipSuccess) {
         hipLaunchKernelGGL(fold_groups_kernel, dim3(kMaxSlots * kMaxLevels), dim3(kSpread), 0, cs,
                            b->d_acc, b->d_rec);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && driver)
-        e = launch_driver_update(driver, (DriverState*)ctx->h_drv_dev, ctx->d_drv_spread, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -470,65 +331,77 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, bool zero_batch,
     return MLMC_OK;
 }
 
-// mlmc_run with persistent = 1: one graph launch per driver iteration.
+// mlmc_run with persistent = 1: the start kernel (fresh state, pilot plan),
+// then per driver iteration the all-levels sampler and the update-and-plan
+// block, as plain launches on the context's stream.
 mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p,
-                           const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st)
+                           const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st,
+                           const DriverInit& init)
 {
     if (o.precision != 32) return fail(ctx, MLMC_EINVAL, "the persistent form runs fp32 paths");
     if (o.cv) return fail(ctx, MLMC_EINVAL, "the persistent form runs plain MLMC");
     mlmc_status st = ensure_bufs(ctx);
     if (st) return st;
     auto* b = bufs_of(ctx);
-    fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, o.seed, d_st->dN, d_st->n,
-              ctx->d_drv_spread);
-    st = upload_desc(ctx, b);
+    // the seed goes in with the start kernel: runs of one problem share the
+    // descriptor's bytes and upload it once
+    fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, 0, d_st->dN, d_st->n, ctx->d_drv_spread);
+    st = upload_desc(ctx, b, true);
     if (st) return st;
-    // the graph reads the descriptor, the driver state and its mirror at
-    // replay, all fixed per context: one capture serves every run
     const PersistentShape s = persistent_shape(ctx);
-    const int key[5] = {sampler_variant(m), o.M, s.block, s.ppt, s.blocks_per_cu};
-    if (!b->run_graph || std::memcmp(key, b->run_key, sizeof(key)) != 0) {
-        // an earlier run may return with its last (empty) launch queued
-        MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        if (b->run_graph) hipGraphExecDestroy(b->run_graph);
-        b->run_graph = nullptr;
-        st = capture(ctx, sampler_variant(m), o.M, false, d_st, &b->run_graph);
-        if (st) return st;
-        std::memcpy(b->run_key, key, sizeof(key));
-    }
-    hipGraphExec_t g = b->run_graph;
+    const auto sampler = pick_persistent(sampler_variant(m), o.M, s.ppt, p.kind);
+    const dim3 grid(ctx->num_cu * s.blocks_per_cu), block(s.block);
+    const BatchDesc* d = b->d_desc;
+    DriverState* mirror = (DriverState*)ctx->h_drv_dev;
+    hipLaunchKernelGGL(driver_start_kernel, dim3(1), dim3(256), 0, ctx->stream, d_st,
+                       ctx->d_drv_spread, init, b->d_desc, o.seed);
+    MLMC_HIP(ctx, hipGetLastError());
+    b->desc_state = 2;   // the device copy now carries this run's seed
     // Iteration k + 1 is enqueued before the host waits for iteration k's
-    // update: its plan reads the batch that update set from the device
-    // state, so the GPU runs the iterations back to back while the host reads
-    // the mirror.  The one launch past the last update finds the driver done
-    // and does nothing (no outstanding batch; the update leaves the state).
+    // update: its sampler reads the items that update planned, so the GPU
+    // runs the iterations back to back while the host reads the mirror.  The
+    // one iteration past the last update finds an empty plan and a finished
+    // state and does nothing.
     int first_tix = -1;
     for (int it = 0;; ++it) {
         if (it > h_st->max_iterations + 1)
             return fail(ctx, MLMC_EDEVICE, "driver state did not reach the host");
-        const TraceRange iter_range("mlmc_run driver iteration (graph)");
+        const TraceRange iter_range("mlmc_run driver iteration (device-planned)");
         for (int k = it ? 1 : 0; k < 2; ++k) {
-            const int tix = timed_begin(ctx, 16, 0.0, 0.0);
-            if (first_tix < 0) first_tix = tix;
-            const hipError_t e = hipGraphLaunch(g, ctx->stream);
-            timed_end(ctx, tix);
+            // the sampler stamps slot 16, the update-and-plan block slot 17
+            hipEvent_t t0, t1;
+            timed_kernel(ctx, 16, 0.0, 0.0, &t0, &t1);
+            if (first_tix < 0 && t0) first_tix = (int)ctx->pending.size() - 1;
+            if (t0) hipExtLaunchKernelGGL(sampler, grid, block, 0, ctx->stream, t0, t1, 0, d);
+            else hipLaunchKernelGGL(sampler, grid, block, 0, ctx->stream, d);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess) {
+                timed_kernel(ctx, 17, 0.0, 0.0, &t0, &t1);
+                if (t0)
+                    hipExtLaunchKernelGGL(driver_update_plan_kernel, dim3(1), dim3(512), 0, ctx->stream,
+                                          t0, t1, 0, d_st, mirror, ctx->d_drv_spread, d);
+                else
+                    hipLaunchKernelGGL(driver_update_plan_kernel, dim3(1), dim3(512), 0, ctx->stream,
+                                       d_st, mirror, ctx->d_drv_spread, d);
+                e = hipGetLastError();
+            }
             if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
         }
-        // the update kernel inside the graph also writes the host mirror h_st
+        // the update kernel also writes the host mirror h_st
         const hipError_t e = wait_update(ctx->stream, h_st, (unsigned long long)it + 1);
         if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
         // the flag comes in the word that publishes the update, so a mirror
         // seen done is complete; later updates leave it as it is
         if (mirror_done(h_st)) break;
     }
-    // the launch past the last update may still run: the result is read from
-    // the mirror, and the stream is waited for only to read timing events
+    // the iteration past the last update may still run: the result is read
+    // from the mirror; stamped launches are read once finished (harvest_ready
+    // now, the rest by a later harvest), the run does not wait for them
     if (ctx->pending.empty()) return MLMC_OK;
-    const hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "persistent iteration");
     if (first_tix >= 0) {
         // the launches' path steps are known only as a whole: every sampled
-        // batch is absorbed into n_l, so they are charged to the first entry
+        // batch is absorbed into n_l, so they are charged to the run's first
+        // stamped sampler launch
         double fine = 0.0, coarse = 0.0;
         for (int l = 0; l <= h_st->L; ++l) {
             const double nf = std::pow((double)o.M, (double)l);
@@ -538,7 +411,7 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
         ctx->pending[first_tix].fine_steps = fine;
         ctx->pending[first_tix].coarse_steps = coarse;
     }
-    harvest_timing(ctx);
+    harvest_ready(ctx);
     return MLMC_OK;
 }
 
@@ -568,9 +441,8 @@ mlmc_status mlmc_set_persistent_launch(mlmc_ctx* ctx, int block, int ppt, int bl
         MLMC_HIP(ctx, hipSetDevice(ctx->device));
         MLMC_HIP(ctx, hipStreamSynchronize(ctx->stream));
         if (b->graph) hipGraphExecDestroy(b->graph);
-        if (b->run_graph) hipGraphExecDestroy(b->run_graph);
-        b->graph = b->run_graph = nullptr;
-        b->graph_key[0] = b->run_key[0] = -1;
+        b->graph = nullptr;
+        b->graph_key[0] = -1;
     }
     return MLMC_OK;
 }
@@ -611,14 +483,18 @@ mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc
               b->d_req + kMaxSlots * kMaxLevels, b->d_acc);
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_req, b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels,
                                  hipMemcpyHostToDevice, ctx->stream));
-    st = upload_desc(ctx, b);
+    st = upload_desc(ctx, b, false);
     if (st) return st;
     const PersistentShape s = persistent_shape(ctx);
-    const int key[5] = {sampler_variant(*model), M, s.block, s.ppt, s.blocks_per_cu};
+    // one payoff kind in every slot: the kernel holds that payoff's code only
+    int payoff = payoffs[0].kind;
+    for (int k = 1; k < npayoffs; ++k)
+        if (payoffs[k].kind != payoff) payoff = kAnyPayoff;
+    const int key[6] = {sampler_variant(*model), M, s.block, s.ppt, s.blocks_per_cu, payoff};
     if (!b->graph || std::memcmp(key, b->graph_key, sizeof(key)) != 0) {
         if (b->graph) hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
-        st = capture(ctx, sampler_variant(*model), M, true, nullptr, &b->graph);
+        st = capture(ctx, sampler_variant(*model), M, payoff, &b->graph);
         if (st) return st;
         std::memcpy(b->graph_key, key, sizeof(key));
     }

@@ -1,0 +1,253 @@
+// Persistent all-levels sampler: the batch descriptor, the work items and
+// the sampler kernel (its plan and host side are in persistent.hip).  The
+// kernel is instantiated per model variant in persistent_<variant>.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "driver.hpp"
+#include "level.hpp"
+#include "sampler_impl.hpp"
+
+namespace mlmc {
+
+constexpr int kMaxSlots = 4;          // payoffs per batch
+constexpr int kPairs = kMaxSlots * kMaxLevels;
+constexpr int kItemsPerBlock = 4;     // target items per resident block
+constexpr unsigned kItemsPerPair = 1024;
+
+struct WorkItem {
+    uint64_t first;     // first sample index of the range
+    uint32_t n;         // number of samples
+    uint16_t level;
+    uint8_t slot;       // payoff slot
+    uint8_t pad;
+};
+
+// The plan of one launch: the (slot, level) pairs with outstanding samples,
+// in processing order; pair q owns items start[q] .. start[q+1] - 1, which
+// cut [first[q], first[q] + left[q]) into pieces of per[q] samples (the last
+// one shorter).  Items are decoded from it by the sampler, not stored.
+struct PlanTable {
+    uint64_t first[kPairs], left[kPairs], per[kPairs];
+    unsigned start[kPairs + 1];
+    int npairs;
+    uint8_t slot[kPairs], level[kPairs];
+    uint32_t pad[1];
+};
+static_assert(sizeof(PlanTable) % 8 == 0, "copied in 8-byte words");
+
+// Device-resident batch description (rewritten before each launch).
+struct BatchDesc {
+    int nslots, L, M, pad;
+    int payoff_kind[kMaxSlots];
+    StepParams<float> params[kMaxSlots][kMaxLevels];
+    uint64_t seed;
+    // outstanding samples and their first index, per (slot, level); for the
+    // driver these alias DriverState::dN / n (slot 0 only)
+    const double* dN;
+    const double* offset;
+    LevelAcc* acc;                    // spread groups [slot][level][kSpread]
+    PlanTable* plan;                  // written by the plan, read by the sampler
+    unsigned* head;                   // dispenser of the items past the first gridDim.x
+    unsigned resident_blocks;         // grid size of the sampler
+    unsigned chunk;                   // blockDim * PPT of the sampler
+    unsigned block;                   // blockDim of the sampler
+    unsigned* split;                  // lanes per path per (slot, level), set by the plan
+    int split_ok;                     // the model's paths are linear in their start (GBM)
+    int num_cu;
+};
+
+// A batch whose slots may hold different payoff kinds.
+constexpr int kAnyPayoff = -1;
+
+// The samples [a.offset, a.offset + a.N) of one item part (a.c2, a.c2b set).
+template <int MODEL, int PAYOFF, int M, int PPT>
+__device__ __forceinline__ void run_range(const LevelArgs<float>& a, double (&sums)[kNumSums],
+                                          unsigned& nonfinite)
+{
+    if constexpr (MODEL != kHeston && PAYOFF != kDigitalCond) {
+        if (a.split > 1) {
+            const uint64_t pass = blockDim.x / a.split;
+            for (uint64_t base = 0; base < a.N; base += pass)
+                process_split<MODEL, PAYOFF, M>(a, base, sums, nonfinite);
+            return;
+        }
+    }
+    if (a.nf < 4) {
+        // one or two steps: samples share generator blocks (two-step levels
+        // exist for M = 2 only: the other code is not compiled for M = 4)
+        constexpr int D = one_factor(MODEL) ? 1 : 2;
+        const int q = M == 2 ? 4 / (a.nf * D) : 4 / D;
+        const uint64_t nblk = short_blocks(a.offset, a.N, q);
+        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
+        const FullChunks f = full_chunks(a.offset, a.N, q, chunk);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(f.lo), hi = __builtin_amdgcn_readfirstlane(f.hi);
+        // one counter segment: chunk indices fit 32 bits (a scalar loop test)
+        const uint32_t nch = __builtin_amdgcn_readfirstlane((uint32_t)((nblk + chunk - 1) / chunk));
+        for (uint32_t c = 0; c < nch; ++c) {
+            const uint64_t base = (uint64_t)c * chunk;
+            const bool full = c >= lo && c < hi;
+            if (M != 2 || a.nf == 1)
+                process_short<MODEL, PAYOFF, float, 1, M, PPT, false>(a, base, full, sums, nonfinite);
+            else
+                process_short<MODEL, PAYOFF, float, 2, M, PPT, false>(a, base, full, sums, nonfinite);
+        }
+    } else if (a.N <= blockDim.x) {
+        // fewer samples than lanes: one per lane
+        process_chunk<MODEL, PAYOFF, float, M, 1, false>(a, 0, sums, nonfinite);
+    } else {
+        const uint64_t chunk = (uint64_t)blockDim.x * PPT;
+        for (uint64_t base = 0; base < a.N; base += chunk)
+            process_chunk<MODEL, PAYOFF, float, M, PPT, false>(a, base, sums, nonfinite);
+    }
+}
+
+// A copy of v that the compiler knows to be the same in every lane (it
+// must be): each 32-bit word read from the first active lane, so the item
+// and its parameters live in scalar registers, as a launch's arguments do.
+template <typename T>
+__device__ __forceinline__ T wave_uniform(const T& v)
+{
+    static_assert(sizeof(T) % 4 == 0, "copied in 32-bit words");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
+template <int MODEL, int PAYOFF, int M, int PPT>
+__device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[kNumSums],
+                         unsigned& nonfinite)
+{
+    LevelArgs<float> a;
+    a.P = wave_uniform(d->params[w.slot][w.level]);
+    a.seed = wave_uniform(d->seed);
+    a.l = w.level;
+    int nf = 1;
+    for (int i = 0; i < a.l; ++i) nf *= M;
+    a.nf = nf;
+    a.ngroups = (uint32_t)((nf + 3) / 4);
+    a.stream = kStreamNormal;
+    a.acc = nullptr;
+    a.pf_out = a.pc_out = nullptr;
+    a.coupled = 1;
+    a.phi0 = nullptr;
+    a.split = __builtin_amdgcn_readfirstlane(d->split[w.slot * kMaxLevels + w.level]);
+    constexpr int D = one_factor(MODEL) ? 1 : 2;
+    // one pass per part of the item whose generator units share counter word 2
+    const uint64_t q = samples_per_unit(nf, D), end = w.first + w.n;
+    for (uint64_t first = w.first; first < end;) {
+        const uint64_t stop = counter_segment_end(first, end, q);
+        a.offset = first;
+        a.N = stop - first;
+        set_counter_words(a, D);
+        run_range<MODEL, PAYOFF, M, PPT>(a, sums, nonfinite);
+        first = stop;
+    }
+}
+
+// Block b takes item b first; later items come from the dispenser until
+// none are left, so a launch with no more items than blocks (an empty one
+// included) makes no atomics on it.  Each item ends with a block reduction
+// into its (payoff, level) spread group.
+// Item `it` of the plan (block-uniform).
+__device__ __forceinline__ WorkItem plan_item(const PlanTable& t, unsigned it)
+{
+    int q = 0;
+    while (q + 1 < t.npairs && t.start[q + 1] <= it) ++q;
+    const uint64_t done = (uint64_t)(it - t.start[q]) * t.per[q];
+    const uint64_t rest = t.left[q] - done;
+    WorkItem w;
+    w.first = t.first[q] + done;
+    w.n = (uint32_t)(rest < t.per[q] ? rest : t.per[q]);
+    w.level = t.level[q];
+    w.slot = t.slot[q];
+    w.pad = 0;
+    return w;
+}
+
+template <int MODEL, int M, int PPT, int PAYOFF>
+__device__ __forceinline__ void sample_items(const BatchDesc* d)
+{
+    __shared__ unsigned s_item;
+    // the plan in LDS: each item is decoded by a short search over its pairs
+    __shared__ PlanTable s_plan;
+    {
+        const unsigned long long* src = (const unsigned long long*)d->plan;
+        unsigned long long* dst = (unsigned long long*)&s_plan;
+        for (int i = threadIdx.x; i < (int)(sizeof(PlanTable) / 8); i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+    }
+    const unsigned count = __builtin_amdgcn_readfirstlane(s_plan.start[s_plan.npairs]);
+    for (unsigned it = blockIdx.x; it < count;) {   // block-uniform
+        const WorkItem w = wave_uniform(plan_item(s_plan, it));
+        double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+        unsigned nonfinite = 0;
+        if constexpr (PAYOFF == kAnyPayoff) {
+            switch (d->payoff_kind[w.slot]) {
+            case kCall: run_item<MODEL, kCall, M, PPT>(d, w, sums, nonfinite); break;
+            case kAsian: run_item<MODEL, kAsian, M, PPT>(d, w, sums, nonfinite); break;
+            case kLookback: run_item<MODEL, kLookback, M, PPT>(d, w, sums, nonfinite); break;
+            case kDigitalCond: run_item<MODEL, kDigitalCond, M, PPT>(d, w, sums, nonfinite); break;
+            default: run_item<MODEL, kDigital, M, PPT>(d, w, sums, nonfinite); break;
+            }
+        } else {
+            run_item<MODEL, PAYOFF, M, PPT>(d, w, sums, nonfinite);
+        }
+        if (w.level == 0) copy_y_sums(sums);
+        block_reduce_add(sums, nonfinite, &d->acc[(w.slot * kMaxLevels + w.level) * kSpread +
+                                                  (blockIdx.x & (kSpread - 1))]);
+        if (count <= gridDim.x) break;
+        if (threadIdx.x == 0) s_item = gridDim.x + atomicAdd(d->head, 1u);
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+    }
+}
+
+// PAYOFF: one payoff kind for every slot of the batch, or kAnyPayoff (each
+// item's slot names it; the kernel then holds every payoff's code and the
+// registers of the largest).
+template <int MODEL, int M, int PPT, int PAYOFF>
+__global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
+{
+    sample_items<MODEL, M, PPT, PAYOFF>(d);
+}
+
+using PersistentFn = void (*)(const BatchDesc*);
+
+template <int MODEL, int M, int PPT>
+PersistentFn pick_persistent_payoff(int payoff)
+{
+    switch (payoff) {
+    case kCall: return persistent_kernel<MODEL, M, PPT, kCall>;
+    case kAsian: return persistent_kernel<MODEL, M, PPT, kAsian>;
+    case kLookback: return persistent_kernel<MODEL, M, PPT, kLookback>;
+    case kDigital: return persistent_kernel<MODEL, M, PPT, kDigital>;
+    case kDigitalCond: return persistent_kernel<MODEL, M, PPT, kDigitalCond>;
+    default: return persistent_kernel<MODEL, M, PPT, kAnyPayoff>;
+    }
+}
+
+// The sampler of one model variant for (M, samples per lane, payoff kind or
+// kAnyPayoff).  Defined here, instantiated once per variant.
+template <int MODEL>
+PersistentFn pick_persistent_variant(int M, int ppt, int payoff)
+{
+    if (M == 2) {
+        switch (ppt) {
+        case 1: return pick_persistent_payoff<MODEL, 2, 1>(payoff);
+        case 2: return pick_persistent_payoff<MODEL, 2, 2>(payoff);
+        default: return pick_persistent_payoff<MODEL, 2, 4>(payoff);
+        }
+    }
+    switch (ppt) {
+    case 1: return pick_persistent_payoff<MODEL, 4, 1>(payoff);
+    case 2: return pick_persistent_payoff<MODEL, 4, 2>(payoff);
+    default: return pick_persistent_payoff<MODEL, 4, 4>(payoff);
+    }
+}
+}  // namespace mlmc

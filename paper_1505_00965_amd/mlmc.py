@@ -26,7 +26,7 @@ EXPORTED = [
     "mlmc_cv_set_params", "mlmc_cv_loss_grad", "mlmc_cv_train", "mlmc_autotune",
     "mlmc_autotune_persistent",
     "mlmc_tuned_shape", "mlmc_rhee_glynn", "mlmc_set_timing_mask", "mlmc_level_noalloc",
-    "mlmc_cv_set_tabulated", "mlmc_cv_get_table",
+    "mlmc_cv_set_tabulated", "mlmc_cv_get_table", "mlmc_set_timing_stride", "mlmc_autotune_run",
 ]
 STAT_SLOTS = 20
 STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
@@ -154,6 +154,8 @@ def lib():
     L.mlmc_tuned_shape.argtypes = [vp, M_, P_, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.mlmc_set_timing.argtypes = [vp, i32]
     L.mlmc_set_timing_mask.argtypes = [vp, u32]
+    L.mlmc_set_timing_stride.argtypes = [vp, u32]
+    L.mlmc_autotune_run.argtypes = [vp, M_, P_, C.POINTER(RunOpts), C.c_char_p, C.POINTER(i32)]
     L.mlmc_kernel_stats.argtypes = [vp, C.POINTER(KernelStat)]
     L.mlmc_level_noalloc.argtypes = [M_, P_, i32, i32, u64, u64, u64, i32, vp, vp, C.c_char_p,
                                      C.c_size_t]
@@ -256,6 +258,10 @@ class Context:
             mask |= 1 << int(s)
         self._check(self._lib.mlmc_set_timing_mask(self.h, mask))
 
+    def set_timing_stride(self, stride=1):
+        """Time one launch in `stride` of each timed slot."""
+        self._check(self._lib.mlmc_set_timing_stride(self.h, int(stride)))
+
     def kernel_stats(self):
         """Per-slot {launches, ms, fine_steps, coarse_steps} (slots 0..15 = level)."""
         arr = (KernelStat * STAT_SLOTS)()
@@ -273,6 +279,17 @@ class Context:
         shape = (C.c_int * 3)()
         self._check(self._lib.mlmc_autotune_persistent(
             self.h, C.byref(m), P, npay, M, L, cache_path.encode() if cache_path else None, shape))
+        return tuple(shape)
+
+    def autotune_run(self, m, p, eps, M=4, L_min=2, L_max=8, n_pilot=10000, seed=1, precision=32,
+                     alpha=0.0, beta=0.0, cache_path=None):
+        """Tune the device-planned run's launch shape on this run configuration;
+        returns (block, ppt, blocks_per_cu)."""
+        o = RunOpts(eps, M, L_min, L_max, n_pilot, seed, precision, 1, alpha, beta, None, 0)
+        shape = (C.c_int * 3)()
+        self._check(self._lib.mlmc_autotune_run(
+            self.h, C.byref(m), C.byref(p), C.byref(o),
+            cache_path.encode() if cache_path else None, shape))
         return tuple(shape)
 
     def tuned_shape(self, m, p, l, M=4, precision=32):

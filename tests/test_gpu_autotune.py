@@ -24,7 +24,7 @@ def test_autotune_cache_and_invariance(tmp_path):
             assert abs(a["sum_y"] - b["sum_y"]) <= 1e-12 * abs(a["sum_y"])
     data = json.load(open(path))
     (machine, entries), = data.items()
-    assert "gfx950" in machine and len(entries) == 3
+    assert "gfx950" in machine and len(entries) == 7       # levels 0..5, then 6 and deeper
     # a new context reads the cache instead of measuring
     with mlmc.Context(0) as ctx:
         assert ctx.tuned_shape(gm, gp, 2) == (0, 0)
@@ -96,3 +96,34 @@ def test_autotune_keys_separate_scheme_twin_and_payoff_mix(tmp_path):
     entries = next(iter(json.load(open(path)).values()))
     persist = [k for k in entries if k.startswith("persist:")]
     assert len(persist) == 2 and len(set(persist)) == 2
+
+
+def test_autotune_run_tunes_the_device_planned_form(tmp_path):
+    """The run tuner times whole device-planned runs of the caller's
+    configuration, sets and caches a shape from the persistent candidate set,
+    and the run's decisions and estimate do not depend on it."""
+    import time
+    path = str(tmp_path / "tune_run.json")
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.ASIAN)
+    kw = dict(M=4, L_min=2, L_max=6, n_pilot=2000, seed=3)
+    with mlmc.Context(0) as ctx:
+        ref = ctx.mlmc_run(gm, gp, 0.02, persistent=1, **kw)
+        shape = ctx.autotune_run(gm, gp, 0.02, cache_path=path, **kw)
+        b, p, c = shape
+        assert b in (128, 256, 512) and p in (1, 2, 4) and c in (2, 4, 8) and b * c <= 2048
+        got = ctx.mlmc_run(gm, gp, 0.02, persistent=1, **kw)
+        assert got["N"] == ref["N"] and got["L"] == ref["L"]
+        assert abs(got["estimate"] - ref["estimate"]) <= 1e-10 * abs(ref["estimate"])
+        with pytest.raises(mlmc.MLMCError) as e:      # only the device-planned form is tuned
+            ctx._check(ctx._lib.mlmc_autotune_run(
+                ctx.h, mlmc.C.byref(gm), mlmc.C.byref(gp),
+                mlmc.C.byref(mlmc.RunOpts(0.02, 4, 2, 6, 2000, 3, 32, 0, 0.0, 0.0, None, 0)),
+                None, None))
+        assert e.value.status == mlmc.MLMC_EINVAL
+        ctx.set_persistent_launch(0, 0, 0)
+    entries = next(iter(json.load(open(path)).values()))
+    assert [k for k in entries if k.startswith("run:")] and list(entries.values()) == [list(shape)]
+    with mlmc.Context(0) as ctx:
+        t0 = time.perf_counter()
+        assert ctx.autotune_run(gm, gp, 0.02, cache_path=path, **kw) == shape
+        assert time.perf_counter() - t0 < 0.5

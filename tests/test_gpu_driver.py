@@ -108,6 +108,27 @@ def test_timing_mask_records_only_its_slots(gctx):
     assert all(st[l]["launches"] >= 1 for l in range(r["L"] + 1))
 
 
+def test_timing_stride_stamps_one_launch_in_k(gctx):
+    """With stride k the slot's statistics cover launches 1, k+1, 2k+1, ...
+    of the slot: ceil(n/k) of its n launches, here level-0 launches of
+    fixed size, so the sampled average is that of every launch."""
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    N = 1 << 16
+    for k, n in ((1, 7), (3, 7), (4, 8), (9, 5)):
+        gctx.set_timing_slots([0])
+        gctx.set_timing_stride(k)
+        for i in range(n):
+            gctx.mlmc_level(gm, gp, 0, 4, N, 1 + i)
+        st = gctx.kernel_stats()[0]
+        gctx.set_timing(False)
+        gctx.set_timing_stride(1)
+        assert st["launches"] == -(-n // k), (k, n, st)
+        assert st["fine_steps"] == st["launches"] * N and st["ms"] > 0
+    with pytest.raises(mlmc.MLMCError) as e:
+        gctx.set_timing_stride(0)
+    assert e.value.status == mlmc.MLMC_EINVAL
+
+
 @pytest.mark.parametrize("persistent", [False, True])
 def test_timed_runs_give_the_untimed_results(gctx, persistent):
     """Kernel timing changes only how launches are stamped: the estimates,
