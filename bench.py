@@ -112,8 +112,9 @@ def parse():
                     help="Adam steps for the control-variate networks (0: plain only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (scales HBM byte counters)")
-    ap.add_argument("--stamp-stride", type=int, default=4,
-                    help="timed region: stamp one launch in this many of the dominant kernel")
+    ap.add_argument("--stamp-every", type=int, default=5,
+                    help="timed region: stamp every launch of the dominant kernel in one "
+                         "estimate in this many (the others run unstamped)")
     ap.add_argument("--form", choices=("planned", "per-level"), default="planned",
                     help="planned: per driver iteration one all-levels sampler launch and one "
                          "update-and-plan launch, enqueued ahead by the host; per-level: one "
@@ -136,6 +137,9 @@ def parse():
     ap.add_argument("--profile-run", type=int, default=0,
                     help="profile mode: this many device-planned adaptive estimates of the "
                          "benchmark workload (after tuning), then one JSON line")
+    ap.add_argument("--planned-shape", default="",
+                    help="with --profile-run: block,ppt,blocks_per_cu of the persistent sampler "
+                         "instead of the run tuner's choice")
     return ap.parse_args()
 
 
@@ -200,7 +204,11 @@ def profile_run_mode(args):
     M, eps = 4, args.eps * W.S0
     run_kw = dict(M=M, L_min=2, L_max=9, n_pilot=10000, precision=32)
     ctx.autotune(gm, gp, M=M, precision=32)
-    shape = ctx.autotune_run(gm, gp, eps, seed=1, **run_kw)
+    if args.planned_shape:
+        shape = tuple(int(x) for x in args.planned_shape.split(","))
+        ctx.set_persistent_launch(*shape)
+    else:
+        shape = ctx.autotune_run(gm, gp, eps, seed=1, **run_kw)
     for i in range(2):
         ctx.mlmc_run(gm, gp, eps, seed=1 + i, persistent=True, **run_kw)
     torch.cuda.synchronize()
@@ -313,11 +321,12 @@ def reference_prices():
         return {k: v["value"] for k, v in json.load(f).items()}
 
 
-def seeds_runs(ctx, m, p, eps, M, cv, seeds, exact, cv_levels=0):
+def seeds_runs(ctx, m, p, eps, M, cv, seeds, exact, cv_levels=0, persistent=False):
     """Runs over the seeds: median wall seconds, empirical RMSE against the
     continuous price, and the median run."""
     import statistics
-    runs = [ctx.mlmc_run(m, p, eps, M=M, seed=s, precision=32, cv=cv, cv_levels=cv_levels)
+    runs = [ctx.mlmc_run(m, p, eps, M=M, seed=s, precision=32, cv=cv, cv_levels=cv_levels,
+                         persistent=persistent)
             for s in seeds]
     rmse = (sum((r["estimate"] - exact) ** 2 for r in runs) / len(runs)) ** 0.5
     mid = sorted(runs, key=lambda r: r["wall_s"])[len(runs) // 2]
@@ -358,6 +367,11 @@ def time_to_accuracy(ctx, mlmc, W, args, seeds=range(1, 33)):
             tp, ep, rp = seeds_runs(ctx, m, p, eps * W.S0, 4, None, seeds, exact)
             e = {"target_rmse": eps * W.S0, "plain_s": tp, "plain_rmse": ep, "plain_cost": rp["cost"],
                  "plain_N": rp["N"], "plain_V": [round(v, 6) for v in rp["V"]]}
+            # plain MLMC device-planned (the control variate runs per level),
+            # in the shape the run tuner picks for this configuration
+            ctx.autotune_run(m, p, eps * W.S0, M=4, seed=1)
+            tq, eq, _ = seeds_runs(ctx, m, p, eps * W.S0, 4, None, seeds, exact, persistent=True)
+            e.update({"plain_planned_s": tq, "plain_planned_rmse": eq})
             if cv is not None:
                 tc, ec, rc = seeds_runs(ctx, m, p, eps * W.S0, 4, cv, seeds, exact)
                 e.update({"cv_s": tc, "cv_rmse": ec, "cv_cost": rc["cost"], "cv_N": rc["N"],
@@ -478,9 +492,11 @@ def accuracy_targets(ctx, mlmc, W, seeds=range(1, 33)):
     for name, md, eps in cases:
         m, p = mlmc.model(**md), mlmc.payoff(**W.CALL)
         t, rmse, mid = seeds_runs(ctx, m, p, eps * W.S0, 4, None, seeds, ref[name])
+        ctx.autotune_run(m, p, eps * W.S0, M=4, seed=1)
+        tq, rq, _ = seeds_runs(ctx, m, p, eps * W.S0, 4, None, seeds, ref[name], persistent=True)
         key = f"eps_{eps:g}_S0" if name == "gbm_call" else f"{name}_eps_{eps:g}_S0"
         out[key] = {"median_s": t, "rmse": rmse, "target_rmse": eps * W.S0, "L": mid["L"],
-                    "N_median_run": mid["N"]}
+                    "N_median_run": mid["N"], "planned_median_s": tq, "planned_rmse": rq}
     return out
 
 
@@ -603,12 +619,21 @@ def main():
     def step(seed, persistent=planned):
         return ctx.mlmc_run(gm, gp, eps, seed=seed, persistent=persistent, **run_kw)
 
-    def timed_pass(persistent=planned):
+    def timed_pass(persistent=planned, stamp_every=0):
+        """The K steps by the clock; with stamp_every k, the timing (set up
+        by the caller) is paused for all but every k-th estimate."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rs = [step(1 + i, persistent) for i in range(args.steps)]
+        rs = []
+        for i in range(args.steps):
+            if stamp_every:
+                ctx.set_timing_paused(i % stamp_every != 0)
+            rs.append(step(1 + i, persistent))
         torch.cuda.synchronize()
-        return rs, time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        if stamp_every:
+            ctx.set_timing_paused(False)
+        return rs, dt
 
     def warm(persistent=planned):
         for i in range(args.warmup):
@@ -629,20 +654,20 @@ def main():
     tune["tuning_s"] = time.perf_counter() - t0
     warm()
     # Which kernel dominates: every slot timed over the same steps, untimed
-    # by the clock.  The timed region then stamps one launch in
-    # --stamp-stride of that kernel only (a stamped launch costs ~10 us of
-    # queue time more than a plain one).
+    # by the clock.  The timed region then stamps that kernel only, and only
+    # in every --stamp-every-th estimate (a stamped launch costs ~10 us of
+    # queue time more than a plain one), every launch of those estimates, so
+    # the stamped launches are whole runs whose work is known.
     ctx.set_timing(True)
     all_runs = [step(1 + i) for i in range(args.steps)]
     all_slots = ctx.kernel_stats()
     ctx.set_timing(False)
     dom = mlmc.STAT_PERSISTENT if planned else max(range(16), key=lambda l: all_slots[l]["ms"])
     ctx.set_timing_slots([dom])
-    ctx.set_timing_stride(args.stamp_stride)
-    runs, dt = timed_pass()
+    runs, dt = timed_pass(stamp_every=args.stamp_every)
     stats = ctx.kernel_stats()
     ctx.set_timing(False)
-    ctx.set_timing_stride(1)
+    stamped_runs = runs[::args.stamp_every]
     # context: the same steps with no kernel stamped
     _, dt_unstamped = timed_pass()
 
@@ -653,13 +678,14 @@ def main():
     if planned and s["launches"]:
         # the device-planned form: one persistent all-levels sampler launch
         # per driver iteration (and the empty one queued past the last
-        # update).  The host sees only whole runs, so the operations of all
-        # the timed runs are spread over all their sampler launches, and the
-        # stamped launches (every --stamp-stride-th) give the average time.
-        launches = sum(r["iterations"] + 1 for r in runs)
-        ops = run_ops(runs, M)
+        # update).  The host sees only whole runs: the operations of the
+        # stamped runs over their stamped sampler launches (all of them).
+        launches = sum(r["iterations"] + 1 for r in stamped_runs)
+        assert launches == s["launches"], (launches, s["launches"])
+        ops = run_ops(stamped_runs, M)
         avg_ms = s["ms"] / s["launches"]
         achieved = ops / launches / (avg_ms * 1e-3)
+        all_launches = sum(r["iterations"] + 1 for r in runs)
         shape = tune.get("planned_run") or (256, 1, 4)
         label = f"persistent_kernel<GBM,M=4,ppt={shape[1]},call>"
         a = all_slots[dom]
@@ -668,17 +694,18 @@ def main():
                     "traffic": measured_traffic(label), "kernel": label,
                     "launch_shape": {"block": shape[0], "ppt": shape[1], "blocks_per_cu": shape[2]},
                     "ops_per_launch": ops / launches, "avg_launch_ms": avg_ms,
-                    "launches": s["launches"], "launches_in_timed_region": launches,
-                    "stamp_stride": args.stamp_stride,
+                    "launches": s["launches"], "launches_in_timed_region": all_launches,
+                    "stamped_estimates": len(stamped_runs), "stamp_every": args.stamp_every,
                     # every sampler launch of the same steps stamped (the
-                    # all-slots pass): the sampled average's cross-check
+                    # all-slots pass): the stamped runs' cross-check
                     "avg_launch_ms_all_stamped": a["ms"] / a["launches"] if a["launches"] else None,
-                    "share_of_step": launches * avg_ms * 1e-3 / dt}
+                    "ops_per_launch_all": run_ops(runs, M) / all_launches,
+                    "share_of_step": all_launches * avg_ms * 1e-3 / dt}
         # from the committed counter summary of this kernel (profiles/): its
         # issue fraction under the counters, this run's rate against the
         # ceiling its instructions per fine step allow, and its fp32 FLOPs
         # over the fp32 peak
-        fine_per_s = fine / launches / (avg_ms * 1e-3)
+        fine_per_s = sum(fine_steps_of(r, M) for r in stamped_runs) / launches / (avg_ms * 1e-3)
         roofline["valu_issue_frac_counters"] = profile_field(label, "valu_issue_frac")
         ipf = profile_field(label, "valu_insts_per_fine_step")
         roofline["valu_insts_per_fine_step"] = ipf
@@ -691,7 +718,8 @@ def main():
                  else f"level_kernel<GBM,call,fp32,M=4> at level {dom}")
         roofline = per_level_roofline(stats, dom, M, label)
         roofline["launches_in_timed_region"] = all_slots[dom]["launches"]
-        roofline["stamp_stride"] = args.stamp_stride
+        roofline["stamped_estimates"] = len(stamped_runs)
+        roofline["stamp_every"] = args.stamp_every
 
     upd = all_slots[mlmc.STAT_DRIVER]
     line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -724,11 +752,9 @@ def main():
         pl_slots = ctx.kernel_stats()
         ctx.set_timing(False)
         ctx.set_timing_slots([0])
-        ctx.set_timing_stride(args.stamp_stride)
-        timed_pass(False)
+        timed_pass(False, stamp_every=args.stamp_every)
         pl_stats = ctx.kernel_stats()
         ctx.set_timing(False)
-        ctx.set_timing_stride(1)
         line["per_level_form"] = {
             "ms_per_step": 1e3 * pl_dt / args.steps,
             "fine_path_steps_per_s": sum(fine_steps_of(r, M) for r in pl_runs) / pl_dt,

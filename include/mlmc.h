@@ -166,6 +166,11 @@ mlmc_status mlmc_set_timing_mask(mlmc_ctx* ctx, uint32_t slot_mask);
  * wants a slot's average duration over a long run without slowing it in
  * proportion samples it.  MLMC_EINVAL for 0.                               */
 mlmc_status mlmc_set_timing_stride(mlmc_ctx* ctx, uint32_t stride);
+/* paused != 0: stamp no launch until called with 0 (the mask, the stride
+ * count and the statistics are kept; no wait for the stream).  A caller
+ * stamps whole calls, e.g. every k-th mlmc_run with every launch of it, by
+ * pausing around the others.                                               */
+mlmc_status mlmc_set_timing_paused(mlmc_ctx* ctx, int paused);
 /* Copy MLMC_STAT_SLOTS statistics into out (host array). */
 mlmc_status mlmc_kernel_stats(mlmc_ctx* ctx, mlmc_kernel_stat* out);
 

@@ -191,7 +191,7 @@ static hipEvent_t pool_event(mlmc_ctx* ctx)
 // k, it is the first, (k+1)-th, (2k+1)-th ... launch since the mask was set.
 static bool time_this(mlmc_ctx* ctx, int slot)
 {
-    if (!(ctx->timing >> slot & 1u)) return false;
+    if (ctx->timing_paused || !(ctx->timing >> slot & 1u)) return false;
     return ctx->timing_seen[slot]++ % ctx->timing_stride == 0;
 }
 
@@ -486,6 +486,13 @@ mlmc_status mlmc_set_timing_stride(mlmc_ctx* ctx, uint32_t stride)
     if (stride < 1) return fail(ctx, MLMC_EINVAL, "stride must be >= 1");
     ctx->timing_stride = stride;
     for (auto& n : ctx->timing_seen) n = 0;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_set_timing_paused(mlmc_ctx* ctx, int paused)
+{
+    if (!ctx) return MLMC_EINVAL;
+    ctx->timing_paused = paused != 0;
     return MLMC_OK;
 }
 

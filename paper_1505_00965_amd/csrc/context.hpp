@@ -40,6 +40,7 @@ struct mlmc_ctx {
     };
     uint32_t timing = 0;                    // bit s: time launches of slot s
     uint32_t timing_stride = 1;             // time one launch in this many of a slot
+    bool timing_paused = false;             // stamp nothing for now (mask and stats kept)
     uint64_t timing_seen[MLMC_STAT_SLOTS] = {};   // launches of each slot since the mask was set
     std::vector<hipEvent_t> event_pool;
     std::vector<Timed> pending;

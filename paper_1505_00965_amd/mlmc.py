@@ -27,6 +27,7 @@ EXPORTED = [
     "mlmc_autotune_persistent",
     "mlmc_tuned_shape", "mlmc_rhee_glynn", "mlmc_set_timing_mask", "mlmc_level_noalloc",
     "mlmc_cv_set_tabulated", "mlmc_cv_get_table", "mlmc_set_timing_stride", "mlmc_autotune_run",
+    "mlmc_set_timing_paused",
 ]
 STAT_SLOTS = 20
 STAT_PERSISTENT, STAT_DRIVER, STAT_CV_TRAIN = 16, 17, 18
@@ -155,6 +156,7 @@ def lib():
     L.mlmc_set_timing.argtypes = [vp, i32]
     L.mlmc_set_timing_mask.argtypes = [vp, u32]
     L.mlmc_set_timing_stride.argtypes = [vp, u32]
+    L.mlmc_set_timing_paused.argtypes = [vp, i32]
     L.mlmc_autotune_run.argtypes = [vp, M_, P_, C.POINTER(RunOpts), C.c_char_p, C.POINTER(i32)]
     L.mlmc_kernel_stats.argtypes = [vp, C.POINTER(KernelStat)]
     L.mlmc_level_noalloc.argtypes = [M_, P_, i32, i32, u64, u64, u64, i32, vp, vp, C.c_char_p,
@@ -261,6 +263,10 @@ class Context:
     def set_timing_stride(self, stride=1):
         """Time one launch in `stride` of each timed slot."""
         self._check(self._lib.mlmc_set_timing_stride(self.h, int(stride)))
+
+    def set_timing_paused(self, paused=True):
+        """Stamp nothing while paused (mask, stride count and statistics kept)."""
+        self._check(self._lib.mlmc_set_timing_paused(self.h, int(bool(paused))))
 
     def kernel_stats(self):
         """Per-slot {launches, ms, fine_steps, coarse_steps} (slots 0..15 = level)."""

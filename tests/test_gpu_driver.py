@@ -127,6 +127,17 @@ def test_timing_stride_stamps_one_launch_in_k(gctx):
     with pytest.raises(mlmc.MLMCError) as e:
         gctx.set_timing_stride(0)
     assert e.value.status == mlmc.MLMC_EINVAL
+    # paused: nothing stamped, the statistics kept; whole runs stamped
+    gctx.set_timing_slots([mlmc.STAT_PERSISTENT])
+    runs = []
+    for i in range(4):
+        gctx.set_timing_paused(i % 2 == 1)
+        runs.append(gctx.mlmc_run(gm, gp, 0.05, M=4, seed=2 + i, persistent=1))
+    gctx.set_timing_paused(False)
+    st = gctx.kernel_stats()[mlmc.STAT_PERSISTENT]
+    gctx.set_timing(False)
+    assert st["launches"] == sum(r["iterations"] + 1 for r in runs[::2])
+    assert st["fine_steps"] == sum(n * 4**l for r in runs[::2] for l, n in enumerate(r["N"]))
 
 
 @pytest.mark.parametrize("persistent", [False, True])
