@@ -386,10 +386,17 @@ def time_to_accuracy(ctx, mlmc, W, args, seeds=range(1, 33)):
                 # parameter change, interpolated by the samplers)
                 cv.set_tabulated(True)
                 tt, et, rt = seeds_runs(ctx, m, p, eps * W.S0, 4, cv, seeds, exact)
+                # the tabulated network in the device-planned form (the
+                # persistent shape as tuned for the plain run above)
+                ctx.autotune_run(m, p, eps * W.S0, M=4, seed=1)
+                tqc, eqc, rqc = seeds_runs(ctx, m, p, eps * W.S0, 4, cv, seeds, exact,
+                                           persistent=True)
                 cv.set_tabulated(False)
                 e.update({"cv_tab_s": tt, "cv_tab_rmse": et, "cv_tab_cost": rt["cost"],
                           "cv_tab_N": rt["N"], "cv_tab_V": [round(v, 6) for v in rt["V"]],
-                          "speedup_tab": tp / tt, "cv_tab_with_training_s": tt + entry["train_s"]})
+                          "speedup_tab": tp / tt, "cv_tab_with_training_s": tt + entry["train_s"],
+                          "cv_tab_planned_s": tqc, "cv_tab_planned_rmse": eqc,
+                          "speedup_tab_planned_vs_plain_planned": e["plain_planned_s"] / tqc})
             entry[key] = e
         if cv is not None:
             cv.close()

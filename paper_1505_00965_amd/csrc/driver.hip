@@ -164,8 +164,9 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
         return fail(ctx, MLMC_EINVAL, "the control variate runs in fp32 paths only");
     if (o.persistent != 0 && o.persistent != 1)
         return fail(ctx, MLMC_EINVAL, "persistent must be 0 or 1");
-    if (o.cv && o.persistent)
-        return fail(ctx, MLMC_EINVAL, "the control variate runs with per-level launches only");
+    if (o.cv && o.persistent && !cv_tabulated(o.cv))
+        return fail(ctx, MLMC_EINVAL,
+                    "the device-planned form takes the tabulated control variate (mlmc_cv_set_tabulated)");
     if (model->antithetic && o.persistent)
         return fail(ctx, MLMC_EINVAL, "the antithetic estimator runs with per-level launches only");
     ctx->err.clear();

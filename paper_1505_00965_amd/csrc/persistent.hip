@@ -159,17 +159,18 @@ __global__ __launch_bounds__(64) void fold_groups_kernel(LevelAcc* groups, Level
     }
 }
 
-extern template PersistentFn pick_persistent_variant<kGBM>(int, int, int);
-extern template PersistentFn pick_persistent_variant<kGBMMil>(int, int, int);
-extern template PersistentFn pick_persistent_variant<kHeston>(int, int, int);
+extern template PersistentFn pick_persistent_variant<kGBM>(int, int, int, bool);
+extern template PersistentFn pick_persistent_variant<kGBMMil>(int, int, int, bool);
+extern template PersistentFn pick_persistent_variant<kHeston>(int, int, int, bool);
 
 // variant: sampler_variant() of the model (GBM Euler, GBM Milstein, Heston);
-// payoff: the kind every slot holds, or kAnyPayoff.
-static PersistentFn pick_persistent(int variant, int M, int ppt, int payoff)
+// payoff: the kind every slot holds, or kAnyPayoff; cv: with the tabulated
+// control variate (nullptr where that kernel does not exist).
+static PersistentFn pick_persistent(int variant, int M, int ppt, int payoff, bool cv = false)
 {
-    if (variant == kGBM) return pick_persistent_variant<kGBM>(M, ppt, payoff);
-    if (variant == kGBMMil) return pick_persistent_variant<kGBMMil>(M, ppt, payoff);
-    return pick_persistent_variant<kHeston>(M, ppt, payoff);
+    if (variant == kGBM) return pick_persistent_variant<kGBM>(M, ppt, payoff, cv);
+    if (variant == kGBMMil) return pick_persistent_variant<kGBMMil>(M, ppt, payoff, cv);
+    return pick_persistent_variant<kHeston>(M, ppt, payoff, cv);
 }
 
 // Device buffers of the persistent form, owned by the context.
@@ -339,17 +340,37 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
                            const DriverInit& init)
 {
     if (o.precision != 32) return fail(ctx, MLMC_EINVAL, "the persistent form runs fp32 paths");
-    if (o.cv) return fail(ctx, MLMC_EINVAL, "the persistent form runs plain MLMC");
+    if (o.cv) {
+        if (!cv_tabulated(o.cv))
+            return fail(ctx, MLMC_EINVAL,
+                        "the device-planned form takes the tabulated control variate (mlmc_cv_set_tabulated)");
+        if (m.scheme != MLMC_EULER || m.antithetic)
+            return fail(ctx, MLMC_EINVAL, "the control variate runs with plain Euler paths");
+        if (p.kind == MLMC_DIGITAL_COND)
+            return fail(ctx, MLMC_EINVAL, "the control variate takes the four plain payoffs");
+        if (cv_in_dim(o.cv) != (m.kind == MLMC_HESTON ? 3 : 2))
+            return fail(ctx, MLMC_EINVAL, "network inputs do not match the model (2: GBM, 3: Heston)");
+    }
     mlmc_status st = ensure_bufs(ctx);
     if (st) return st;
     auto* b = bufs_of(ctx);
     // the seed goes in with the start kernel: runs of one problem share the
     // descriptor's bytes and upload it once
     fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, 0, d_st->dN, d_st->n, ctx->d_drv_spread);
+    size_t lds = 0;
+    if (o.cv) {
+        int max_nf = 1;
+        for (int l = 0; l < o.L_max; ++l) max_nf *= o.M;
+        const hipError_t e = cv_table_view(o.cv, m, ctx->stream, max_nf, &b->h_desc->cv_table,
+                                           &b->h_desc->cv_spec, &b->h_desc->cv_phi0, &lds);
+        if (e != hipSuccess) return hip_fail(ctx, e, "control-variate table");
+        b->h_desc->cv_levels = o.cv_levels;
+    }
     st = upload_desc(ctx, b, true);
     if (st) return st;
     const PersistentShape s = persistent_shape(ctx);
-    const auto sampler = pick_persistent(sampler_variant(m), o.M, s.ppt, p.kind);
+    const auto sampler = pick_persistent(sampler_variant(m), o.M, s.ppt, p.kind, o.cv != nullptr);
+    if (!sampler) return fail(ctx, MLMC_EINVAL, "no persistent sampler for this model and payoff");
     const dim3 grid(ctx->num_cu * s.blocks_per_cu), block(s.block);
     const BatchDesc* d = b->d_desc;
     DriverState* mirror = (DriverState*)ctx->h_drv_dev;
@@ -372,8 +393,8 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
             hipEvent_t t0, t1;
             timed_kernel(ctx, 16, 0.0, 0.0, &t0, &t1);
             if (first_tix < 0 && t0) first_tix = (int)ctx->pending.size() - 1;
-            if (t0) hipExtLaunchKernelGGL(sampler, grid, block, 0, ctx->stream, t0, t1, 0, d);
-            else hipLaunchKernelGGL(sampler, grid, block, 0, ctx->stream, d);
+            if (t0) hipExtLaunchKernelGGL(sampler, grid, block, lds, ctx->stream, t0, t1, 0, d);
+            else hipLaunchKernelGGL(sampler, grid, block, lds, ctx->stream, d);
             hipError_t e = hipGetLastError();
             if (e == hipSuccess) {
                 timed_kernel(ctx, 17, 0.0, 0.0, &t0, &t1);

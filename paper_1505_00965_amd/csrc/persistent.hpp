@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "cv_tab.hpp"
 #include "driver.hpp"
 #include "level.hpp"
 #include "sampler_impl.hpp"
@@ -55,6 +56,13 @@ struct BatchDesc {
     unsigned* split;                  // lanes per path per (slot, level), set by the plan
     int split_ok;                     // the model's paths are linear in their start (GBM)
     int num_cu;
+    // the tabulated control variate of a driver run (the sampler kernel
+    // compiled with it): its table and grid, phi(0, S0) from the table, and
+    // the levels it applies to (l < cv_levels, or all for 0)
+    const float* cv_table;
+    TableSpec cv_spec;
+    const float* cv_phi0;
+    int cv_levels;
 };
 
 // A batch whose slots may hold different payoff kinds.
@@ -102,6 +110,35 @@ __device__ __forceinline__ void run_range(const LevelArgs<float>& a, double (&su
     }
 }
 
+// The samples [a.offset, a.offset + a.N) of one item part of a level >= 1
+// with the tabulated control variate (the level's rows in LDS, tv): the
+// per-level kernels' paths (split GBM paths, two-step samples at M = 2, or
+// up to two samples per lane).
+template <int MODEL, int PAYOFF, int M, int PPT>
+__device__ __forceinline__ void run_range_tab(const LevelArgs<float>& a, const TabView& tv,
+                                              double (&sums)[kNumSums], unsigned& nonfinite)
+{
+    if constexpr (MODEL == kGBM) {
+        if (a.split > 1) {
+            const uint64_t pass = blockDim.x / a.split;
+            for (uint64_t base = 0; base < a.N; base += pass)
+                process_split_tab<PAYOFF, M>(a, base, tv, sums, nonfinite);
+            return;
+        }
+    }
+    if (a.nf < 4) {
+        if constexpr (M == 2) {
+            for (uint64_t base = 0; base < a.N; base += blockDim.x)
+                process_short_tab<MODEL, PAYOFF, M>(a, base, tv, sums, nonfinite);
+        }
+        return;
+    }
+    constexpr int TP = PPT > 2 ? 2 : PPT;
+    const uint64_t chunk = (uint64_t)blockDim.x * TP;
+    for (uint64_t base = 0; base < a.N; base += chunk)
+        process_chunk_tab<MODEL, PAYOFF, M, TP>(a, base, tv, sums, nonfinite);
+}
+
 // A copy of v that the compiler knows to be the same in every lane (it
 // must be): each 32-bit word read from the first active lane, so the item
 // and its parameters live in scalar registers, as a launch's arguments do.
@@ -118,9 +155,13 @@ __device__ __forceinline__ T wave_uniform(const T& v)
     return out;
 }
 
-template <int MODEL, int PAYOFF, int M, int PPT>
+// One item.  CV: the kernel carries the tabulated control variate; an item
+// of a level it applies to takes phi(0, S0) (level 0) or the level's table
+// rows, copied into s_tab unless the block's previous item left them there
+// (tab_level, block-uniform; items are separated by barriers).
+template <int MODEL, int PAYOFF, int M, int PPT, bool CV>
 __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[kNumSums],
-                         unsigned& nonfinite)
+                                         unsigned& nonfinite, float* s_tab, int& tab_level)
 {
     LevelArgs<float> a;
     a.P = wave_uniform(d->params[w.slot][w.level]);
@@ -136,6 +177,26 @@ __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, 
     a.coupled = 1;
     a.phi0 = nullptr;
     a.split = __builtin_amdgcn_readfirstlane(d->split[w.slot * kMaxLevels + w.level]);
+    bool tab = false;
+    TabView tv{};
+    if constexpr (CV) {
+        const int cl = __builtin_amdgcn_readfirstlane(d->cv_levels);
+        if (cl <= 0 || (int)w.level < cl) {
+            if (w.level == 0) {
+                a.phi0 = d->cv_phi0;
+            } else {
+                tab = true;
+                const TableSpec t = wave_uniform(d->cv_spec);
+                if (tab_level != (int)w.level) {
+                    tv = load_level_table(s_tab, d->cv_table, t, nf);   // ends with a barrier
+                    tab_level = w.level;
+                } else {
+                    const int lr = nf < t.rows ? nf : t.rows;
+                    tv = TabView{s_tab, t, lr, nf};
+                }
+            }
+        }
+    }
     constexpr int D = one_factor(MODEL) ? 1 : 2;
     // one pass per part of the item whose generator units share counter word 2
     const uint64_t q = samples_per_unit(nf, D), end = w.first + w.n;
@@ -144,15 +205,12 @@ __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, 
         a.offset = first;
         a.N = stop - first;
         set_counter_words(a, D);
-        run_range<MODEL, PAYOFF, M, PPT>(a, sums, nonfinite);
+        if (CV && tab) run_range_tab<MODEL, PAYOFF, M, PPT>(a, tv, sums, nonfinite);
+        else run_range<MODEL, PAYOFF, M, PPT>(a, sums, nonfinite);
         first = stop;
     }
 }
 
-// Block b takes item b first; later items come from the dispenser until
-// none are left, so a launch with no more items than blocks (an empty one
-// included) makes no atomics on it.  Each item ends with a block reduction
-// into its (payoff, level) spread group.
 // Item `it` of the plan (block-uniform).
 __device__ __forceinline__ WorkItem plan_item(const PlanTable& t, unsigned it)
 {
@@ -169,8 +227,12 @@ __device__ __forceinline__ WorkItem plan_item(const PlanTable& t, unsigned it)
     return w;
 }
 
-template <int MODEL, int M, int PPT, int PAYOFF>
-__device__ __forceinline__ void sample_items(const BatchDesc* d)
+// Block b takes item b first; later items come from the dispenser until
+// none are left, so a launch with no more items than blocks (an empty one
+// included) makes no atomics on it.  Each item ends with a block reduction
+// into its (payoff, level) spread group.
+template <int MODEL, int M, int PPT, int PAYOFF, bool CV>
+__device__ __forceinline__ void sample_items(const BatchDesc* d, float* s_tab)
 {
     __shared__ unsigned s_item;
     // the plan in LDS: each item is decoded by a short search over its pairs
@@ -181,6 +243,7 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d)
         for (int i = threadIdx.x; i < (int)(sizeof(PlanTable) / 8); i += blockDim.x) dst[i] = src[i];
         __syncthreads();
     }
+    int tab_level = -1;
     const unsigned count = __builtin_amdgcn_readfirstlane(s_plan.start[s_plan.npairs]);
     for (unsigned it = blockIdx.x; it < count;) {   // block-uniform
         const WorkItem w = wave_uniform(plan_item(s_plan, it));
@@ -188,14 +251,18 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d)
         unsigned nonfinite = 0;
         if constexpr (PAYOFF == kAnyPayoff) {
             switch (d->payoff_kind[w.slot]) {
-            case kCall: run_item<MODEL, kCall, M, PPT>(d, w, sums, nonfinite); break;
-            case kAsian: run_item<MODEL, kAsian, M, PPT>(d, w, sums, nonfinite); break;
-            case kLookback: run_item<MODEL, kLookback, M, PPT>(d, w, sums, nonfinite); break;
-            case kDigitalCond: run_item<MODEL, kDigitalCond, M, PPT>(d, w, sums, nonfinite); break;
-            default: run_item<MODEL, kDigital, M, PPT>(d, w, sums, nonfinite); break;
+            case kCall: run_item<MODEL, kCall, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level); break;
+            case kAsian: run_item<MODEL, kAsian, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level); break;
+            case kLookback:
+                run_item<MODEL, kLookback, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level);
+                break;
+            case kDigitalCond:
+                run_item<MODEL, kDigitalCond, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level);
+                break;
+            default: run_item<MODEL, kDigital, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level); break;
             }
         } else {
-            run_item<MODEL, PAYOFF, M, PPT>(d, w, sums, nonfinite);
+            run_item<MODEL, PAYOFF, M, PPT, CV>(d, w, sums, nonfinite, s_tab, tab_level);
         }
         if (w.level == 0) copy_y_sums(sums);
         block_reduce_add(sums, nonfinite, &d->acc[(w.slot * kMaxLevels + w.level) * kSpread +
@@ -210,44 +277,62 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d)
 
 // PAYOFF: one payoff kind for every slot of the batch, or kAnyPayoff (each
 // item's slot names it; the kernel then holds every payoff's code and the
-// registers of the largest).
-template <int MODEL, int M, int PPT, int PAYOFF>
+// registers of the largest).  CV: with the tabulated control variate (one
+// payoff, Euler paths; launched with the deepest level's table rows of
+// dynamic LDS).
+template <int MODEL, int M, int PPT, int PAYOFF, bool CV>
 __global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
 {
-    sample_items<MODEL, M, PPT, PAYOFF>(d);
+    extern __shared__ __attribute__((aligned(16))) float s_tab[];
+    sample_items<MODEL, M, PPT, PAYOFF, CV>(d, s_tab);
 }
 
 using PersistentFn = void (*)(const BatchDesc*);
 
 template <int MODEL, int M, int PPT>
-PersistentFn pick_persistent_payoff(int payoff)
+PersistentFn pick_persistent_payoff(int payoff, bool cv)
 {
+    if (cv) {
+        // the control variate runs with Euler paths and the four plain payoffs
+        if constexpr (MODEL != kGBMMil) {
+            switch (payoff) {
+            case kCall: return persistent_kernel<MODEL, M, PPT, kCall, true>;
+            case kAsian: return persistent_kernel<MODEL, M, PPT, kAsian, true>;
+            case kLookback: return persistent_kernel<MODEL, M, PPT, kLookback, true>;
+            case kDigital: return persistent_kernel<MODEL, M, PPT, kDigital, true>;
+            default: return nullptr;
+            }
+        }
+        return nullptr;
+    }
     switch (payoff) {
-    case kCall: return persistent_kernel<MODEL, M, PPT, kCall>;
-    case kAsian: return persistent_kernel<MODEL, M, PPT, kAsian>;
-    case kLookback: return persistent_kernel<MODEL, M, PPT, kLookback>;
-    case kDigital: return persistent_kernel<MODEL, M, PPT, kDigital>;
-    case kDigitalCond: return persistent_kernel<MODEL, M, PPT, kDigitalCond>;
-    default: return persistent_kernel<MODEL, M, PPT, kAnyPayoff>;
+    case kCall: return persistent_kernel<MODEL, M, PPT, kCall, false>;
+    case kAsian: return persistent_kernel<MODEL, M, PPT, kAsian, false>;
+    case kLookback: return persistent_kernel<MODEL, M, PPT, kLookback, false>;
+    case kDigital: return persistent_kernel<MODEL, M, PPT, kDigital, false>;
+    case kDigitalCond: return persistent_kernel<MODEL, M, PPT, kDigitalCond, false>;
+    default: return persistent_kernel<MODEL, M, PPT, kAnyPayoff, false>;
     }
 }
 
 // The sampler of one model variant for (M, samples per lane, payoff kind or
-// kAnyPayoff).  Defined here, instantiated once per variant.
+// kAnyPayoff, with the tabulated control variate or not); nullptr for a
+// combination that does not exist.  Defined here, instantiated once per
+// variant.
 template <int MODEL>
-PersistentFn pick_persistent_variant(int M, int ppt, int payoff)
+PersistentFn pick_persistent_variant(int M, int ppt, int payoff, bool cv)
 {
     if (M == 2) {
         switch (ppt) {
-        case 1: return pick_persistent_payoff<MODEL, 2, 1>(payoff);
-        case 2: return pick_persistent_payoff<MODEL, 2, 2>(payoff);
-        default: return pick_persistent_payoff<MODEL, 2, 4>(payoff);
+        case 1: return pick_persistent_payoff<MODEL, 2, 1>(payoff, cv);
+        case 2: return pick_persistent_payoff<MODEL, 2, 2>(payoff, cv);
+        default: return pick_persistent_payoff<MODEL, 2, 4>(payoff, cv);
         }
     }
     switch (ppt) {
-    case 1: return pick_persistent_payoff<MODEL, 4, 1>(payoff);
-    case 2: return pick_persistent_payoff<MODEL, 4, 2>(payoff);
-    default: return pick_persistent_payoff<MODEL, 4, 4>(payoff);
+    case 1: return pick_persistent_payoff<MODEL, 4, 1>(payoff, cv);
+    case 2: return pick_persistent_payoff<MODEL, 4, 2>(payoff, cv);
+    default: return pick_persistent_payoff<MODEL, 4, 4>(payoff, cv);
     }
 }
 }  // namespace mlmc

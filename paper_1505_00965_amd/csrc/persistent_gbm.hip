@@ -3,6 +3,6 @@
 
 namespace mlmc {
 
-template PersistentFn pick_persistent_variant<kGBM>(int, int, int);
+template PersistentFn pick_persistent_variant<kGBM>(int, int, int, bool);
 
 }  // namespace mlmc

@@ -3,6 +3,6 @@
 
 namespace mlmc {
 
-template PersistentFn pick_persistent_variant<kHeston>(int, int, int);
+template PersistentFn pick_persistent_variant<kHeston>(int, int, int, bool);
 
 }  // namespace mlmc

@@ -216,7 +216,7 @@ def test_run_with_control_variate(gctx, orc):
     assert np.sqrt(np.mean(np.square(errs))) < 1.35 * eps
     with pytest.raises(mlmc.MLMCError):
         gctx.mlmc_run(gm, gp, eps, cv=cv, precision=64)
-    with pytest.raises(mlmc.MLMCError):
+    with pytest.raises(mlmc.MLMCError):     # the device-planned form takes the table
         gctx.mlmc_run(gm, gp, eps, cv=cv, persistent=True)
     with pytest.raises(mlmc.MLMCError):     # Heston needs a 3-input network
         gctx.mlmc_level(mlmc.model(**W.HESTON_MODEL), gp, 1, 4, 100, 1, cv=cv)

@@ -122,3 +122,45 @@ def test_trained_table_removes_the_networks_variance(gctx, kind, pname):
     # network's reduction (coarsest on Heston's three-input grid)
     assert all(r < 1.25 for r in ratios), ratios
     cv.close()
+
+
+@pytest.mark.parametrize("kind,pname,M,cv_levels,eps", [(0, "asian", 4, 0, 0.05), (1, "call", 4, 0, 0.1),
+                                                        (0, "call", 2, 0, 0.05), (0, "lookback", 4, 2, 0.1),
+                                                        (0, "digital", 4, 0, 0.5)])
+def test_device_planned_run_with_table_matches_per_level_run(gctx, orc, kind, pname, M, cv_levels, eps):
+    """The device-planned form with the tabulated control variate computes
+    every sample as the per-level kernels do (level 0 with phi(0, S0), the
+    level's rows in LDS, split GBM paths, two-step samples at M = 2), so the
+    two forms take the same decisions and their sums agree up to fp64
+    summation order."""
+    gm, om, cv, g, otab, ocv = setup(gctx, orc, kind)
+    gp = mlmc.payoff(**W.PAYOFFS[pname])
+    kw = dict(M=M, L_min=2, L_max=6, n_pilot=3000, seed=5, cv=cv, cv_levels=cv_levels)
+    a = gctx.mlmc_run(gm, gp, eps, persistent=0, **kw)
+    b = gctx.mlmc_run(gm, gp, eps, persistent=1, **kw)
+    print(f"PLANNEDCV kind={kind} payoff={pname} M={M} L={a['L']} N={a['N']} it={a['iterations']}",
+          flush=True)
+    assert a["N"] == b["N"] and a["L"] == b["L"] and a["iterations"] == b["iterations"]
+    for k in ("sum_y", "sum_y2"):
+        for x, y in zip(a[k], b[k]):
+            assert abs(x - y) <= 1e-10 * max(abs(x), abs(y), 1e-300), (k, x, y)
+    assert abs(a["estimate"] - b["estimate"]) <= 1e-10 * abs(a["estimate"])
+    # a second planned run reuses the table and the descriptor
+    c = gctx.mlmc_run(gm, gp, eps, persistent=1, **kw)
+    assert c["N"] == b["N"] and c["estimate"] == b["estimate"]
+    cv.close()
+
+
+def test_device_planned_run_takes_only_the_table(gctx, orc):
+    gm, om, cv, g, otab, ocv = setup(gctx, orc, 0)
+    gp = mlmc.payoff(**W.CALL)
+    cv.set_tabulated(False)
+    with pytest.raises(mlmc.MLMCError) as e:
+        gctx.mlmc_run(gm, gp, 0.05, M=4, cv=cv, persistent=1)
+    assert e.value.status == mlmc.MLMC_EINVAL
+    cv.set_tabulated(True)
+    with pytest.raises(mlmc.MLMCError):     # Milstein paths: no control variate
+        gctx.mlmc_run(mlmc.model(**dict(W.GBM_MODEL, scheme=1)), gp, 0.05, M=4, cv=cv, persistent=1)
+    r = gctx.mlmc_run(gm, gp, 0.05, M=4, cv=cv, persistent=1)
+    assert r["converged"]
+    cv.close()
