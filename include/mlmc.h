@@ -310,8 +310,10 @@ typedef struct {
                             enqueues each iteration before the previous
                             update is read (the device plans every batch)  */
     double alpha, beta;  /* assumed weak and variance rates (<= 0: 1 and 1) */
-    const mlmc_cv* cv;   /* NULL: plain MLMC.  Needs precision 32 and
-                            persistent 0 (MLMC_EINVAL otherwise).             */
+    const mlmc_cv* cv;   /* NULL: plain MLMC.  Needs precision 32, Euler
+                            paths without the twin and a plain payoff; with
+                            persistent 1 the tabulated form only
+                            (mlmc_cv_set_tabulated; MLMC_EINVAL otherwise). */
     int cv_levels;       /* with cv: apply it on levels l < cv_levels only
                             (0 = every level).  Each level estimator keeps its
                             mean either way, so any split is unbiased; level 0
