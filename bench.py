@@ -58,8 +58,8 @@ KERNEL_SOURCES = {
     "level": ("philox.hpp", "sampler.hpp", "sampler_impl.hpp", "reduce.hpp", "level.hip",
               "level.hpp", "level_kernels.hpp", "level_gbm.hip"),
     "persistent": ("philox.hpp", "sampler.hpp", "sampler_impl.hpp", "reduce.hpp", "level.hpp",
-                   "driver.hpp", "driver_dev.hpp", "persistent.hpp", "persistent.hip",
-                   "persistent_gbm.hip"),
+                   "driver.hpp", "driver_dev.hpp", "cv.hpp", "cv_tab.hpp", "persistent.hpp",
+                   "persistent.hip", "persistent_gbm.hip"),
 }
 
 
