@@ -350,10 +350,15 @@ __global__ void cv_weights_kernel(const LevelAcc* rec, const double* ydump, uint
 // Backward pass over the samples of one level (one wave per block): the
 // same paths as the forward pass, regenerated from their counters; every
 // evaluation point contributes with g = -w dW1 (fine) or +w dW1c (coarse).
+// A path's generator groups are cut into `segs` runs of whole groups, one
+// block per (64 samples, run): a block advances its paths from the start
+// (a plain step costs ~20 instructions, an evaluation point with its
+// backward pass thousands) and evaluates only the points of its run, so a
+// deep level's few samples still fill the device.
 template <int MODEL, int PAYOFF, int M>
 __global__ __launch_bounds__(64) void cv_backward_kernel(LevelArgs<float> a, CvKernelArgs c,
                                                           const bf16x8* abwd, const float* w,
-                                                          float* gpart)
+                                                          float* gpart, uint32_t segs)
 {
     constexpr int D = (MODEL == kGBM) ? 2 : 3;
     __shared__ NetShared sh;
@@ -371,15 +376,19 @@ __global__ __launch_bounds__(64) void cv_backward_kernel(LevelArgs<float> a, CvK
     const bool coupled = a.l > 0;
     const int lane = threadIdx.x & 63;
     const uint64_t nchunks = (a.N + 63) / 64;
-    for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const uint32_t per_seg = a.ngroups / segs;      // segs divides ngroups (host)
+    for (uint64_t b = blockIdx.x; b < nchunks * segs; b += gridDim.x) {
+        const uint64_t ch = b / segs;
+        const uint32_t g0 = (uint32_t)(b % segs) * per_seg, g1 = g0 + per_seg;
         const uint64_t idx = ch * 64 + lane;
         const uint64_t s = a.offset + idx;
         const float wp = idx < a.N ? w[idx] : 0.0f;
         PathPair<float> q;
         init_pair<float, MODEL, PAYOFF>(q, P);
-        for (uint32_t g = 0; g < a.ngroups; ++g) {
+        for (uint32_t g = 0; g < g1; ++g) {
             float dw1[4], dwp[4], e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             fetch_group<MODEL, PAYOFF>(a, s, g, dw1, dwp, e);
+            const bool eval = g >= g0;                      // block-uniform
 #pragma unroll 1
             for (int k = 0; k < 4; ++k) {
                 const int n = 4 * (int)g + k;
@@ -387,13 +396,15 @@ __global__ __launch_bounds__(64) void cv_backward_kernel(LevelArgs<float> a, CvK
                 const float d1 = k == 0 ? dw1[0] : k == 1 ? dw1[1] : k == 2 ? dw1[2] : dw1[3];
                 const float dp = k == 0 ? dwp[0] : k == 1 ? dwp[1] : k == 2 ? dwp[2] : dwp[3];
                 const float ek = k == 0 ? e[0] : k == 1 ? e[1] : k == 2 ? e[2] : e[3];
-                const float x0 = (float)n * P.h * sh.inv_T;
-                eval_backward<D>(sh, afw, abw, st, x0, q.S, q.v, -wp * d1, acc);
-                if (coupled && (n & (M - 1)) == 0) {
-                    // the coarse step starting here sums the next M fine increments
-                    const float dwc = (M == 4) ? dw1[0] + dw1[1] + dw1[2] + dw1[3]
-                                               : (k == 0 ? dw1[0] + dw1[1] : dw1[2] + dw1[3]);
-                    eval_backward<D>(sh, afw, abw, st, x0, q.Sc, q.vc, wp * dwc, acc);
+                if (eval) {
+                    const float x0 = (float)n * P.h * sh.inv_T;
+                    eval_backward<D>(sh, afw, abw, st, x0, q.S, q.v, -wp * d1, acc);
+                    if (coupled && (n & (M - 1)) == 0) {
+                        // the coarse step starting here sums the next M fine increments
+                        const float dwc = (M == 4) ? dw1[0] + dw1[1] + dw1[2] + dw1[3]
+                                                   : (k == 0 ? dw1[0] + dw1[1] : dw1[2] + dw1[3]);
+                        eval_backward<D>(sh, afw, abw, st, x0, q.Sc, q.vc, wp * dwc, acc);
+                    }
                 }
                 fine_step<float, MODEL, PAYOFF>(q, P, d1, dp, ek, n & (M - 1), coupled);
                 if (coupled && ((n + 1) & (M - 1)) == 0) coarse_step<float, MODEL, PAYOFF>(q, P);
@@ -442,14 +453,32 @@ __global__ __launch_bounds__(64) void cv_backward_kernel(LevelArgs<float> a, CvK
             }
 }
 
-// grad[i] = sum over the partial rows (fixed order).
+// grad[i] = sum over the partial rows (fixed order): rows [r0, r1) of the
+// partials into one row, with the loads of a thread issued ahead of its adds.
 __global__ void cv_reduce_kernel(const float* gpart, int rows, int np, float* grad)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     float s = 0.0f;
+#pragma unroll 8
     for (int r = 0; r < rows; ++r) s += gpart[(uint64_t)r * np + i];
     grad[i] = s;
+}
+
+// First pass of the reduction: chunk blockIdx.y of kReduceRows rows into row
+// blockIdx.y of `partial` (the second pass, cv_reduce_kernel, adds those rows
+// in order; the whole sum keeps one fixed order).
+constexpr int kReduceRows = 32;
+__global__ void cv_reduce_rows_kernel(const float* gpart, int rows, int np, float* partial)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int r0 = blockIdx.y * kReduceRows;
+    const int r1 = r0 + kReduceRows < rows ? r0 + kReduceRows : rows;
+    float s = 0.0f;
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) s += gpart[(uint64_t)r * np + i];
+    partial[(uint64_t)blockIdx.y * np + i] = s;
 }
 
 // Adam (Kingma and Ba 2015) on the fp32 master parameters.
@@ -468,7 +497,7 @@ __global__ void cv_adam_kernel(float* params, float* m1, float* m2, const float*
 
 // ----------------------------------------------------------- dispatch
 using CvFn = void (*)(LevelArgs<float>, CvKernelArgs);
-using CvBwdFn = void (*)(LevelArgs<float>, CvKernelArgs, const bf16x8*, const float*, float*);
+using CvBwdFn = void (*)(LevelArgs<float>, CvKernelArgs, const bf16x8*, const float*, float*, uint32_t);
 
 template <int MODEL, int PAYOFF>
 static CvBwdFn pick_bwd_m(int M)
@@ -658,12 +687,43 @@ hipError_t cv_launch_level(const mlmc_cv* ccv, const mlmc_model& m, const mlmc_p
     return hipGetLastError();
 }
 
+// The backward launch of level l for a batch of B: segments per path (a
+// power of two dividing the level's generator groups, so that the level
+// has about kBwdBlocks blocks of 64 samples x segment) and its grid.
+constexpr uint64_t kBwdBlocks = 2048;
+struct BwdShape {
+    uint32_t segs;
+    int grid;
+};
+static BwdShape bwd_shape(uint64_t B, int l, int M)
+{
+    uint64_t nf = 1;
+    for (int i = 0; i < l; ++i) nf *= (uint64_t)M;
+    const uint64_t groups = (nf + 3) / 4, nchunks = (B + 63) / 64;
+    uint32_t segs = 1;
+    while ((uint64_t)segs * 2 <= groups && groups % ((uint64_t)segs * 2) == 0 &&
+           nchunks * segs * 2 <= kBwdBlocks)
+        segs *= 2;
+    const uint64_t units = nchunks * segs;
+    return BwdShape{segs, (int)(units < kBwdBlocks ? units : kBwdBlocks)};
+}
+
+// Rows of per-block gradient partials of one training step, and the
+// reduction's first-pass rows after them (the gradient is the row after).
+static int bwd_rows(uint64_t B, int lmax, int M)
+{
+    int rows = 0;
+    for (int l = 0; l <= lmax; ++l) rows += bwd_shape(B, l, M).grid;
+    return rows;
+}
+
 // Scratch for a training batch of B samples per level, levels 0..lmax.
-static mlmc_status ensure_train(mlmc_cv* cv, uint64_t B, int lmax)
+static mlmc_status ensure_train(mlmc_cv* cv, uint64_t B, int lmax, int M)
 {
     mlmc_ctx* ctx = cv->ctx;
     const uint64_t need = B * (uint64_t)(lmax + 1);
-    const int rows = (int)(((B + 63) / 64 < 512 ? (B + 63) / 64 : 512) * (lmax + 1));
+    const int brows = bwd_rows(B, lmax, M);
+    const int rows = brows + (brows + kReduceRows - 1) / kReduceRows;
     if (cv->batch_cap < need) {
         if (cv->d_y) hipFree(cv->d_y);
         if (cv->d_w) hipFree(cv->d_w);
@@ -690,7 +750,7 @@ static mlmc_status enqueue_loss_grad(mlmc_cv* cv, const mlmc_model& m, const mlm
                                      LevelAcc* rec, float** grad_out)
 {
     mlmc_ctx* ctx = cv->ctx;
-    mlmc_status st = ensure_train(cv, B, lmax);
+    mlmc_status st = ensure_train(cv, B, lmax, M);
     if (st) return st;
     MLMC_HIP(ctx, zero_records(rec, lmax + 1, ctx->stream));
     MLMC_HIP(ctx, hipMemsetAsync(cv->d_loss, 0, sizeof(double) * 64, ctx->stream));
@@ -705,7 +765,6 @@ static mlmc_status enqueue_loss_grad(mlmc_cv* cv, const mlmc_model& m, const mlm
                        (const LevelAcc*)rec, (const double*)cv->d_y, B, M, cv->d_w, cv->d_loss);
     MLMC_HIP(ctx, hipGetLastError());
     CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
-    const int per_level = (int)((B + 63) / 64 < 512 ? (B + 63) / 64 : 512);
     int row0 = 0;
     const int tix = timed_begin(ctx, 18, 0.0, 0.0);
     for (int l = 0; l <= lmax; ++l) {
@@ -726,15 +785,22 @@ static mlmc_status enqueue_loss_grad(mlmc_cv* cv, const mlmc_model& m, const mlm
         a.phi0 = nullptr;
         CvBwdFn fn = m.kind == MLMC_GBM ? pick_bwd_payoff<kGBM>(p.kind, M)
                                         : pick_bwd_payoff<kHeston>(p.kind, M);
-        hipLaunchKernelGGL(fn, dim3(per_level), dim3(64), 0, ctx->stream, a, c,
+        const BwdShape bs = bwd_shape(B, l, M);
+        hipLaunchKernelGGL(fn, dim3(bs.grid), dim3(64), 0, ctx->stream, a, c,
                            (const bf16x8*)cv->d_abwd, (const float*)(cv->d_w + (uint64_t)l * B),
-                           cv->d_gpart + (uint64_t)row0 * cv->np);
+                           cv->d_gpart + (uint64_t)row0 * cv->np, bs.segs);
         MLMC_HIP(ctx, hipGetLastError());
-        row0 += per_level;
+        row0 += bs.grid;
     }
-    float* grad = cv->d_gpart + (uint64_t)row0 * cv->np;
+    // two passes in a fixed order: chunks of kReduceRows rows, then the chunks
+    const int nchunk = (row0 + kReduceRows - 1) / kReduceRows;
+    float* partial = cv->d_gpart + (uint64_t)row0 * cv->np;
+    float* grad = partial + (uint64_t)nchunk * cv->np;
+    hipLaunchKernelGGL(cv_reduce_rows_kernel, dim3((cv->np + 255) / 256, nchunk), dim3(256), 0,
+                       ctx->stream, (const float*)cv->d_gpart, row0, cv->np, partial);
+    MLMC_HIP(ctx, hipGetLastError());
     hipLaunchKernelGGL(cv_reduce_kernel, dim3((cv->np + 255) / 256), dim3(256), 0, ctx->stream,
-                       (const float*)cv->d_gpart, row0, cv->np, grad);
+                       (const float*)partial, nchunk, cv->np, grad);
     MLMC_HIP(ctx, hipGetLastError());
     timed_end(ctx, tix);
     *grad_out = grad;

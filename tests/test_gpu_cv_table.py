@@ -145,9 +145,10 @@ def test_device_planned_run_with_table_matches_per_level_run(gctx, orc, kind, pn
         for x, y in zip(a[k], b[k]):
             assert abs(x - y) <= 1e-10 * max(abs(x), abs(y), 1e-300), (k, x, y)
     assert abs(a["estimate"] - b["estimate"]) <= 1e-10 * abs(a["estimate"])
-    # a second planned run reuses the table and the descriptor
+    # a second planned run reuses the table and the descriptor (the fp64
+    # atomics add in another order)
     c = gctx.mlmc_run(gm, gp, eps, persistent=1, **kw)
-    assert c["N"] == b["N"] and c["estimate"] == b["estimate"]
+    assert c["N"] == b["N"] and abs(c["estimate"] - b["estimate"]) <= 1e-10 * abs(b["estimate"])
     cv.close()
 
 
