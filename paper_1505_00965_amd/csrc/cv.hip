@@ -50,6 +50,8 @@ struct mlmc_cv {
     float* d_w = nullptr;         // per-sample loss weights
     double* d_loss = nullptr;     // loss and per-level variances
     uint64_t batch_cap = 0;
+    float* d_fpart = nullptr;     // forward runs' partial sums of one level
+    uint64_t fpart_cap = 0;       // floats allocated
 };
 
 namespace mlmc {
@@ -316,6 +318,90 @@ __global__ __launch_bounds__(256) void cv_tab_short_kernel(LevelArgs<float> a, c
     block_reduce_add(sums, nonfinite, a.acc + (blockIdx.x & a.spread_mask));
 }
 
+// Training forward of a deep level in runs (as the backward pass cuts it):
+// block (64 samples, run r) advances its paths from the start, evaluates
+// the network at the points of its run only, and writes its fp32 sums of
+// phi dW1 on the fine and the coarse path to part[2r][i], part[2r+1][i];
+// the last run also writes the two payoffs to part[2 segs], part[2 segs + 1].
+// cv_train_combine_kernel then forms Y (payoff minus the runs' sums, added
+// in run order), the per-sample dumps and the level sums.
+template <int MODEL, int PAYOFF, int M>
+__global__ __launch_bounds__(64) void cv_train_fwd_kernel(LevelArgs<float> a, CvKernelArgs c, uint32_t segs,
+                                                          float* part)
+{
+    constexpr int D = (MODEL == kGBM) ? 2 : 3;
+    __shared__ NetShared sh;
+    __shared__ bf16x8 s_afwd[8 * 64];
+    load_shared<D>(sh, c.params, c.nc);
+    for (int i = threadIdx.x; i < 8 * 64; i += blockDim.x) s_afwd[i] = c.afwd[i];
+    __syncthreads();
+    const StepParams<float>& P = a.P;
+    const uint64_t nchunks = (a.N + 63) / 64;
+    const uint32_t per_seg = a.ngroups / segs;      // segs divides ngroups (host)
+    for (uint64_t b = blockIdx.x; b < nchunks * segs; b += gridDim.x) {
+        const uint64_t ch = b / segs;
+        const uint32_t r = (uint32_t)(b % segs), g0 = r * per_seg, g1 = g0 + per_seg;
+        const uint64_t idx = ch * 64 + threadIdx.x;
+        const uint64_t s = a.offset + idx;
+        PathPair<float> q;
+        init_pair<float, MODEL, PAYOFF>(q, P);
+        float phic = 0.0f;
+        for (uint32_t g = 0; g < g1; ++g) {
+            float dw1[4], dwp[4], e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            fetch_group<MODEL, PAYOFF>(a, s, g, dw1, dwp, e);
+            const bool eval = g >= g0;                      // block-uniform
+#pragma unroll 1
+            for (int k = 0; k < 4; ++k) {
+                const int n = 4 * (int)g + k;
+                if (n >= a.nf) break;                       // wave-uniform
+                const float d1 = k == 0 ? dw1[0] : k == 1 ? dw1[1] : k == 2 ? dw1[2] : dw1[3];
+                const float dp = k == 0 ? dwp[0] : k == 1 ? dwp[1] : k == 2 ? dwp[2] : dwp[3];
+                const float ek = k == 0 ? e[0] : k == 1 ? e[1] : k == 2 ? e[2] : e[3];
+                if (eval) {
+                    const float x0 = (float)n * P.h * sh.inv_T;
+                    const float phif = phi_eval<D>(sh, s_afwd, x0, q.S, q.v);
+                    q.cvf = __builtin_fmaf(phif, d1, q.cvf);
+                    if ((n & (M - 1)) == 0) phic = phi_eval<D>(sh, s_afwd, x0, q.Sc, q.vc);
+                }
+                fine_step<float, MODEL, PAYOFF>(q, P, d1, dp, ek, n & (M - 1), true);
+                if (((n + 1) & (M - 1)) == 0) {
+                    if (eval) q.cvc = __builtin_fmaf(phic, q.dw1c, q.cvc);
+                    coarse_step<float, MODEL, PAYOFF>(q, P);
+                }
+            }
+        }
+        if (idx < a.N) {
+            part[(uint64_t)(2 * r) * a.N + idx] = q.cvf;
+            part[(uint64_t)(2 * r + 1) * a.N + idx] = q.cvc;
+            if (r + 1 == segs) {
+                part[(uint64_t)(2 * segs) * a.N + idx] =
+                    payoff_value<float, PAYOFF>(P, q.S, q.asum, q.acomp, q.mn, P.h);
+                part[(uint64_t)(2 * segs + 1) * a.N + idx] =
+                    payoff_value<float, PAYOFF>(P, q.Sc, q.csum, q.ccomp, q.mnc, P.H);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void cv_train_combine_kernel(LevelArgs<float> a, uint32_t segs,
+                                                               const float* part)
+{
+    double sums[kNumSums] = {0, 0, 0, 0, 0, 0};
+    unsigned nonfinite = 0;
+    for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < a.N;
+         idx += (uint64_t)gridDim.x * blockDim.x) {
+        float cf = 0.0f, cc = 0.0f;
+        for (uint32_t r = 0; r < segs; ++r) {
+            cf += part[(uint64_t)(2 * r) * a.N + idx];
+            cc += part[(uint64_t)(2 * r + 1) * a.N + idx];
+        }
+        const float pf = part[(uint64_t)(2 * segs) * a.N + idx] - cf;
+        const float pc = part[(uint64_t)(2 * segs + 1) * a.N + idx] - cc;
+        accumulate(a, idx, pf, pc, sums, nonfinite);
+    }
+    block_reduce_add(sums, nonfinite, a.acc);
+}
+
 // ------------------------------------------------------------ training
 // Loss over levels 0..lmax (the MLMC cost functional; total cost scales as
 // (sum_l sqrt(V_l C_l))^2):  loss = sum_l sqrt(C_l Var_batch(Y_l)),
@@ -498,6 +584,19 @@ __global__ void cv_adam_kernel(float* params, float* m1, float* m2, const float*
 // ----------------------------------------------------------- dispatch
 using CvFn = void (*)(LevelArgs<float>, CvKernelArgs);
 using CvBwdFn = void (*)(LevelArgs<float>, CvKernelArgs, const bf16x8*, const float*, float*, uint32_t);
+using CvTrainFwdFn = void (*)(LevelArgs<float>, CvKernelArgs, uint32_t, float*);
+
+template <int MODEL>
+static CvTrainFwdFn pick_train_fwd(int payoff, int M)
+{
+    switch (payoff) {
+    case kCall: return M == 2 ? cv_train_fwd_kernel<MODEL, kCall, 2> : cv_train_fwd_kernel<MODEL, kCall, 4>;
+    case kAsian: return M == 2 ? cv_train_fwd_kernel<MODEL, kAsian, 2> : cv_train_fwd_kernel<MODEL, kAsian, 4>;
+    case kLookback:
+        return M == 2 ? cv_train_fwd_kernel<MODEL, kLookback, 2> : cv_train_fwd_kernel<MODEL, kLookback, 4>;
+    default: return M == 2 ? cv_train_fwd_kernel<MODEL, kDigital, 2> : cv_train_fwd_kernel<MODEL, kDigital, 4>;
+    }
+}
 
 template <int MODEL, int PAYOFF>
 static CvBwdFn pick_bwd_m(int M)
@@ -733,6 +832,19 @@ static mlmc_status ensure_train(mlmc_cv* cv, uint64_t B, int lmax, int M)
         MLMC_HIP(ctx, hipMalloc(&cv->d_w, sizeof(float) * need));
         cv->batch_cap = need;
     }
+    // the forward runs' partials of the level with the most runs
+    uint64_t fneed = 0;
+    for (int l = 0; l <= lmax; ++l) {
+        const uint64_t segs = bwd_shape(B, l, M).segs;
+        if (segs > 1 && (2 * segs + 2) * B > fneed) fneed = (2 * segs + 2) * B;
+    }
+    if (cv->fpart_cap < fneed) {
+        if (cv->d_fpart) hipFree(cv->d_fpart);
+        cv->d_fpart = nullptr;
+        cv->fpart_cap = 0;
+        MLMC_HIP(ctx, hipMalloc(&cv->d_fpart, sizeof(float) * fneed));
+        cv->fpart_cap = fneed;
+    }
     if (cv->gpart_blocks < rows + 1) {
         if (cv->d_gpart) hipFree(cv->d_gpart);
         cv->d_gpart = nullptr;
@@ -740,6 +852,30 @@ static mlmc_status ensure_train(mlmc_cv* cv, uint64_t B, int lmax, int M)
         cv->gpart_blocks = rows + 1;
     }
     return MLMC_OK;
+}
+
+// Kernel arguments of level l of a training batch (the training streams;
+// fetch_group forms every counter from the sample index, so no counter words
+// are set).
+static LevelArgs<float> train_args(const mlmc_model& m, const mlmc_payoff& p, int l, int M, uint64_t B,
+                                   uint64_t seed, uint64_t offset)
+{
+    LevelArgs<float> a;
+    a.P = make_step_params<float>(m, p, l, M);
+    a.seed = seed;
+    a.offset = offset;
+    a.N = B;
+    a.l = l;
+    int nf = 1;
+    for (int i = 0; i < l; ++i) nf *= M;
+    a.nf = nf;
+    a.ngroups = (uint32_t)((nf + 3) / 4);
+    a.stream = kStreamTrainNormal;
+    a.acc = nullptr;
+    a.pf_out = a.pc_out = nullptr;
+    a.coupled = 1;
+    a.phi0 = nullptr;
+    return a;
 }
 
 // One loss/gradient evaluation: forward pass with per-sample dumps, weights,
@@ -755,34 +891,39 @@ static mlmc_status enqueue_loss_grad(mlmc_cv* cv, const mlmc_model& m, const mlm
     MLMC_HIP(ctx, zero_records(rec, lmax + 1, ctx->stream));
     MLMC_HIP(ctx, hipMemsetAsync(cv->d_loss, 0, sizeof(double) * 64, ctx->stream));
     const uint64_t offset = step * B;
+    CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
     for (int l = 0; l <= lmax; ++l) {
         double* pf = cv->d_y + 2 * (uint64_t)l * B;
-        st = enqueue_level(ctx, m, p, l, M, B, seed, offset, 32, kStreamTrainNormal, 1, &rec[l], pf,
-                           pf + B, cv);
-        if (st) return st;
+        const BwdShape bs = bwd_shape(B, l, M);
+        if (bs.segs == 1) {
+            // one sample per lane (the sampler's own launch)
+            st = enqueue_level(ctx, m, p, l, M, B, seed, offset, 32, kStreamTrainNormal, 1, &rec[l],
+                               pf, pf + B, cv);
+            if (st) return st;
+            continue;
+        }
+        // a deep level in runs of generator groups, as the backward pass
+        LevelArgs<float> a = train_args(m, p, l, M, B, seed, offset);
+        a.acc = &rec[l];
+        a.pf_out = pf;
+        a.pc_out = pf + B;
+        a.coupled = 1;
+        const CvTrainFwdFn fwd = m.kind == MLMC_GBM ? pick_train_fwd<kGBM>(p.kind, M)
+                                                    : pick_train_fwd<kHeston>(p.kind, M);
+        hipLaunchKernelGGL(fwd, dim3(bs.grid), dim3(64), 0, ctx->stream, a, c, bs.segs, cv->d_fpart);
+        MLMC_HIP(ctx, hipGetLastError());
+        const int cgrid = (int)((B + 255) / 256 < 256 ? (B + 255) / 256 : 256);
+        hipLaunchKernelGGL(cv_train_combine_kernel, dim3(cgrid), dim3(256), 0, ctx->stream, a, bs.segs,
+                           (const float*)cv->d_fpart);
+        MLMC_HIP(ctx, hipGetLastError());
     }
     hipLaunchKernelGGL(cv_weights_kernel, dim3(lmax + 1), dim3(256), 0, ctx->stream,
                        (const LevelAcc*)rec, (const double*)cv->d_y, B, M, cv->d_w, cv->d_loss);
     MLMC_HIP(ctx, hipGetLastError());
-    CvKernelArgs c{cv->d_params, cv->d_afwd, net_consts(m), cv->D};
     int row0 = 0;
     const int tix = timed_begin(ctx, 18, 0.0, 0.0);
     for (int l = 0; l <= lmax; ++l) {
-        LevelArgs<float> a;
-        a.P = make_step_params<float>(m, p, l, M);
-        a.seed = seed;
-        a.offset = offset;
-        a.N = B;
-        a.l = l;
-        int nf = 1;
-        for (int i = 0; i < l; ++i) nf *= M;
-        a.nf = nf;
-        a.ngroups = (uint32_t)((nf + 3) / 4);
-        a.stream = kStreamTrainNormal;
-        a.acc = nullptr;
-        a.pf_out = a.pc_out = nullptr;
-        a.coupled = 1;
-        a.phi0 = nullptr;
+        const LevelArgs<float> a = train_args(m, p, l, M, B, seed, offset);
         CvBwdFn fn = m.kind == MLMC_GBM ? pick_bwd_payoff<kGBM>(p.kind, M)
                                         : pick_bwd_payoff<kHeston>(p.kind, M);
         const BwdShape bs = bwd_shape(B, l, M);
@@ -849,7 +990,7 @@ mlmc_status mlmc_cv_destroy(mlmc_cv* cv)
     if (cv->ctx) hipSetDevice(cv->ctx->device);
     for (void* p : {(void*)cv->d_params, (void*)cv->d_m1, (void*)cv->d_m2, (void*)cv->d_afwd,
                     (void*)cv->d_abwd, (void*)cv->d_phi0, (void*)cv->d_gpart, (void*)cv->d_y,
-                    (void*)cv->d_w, (void*)cv->d_loss, (void*)cv->d_table})
+                    (void*)cv->d_w, (void*)cv->d_loss, (void*)cv->d_table, (void*)cv->d_fpart})
         if (p) hipFree(p);
     delete cv;
     return MLMC_OK;
