@@ -242,30 +242,70 @@ __device__ __forceinline__ void driver_update_wave(DriverState& s)
 // The update is a chain of a few hundred dependent fp64 operations on the
 // state, so the state is staged in LDS (a global round trip per access
 // would dominate), updated by the first wave (one lane per level), and
-// written back.  The same words go
-// to the host's pinned mirror (if any): everything before the batch records
-// but `seq` first, then a system-scope fence, then `seq` (there 2 x the
-// update count + the done flag), so a host that sees the new word sees the
-// whole update, and the done flag of that same update.  With mirror_each
-// false only the finishing update writes the whole mirror; the others write
-// `seq` alone (for a host that reads the state at the end only).  Once the state is done the call
-// does nothing (no write, `seq` unchanged), so launches queued past the last
-// update are harmless.  With `spread` (kMaxLevels spread
-// groups, one per level) the block first folds each sampled level's group
-// into batch[l] (the sums of Y and Y^2 and the non-finite count), one wave
-// per level, and clears it.  With `init` the state is built fresh in `s`
-// instead of read (the first update of a run whose groups hold only the
-// pilot's sums).  Every thread of the block must call it; `s` is
-// the block's LDS copy of the state.
-__device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s,
-                                                    LevelAcc* spread, const DriverInit* init = nullptr,
-                                                    bool mirror_each = true)
+// written back.  update_state and publish_state are its last two steps;
+// driver_update_block is the whole update of the per-level form, and the
+// device-planned form's kernel (persistent.hip) composes the steps itself.
+
+// The first wave updates `s` (LDS) and counts the update; ends with a barrier.
+__device__ __forceinline__ void update_state(DriverState& s)
+{
+    if (threadIdx.x < 64) driver_update_wave(s);
+    if (threadIdx.x == 0) s.seq += 1;
+    __syncthreads();
+}
+
+// Write the updated state `s` back to `st`, and to the host's pinned mirror
+// (if any): with mirror_each, or once the state is done, everything before
+// the batch records but `seq` first, then a system-scope fence, then `seq`
+// (there 2 x the update count + the done flag), so a host that sees the new
+// word sees the whole update, and the done flag of that same update;
+// otherwise `seq` alone (for a host that reads the state at the end only).
+// `seq` is a relaxed system-scope store: nothing waits for it, the kernel's
+// end makes it visible.  Every thread of the block must call it.
+__device__ __forceinline__ void publish_state(DriverState* st, DriverState* mirror, const DriverState& s,
+                                              bool mirror_each)
 {
     static_assert(sizeof(DriverState) % 8 == 0, "state is copied in 8-byte words");
     static_assert(offsetof(DriverState, seq) % 8 == 0, "seq is one word");
     static_assert(offsetof(DriverState, batch) % 8 == 0, "batch starts a word");
     constexpr int kWords = sizeof(DriverState) / 8;
     constexpr int kSeq = offsetof(DriverState, seq) / 8;
+    const unsigned long long* w = (const unsigned long long*)&s;
+    // the host waits for the mirror: publish it first; the device copy is
+    // read by the next update only, which the stream orders after this one
+    if (mirror) {
+        // the host never reads the batch records: every word before them
+        constexpr int kMirrorWords = offsetof(DriverState, batch) / 8;
+        static_assert(kSeq < kMirrorWords, "seq precedes the batch records");
+        unsigned long long* h = (unsigned long long*)mirror;
+        if (mirror_each || s.done) {    // block-uniform (LDS after a barrier)
+            for (int i = threadIdx.x; i < kMirrorWords; i += blockDim.x)
+                if (i != kSeq) ((volatile unsigned long long*)h)[i] = w[i];
+            __threadfence_system();
+            __syncthreads();
+        }
+        // the published word carries the done flag beside the update count
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&h[kSeq], 2ull * w[kSeq] + (s.done ? 1ull : 0ull), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    unsigned long long* dst = (unsigned long long*)st;
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = w[i];
+}
+
+// The whole update of the per-level form.  Once the state is done the call
+// does nothing (no write, `seq` unchanged), so launches queued past the last
+// update are harmless.  With `spread` (kMaxLevels spread groups, one per
+// level) the block first folds each sampled level's group into batch[l]
+// (the sums of Y and Y^2 and the non-finite count), one wave per level, and
+// clears it.  With `init` the state is built fresh in `s` instead of read
+// (the first update of a run whose groups hold only the pilot's sums).
+// Every thread of the block must call it; `s` is the block's LDS copy of the
+// state.
+__device__ __forceinline__ void driver_update_block(DriverState* st, DriverState* mirror, DriverState& s,
+                                                    LevelAcc* spread, const DriverInit* init = nullptr)
+{
+    constexpr int kWords = sizeof(DriverState) / 8;
     const unsigned long long* src = (const unsigned long long*)st;
     unsigned long long* w = (unsigned long long*)&s;
     if (init) {
@@ -299,27 +339,41 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
         }
         __syncthreads();
     }
-    if (threadIdx.x < 64) driver_update_wave(s);
-    if (threadIdx.x == 0) s.seq += 1;
-    __syncthreads();
-    // the host waits for the mirror: publish it first; the device copy is
-    // read by the next update only, which the stream orders after this one
-    if (mirror) {
-        // the host never reads the batch records: every word before them
-        constexpr int kMirrorWords = offsetof(DriverState, batch) / 8;
-        static_assert(kSeq < kMirrorWords, "seq precedes the batch records");
-        volatile unsigned long long* h = (volatile unsigned long long*)mirror;
-        if (mirror_each || s.done) {    // block-uniform (LDS after a barrier)
-            for (int i = threadIdx.x; i < kMirrorWords; i += blockDim.x)
-                if (i != kSeq) h[i] = w[i];
-            __threadfence_system();
-            __syncthreads();
+    update_state(s);
+    publish_state(st, mirror, s, true);
+}
+
+// Sums of the spread groups of levels 0..L (sum Y, sum Y^2 and the
+// non-finite count per level, in LDS), one wave per level, in the order
+// driver_update_block folds them; the records are left as they are.
+struct GroupSums {
+    double y[kMaxLevels], y2[kMaxLevels], c[kMaxLevels];
+};
+__device__ __forceinline__ void sum_groups(const LevelAcc* spread, int L, GroupSums& g)
+{
+    static_assert(kSpread == 64, "one lane per record of a group");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = (int)(blockDim.x >> 6);
+    for (int l = wave; l <= L; l += nwaves) {    // wave-uniform
+        const LevelAcc& r = spread[l * kSpread + lane];
+        const double y = wave_sum(r.sum[0]);
+        const double y2 = wave_sum(r.sum[1]);
+        const double c = wave_sum((double)r.n_nonfinite);
+        if (lane == 0) {
+            g.y[l] = y;
+            g.y2[l] = y2;
+            g.c[l] = c;
         }
-        // the published word carries the done flag beside the update count
-        if (threadIdx.x == 0) h[kSeq] = 2ull * w[kSeq] + (s.done ? 1ull : 0ull);
     }
-    unsigned long long* dst = (unsigned long long*)st;
-    for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = w[i];
+}
+
+// Zero the spread groups of levels 0..L (every word of their records).
+__device__ __forceinline__ void clear_groups(LevelAcc* spread, int L)
+{
+    static_assert(sizeof(LevelAcc) % 8 == 0, "records are cleared in 8-byte words");
+    unsigned long long* w = (unsigned long long*)spread;
+    const int n = (L + 1) * kSpread * (int)(sizeof(LevelAcc) / 8);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0ull;
 }
 
 }  // namespace mlmc

@@ -30,52 +30,113 @@
 
 namespace mlmc {
 
+// What the plan reads of the descriptor besides the request: loaded at a
+// kernel's start, so the loads overlap the kernel's other reads.
+struct PlanArgs {
+    int L, M, nslots, dim, split_ok, num_cu;
+    unsigned resident_blocks, chunk, block;
+    int payoff_kind[kMaxSlots];
+    PlanTable* plan;
+    unsigned* head;
+    unsigned* split;
+};
+
+__device__ __forceinline__ PlanArgs plan_args(const BatchDesc* d)
+{
+    PlanArgs a;
+    a.L = d->L;
+    a.M = d->M;
+    a.nslots = d->nslots;
+    a.dim = d->dim;
+    a.split_ok = d->split_ok;
+    a.num_cu = d->num_cu;
+    a.resident_blocks = d->resident_blocks;
+    a.chunk = d->chunk;
+    a.block = d->block;
+#pragma unroll
+    for (int k = 0; k < kMaxSlots; ++k) a.payoff_kind[k] = d->payoff_kind[k];
+    a.plan = d->plan;
+    a.head = d->head;
+    a.split = d->split;
+    return a;
+}
+
+// ceil(a / b) for a < 2^53, b > 0: the fp64 quotient is within one of it.
+__device__ __forceinline__ uint64_t ceil_div_u53(uint64_t a, uint64_t b)
+{
+    uint64_t q = (uint64_t)ceil((double)a / (double)b);
+    if (q * b < a) ++q;
+    else if (q && (q - 1) * b >= a) --q;
+    return q;
+}
+
 // Plan: the first wave sizes the (slot, level) pairs, one lane each, in
-// processing order (deepest level first, then slot), so the independent
-// global reads and the 64-bit divisions run side by side; a wave scan gives
-// each pair its first item, and each lane writes its pair's row of the plan
-// table (the sampler decodes the items from it).  Only the first wave works;
-// every thread of the block may call it.
-__device__ __forceinline__ void plan_body(const BatchDesc* d)
+// processing order (deepest level first, then slot), so the per-pair
+// arithmetic runs side by side; a wave scan gives each pair its first item,
+// and each lane writes its pair's row of the plan table (the sampler decodes
+// the items from it).  dN and off: the outstanding samples and their first
+// index per (slot, level) (device memory, or the driver state in LDS).  Only
+// the first wave works; every thread of the block may call it.  Block sizes
+// and samples per lane are powers of two (the launch shape's rule), and so
+// are the sampler's chunks and split passes: they are cut with masks.
+__device__ __forceinline__ void plan_body(const PlanArgs& a, const double* dN, const double* off)
 {
     static_assert(kPairs == 64, "one lane of the first wave per (slot, level) pair");
     if (threadIdx.x >= 64) return;
-    const int L = d->L, M = d->M, nslots = d->nslots;
+    const int L = a.L, M = a.M, nslots = a.nslots;
     const int p = (int)threadIdx.x;
     const bool valid = p < (L + 1) * nslots;
     const int l = valid ? L - p / nslots : 0, s = valid ? p % nslots : 0;
     double nf = 1.0;
     for (int i = 0; i < l; ++i) nf *= M;   // M^l, exact
     const double per = nf + (l ? nf / M : 0.0);
-    const double dn = valid ? d->dN[s * kMaxLevels + l] : 0.0;
+    const double dn = valid ? dN[s * kMaxLevels + l] : 0.0;
     // samples x steps over the batch (lane 0's sum: the rotations leave
     // other lanes with other association orders)
     const double total = __shfl(wave_sum(valid ? dn * per : 0.0), 0);
-    const double target = total / ((double)d->resident_blocks * kItemsPerBlock);
+    const double target = total / ((double)a.resident_blocks * kItemsPerBlock);
     const uint64_t left = (uint64_t)dn;
+    const uint64_t first = valid ? (uint64_t)off[s * kMaxLevels + l] : 0;
+    uint64_t base = first;
     unsigned items = 0;
     uint64_t per_item = 0;
     if (valid) {
         // lanes per path: the per-level launch's rule on the same count
-        const uint32_t G = split_lanes((int)nf, left, d->num_cu,
-                                       d->split_ok && d->payoff_kind[s] != kDigitalCond);
-        d->split[s * kMaxLevels + l] = G;
+        const uint32_t G = split_lanes((int)nf, left, a.num_cu,
+                                       a.split_ok && a.payoff_kind[s] != kDigitalCond);
+        a.split[s * kMaxLevels + l] = G;
         if (left) {
             uint64_t paths = (uint64_t)(target / per);
+            // samples of one chunk of the sampler: block x ppt samples, or on
+            // one- and two-step levels block x ppt generator blocks of q
+            const uint64_t unit = (uint64_t)a.chunk * (nf < 4 ? (uint64_t)(4 / ((int)nf * a.dim)) : 1ull);
             if (G > 1) {
                 // split paths: whole block passes of block / G paths
-                const uint64_t pass = d->block / G;
-                paths = paths < pass ? pass : (paths / pass) * pass;
-            } else if (paths >= d->chunk) {
-                paths = (paths / d->chunk) * d->chunk;   // whole chunks where possible
-            } else if (paths < d->block) {
-                paths = d->block;                        // one sample per lane at least
+                const uint64_t pass = a.block / G;
+                paths = paths < pass ? pass : paths & ~(pass - 1);
+            } else if (paths >= unit) {
+                paths &= ~(unit - 1);                    // whole chunks where possible
+            } else {
+                // one sample per lane, or one whole chunk, whichever is nearer
+                paths = 2 * paths >= a.block + unit ? unit : a.block;
             }
             if (paths > (1ull << 31)) paths = 1ull << 31;   // item sizes fit 32 bits
-            // at most kItemsPerPair items per pair: item indices stay small
+            // at most kItemsPerPair items per pair (one more when cut on the
+            // chunk grid below): item indices stay small
             const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
             per_item = paths > min_items ? paths : min_items;
-            items = (unsigned)((left + per_item - 1) / per_item);
+            if (G == 1 && per_item > a.block) {
+                // whole chunks (the sampler simulates a whole chunk, the
+                // samples past the item's end included), cut on a grid of
+                // whole chunks from the pair's first sample rounded down:
+                // every piece but the pair's first and last then fills all
+                // its chunks (on one- and two-step levels a partial chunk
+                // also takes per-sample range checks)
+                per_item = (per_item + unit - 1) & ~(unit - 1);
+                base = first & ~(unit - 1);
+            }
+            if (per_item > (1ull << 31)) per_item = (1ull << 31) & ~(unit - 1);
+            items = (unsigned)ceil_div_u53(first + left - base, per_item);
         }
     }
     // inclusive scan of the item counts over the lanes (pair order)
@@ -88,11 +149,12 @@ __device__ __forceinline__ void plan_body(const BatchDesc* d)
     // pairs with samples, packed in order
     const uint64_t active = __ballot(items > 0);
     const int rank = __popcll(active & ((1ull << p) - 1ull));
-    PlanTable* t = d->plan;
+    PlanTable* t = a.plan;
     if (items) {
-        t->first[rank] = (uint64_t)d->offset[s * kMaxLevels + l];
+        t->first[rank] = first;
         t->left[rank] = left;
         t->per[rank] = per_item;
+        t->base[rank] = base;
         t->slot[rank] = (uint8_t)s;
         t->level[rank] = (uint8_t)l;
         t->start[rank] = incl - items;
@@ -101,41 +163,74 @@ __device__ __forceinline__ void plan_body(const BatchDesc* d)
         const int np = __popcll(active);
         t->start[np] = incl;
         t->npairs = np;
-        *d->head = 0;
+        *a.head = 0;
     }
 }
 
-__global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d) { plan_body(d); }
+__global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d)
+{
+    plan_body(plan_args(d), d->dN, d->offset);
+}
 
-// The adaptive run's first kernel: the spread groups cleared, a fresh state
-// (n_pilot samples outstanding on levels 0..L_min), the run's seed into the
-// descriptor, and the pilot batch planned.  The plan reads the state's dN and
-// n, which this block has just written (a barrier orders them).
+// The adaptive run's first kernel: a fresh state (n_pilot samples
+// outstanding on levels 0..L_min) built in LDS and planned from there, the
+// run's seed into the descriptor, then the state written out and the spread
+// groups cleared (the stores last: nothing waits for them).
 __global__ __launch_bounds__(256) void driver_start_kernel(DriverState* st, LevelAcc* spread,
                                                            DriverInit c, BatchDesc* d, uint64_t seed)
 {
-    unsigned long long* g = (unsigned long long*)spread;
-    constexpr int kSpreadWords = kMaxLevels * kSpread * (int)sizeof(LevelAcc) / 8;
-    for (int i = threadIdx.x; i < kSpreadWords; i += blockDim.x) g[i] = 0ull;
-    init_state(*st, c);
+    __shared__ DriverState s;
+    const PlanArgs pa = plan_args(d);
+    init_state(s, c);   // ends with a barrier
+    plan_body(pa, s.dN, s.n);
     if (threadIdx.x == 0) d->seed = seed;
-    __syncthreads();
-    plan_body(d);
+    constexpr int kWords = sizeof(DriverState) / 8;
+    const unsigned long long* w = (const unsigned long long*)&s;
+    unsigned long long* dst = (unsigned long long*)st;
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = w[i];
+    clear_groups(spread, kMaxLevels - 1);
 }
 
-// One iteration's end: fold the spread groups, absorb the batch, re-plan
-// (driver_update_block), then plan the next batch's items.  The host reads
-// the update count every iteration and the state once, at the end: the
-// mirror is written whole by the finishing update only.  A finished state
-// has no outstanding samples, so its plan is empty and a sampler launched
-// after it does nothing.
+// One iteration's end: sum the spread groups, absorb the batch, re-plan
+// (update_state), plan the next batch's items from the new state in LDS,
+// then write the state back and clear the groups.  The host reads the
+// update count every iteration and the state once, at the end: the mirror
+// is written whole by the finishing update only.  The group loads go out
+// beside the state's (the level count comes from the stored state) and the
+// stores come last, so the block waits on memory twice: for the loads and
+// for nothing else.  A finished state has no outstanding samples: the plan
+// its finishing update wrote is empty, so a sampler launched after it does
+// nothing, and an update launched after it returns at once.
 __global__ __launch_bounds__(512) void driver_update_plan_kernel(DriverState* st, DriverState* mirror,
                                                                  LevelAcc* spread, const BatchDesc* d)
 {
     __shared__ DriverState s;
-    driver_update_block(st, mirror, s, spread, nullptr, false);
+    __shared__ GroupSums g;
+    const PlanArgs pa = plan_args(d);
+    // the levels the batch sampled: 0..L of the stored state (the word the
+    // copy below brings into LDS)
+    const int L0 = __builtin_amdgcn_readfirstlane(st->L);
+    sum_groups(spread, L0, g);
+    {
+        constexpr int kWords = sizeof(DriverState) / 8;
+        const unsigned long long* src = (const unsigned long long*)st;
+        unsigned long long* w = (unsigned long long*)&s;
+        for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = src[i];
+    }
     __syncthreads();
-    plan_body(d);
+    if (s.done) return;   // block-uniform (LDS after a barrier)
+    // absorb the groups into the batch records (held at zero between updates)
+    if ((int)threadIdx.x <= L0) {
+        const int l = (int)threadIdx.x;
+        s.batch[l].sum[0] += g.y[l];
+        s.batch[l].sum[1] += g.y2[l];
+        s.batch[l].n_nonfinite += (unsigned long long)g.c[l];
+    }
+    __syncthreads();
+    update_state(s);   // ends with a barrier
+    plan_body(pa, s.dN, s.n);
+    publish_state(st, mirror, s, false);
+    clear_groups(spread, L0);
 }
 
 // Fold each spread group (kSpread records) into one record, group g by
@@ -263,6 +358,7 @@ static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const ml
     h->nslots = np;
     h->L = L;
     h->M = M;
+    h->dim = m.kind == MLMC_HESTON ? 2 : 1;
     for (int k = 0; k < np; ++k) {
         h->payoff_kind[k] = p[k].kind;
         for (int l = 0; l <= L; ++l) h->params[k][l] = make_step_params<float>(m, p[k], l, M);

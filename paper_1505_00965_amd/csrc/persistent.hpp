@@ -26,10 +26,11 @@ struct WorkItem {
 
 // The plan of one launch: the (slot, level) pairs with outstanding samples,
 // in processing order; pair q owns items start[q] .. start[q+1] - 1, which
-// cut [first[q], first[q] + left[q]) into pieces of per[q] samples (the last
-// one shorter).  Items are decoded from it by the sampler, not stored.
+// cut [first[q], first[q] + left[q]) at base[q] + i per[q] (base[q] <=
+// first[q]: the first and last pieces may be shorter).  Items are decoded
+// from it by the sampler, not stored.
 struct PlanTable {
-    uint64_t first[kPairs], left[kPairs], per[kPairs];
+    uint64_t first[kPairs], left[kPairs], per[kPairs], base[kPairs];
     unsigned start[kPairs + 1];
     int npairs;
     uint8_t slot[kPairs], level[kPairs];
@@ -39,7 +40,8 @@ static_assert(sizeof(PlanTable) % 8 == 0, "copied in 8-byte words");
 
 // Device-resident batch description (rewritten before each launch).
 struct BatchDesc {
-    int nslots, L, M, pad;
+    int nslots, L, M;
+    int dim;                          // Brownian dimension: 1 (GBM), 2 (Heston)
     int payoff_kind[kMaxSlots];
     StepParams<float> params[kMaxSlots][kMaxLevels];
     uint64_t seed;
@@ -216,11 +218,11 @@ __device__ __forceinline__ WorkItem plan_item(const PlanTable& t, unsigned it)
 {
     int q = 0;
     while (q + 1 < t.npairs && t.start[q + 1] <= it) ++q;
-    const uint64_t done = (uint64_t)(it - t.start[q]) * t.per[q];
-    const uint64_t rest = t.left[q] - done;
+    const uint64_t lo = t.base[q] + (uint64_t)(it - t.start[q]) * t.per[q];
+    const uint64_t hi = lo + t.per[q], end = t.first[q] + t.left[q];
     WorkItem w;
-    w.first = t.first[q] + done;
-    w.n = (uint32_t)(rest < t.per[q] ? rest : t.per[q]);
+    w.first = lo > t.first[q] ? lo : t.first[q];
+    w.n = (uint32_t)((hi < end ? hi : end) - w.first);
     w.level = t.level[q];
     w.slot = t.slot[q];
     w.pad = 0;
