@@ -77,10 +77,9 @@ __host__ __device__ inline void set_counter_words(LevelArgs<Real>& a, int d)
 __host__ __device__ inline uint32_t split_lanes(int nf, uint64_t N, int num_cu, bool eligible)
 {
     if (!eligible || N == 0 || nf < 16) return 1;
-    // G > floor(num_cu 1024 / N) exactly when G N > num_cu 1024 (no division)
-    const uint64_t want = (uint64_t)num_cu * 1024;
+    const uint64_t want = (uint64_t)num_cu * 1024 / N;
     uint32_t G = 64;
-    while (G > 1 && ((uint64_t)G * N > want || (uint32_t)(nf / 4) % G != 0)) G >>= 1;
+    while (G > 1 && ((uint64_t)G > want || (uint32_t)(nf / 4) % G != 0)) G >>= 1;
     return G >= 4 ? G : 1;
 }
 
