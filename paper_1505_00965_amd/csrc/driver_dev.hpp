@@ -343,29 +343,11 @@ __device__ __forceinline__ void driver_update_block(DriverState* st, DriverState
     publish_state(st, mirror, s, true);
 }
 
-// Sums of the spread groups of levels 0..L (sum Y, sum Y^2 and the
-// non-finite count per level, in LDS), one wave per level, in the order
-// driver_update_block folds them; the records are left as they are.
+// Sums of the spread groups per level (sum Y, sum Y^2 and the non-finite
+// count), staged in LDS by the device-planned update.
 struct GroupSums {
     double y[kMaxLevels], y2[kMaxLevels], c[kMaxLevels];
 };
-__device__ __forceinline__ void sum_groups(const LevelAcc* spread, int L, GroupSums& g)
-{
-    static_assert(kSpread == 64, "one lane per record of a group");
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwaves = (int)(blockDim.x >> 6);
-    for (int l = wave; l <= L; l += nwaves) {    // wave-uniform
-        const LevelAcc& r = spread[l * kSpread + lane];
-        const double y = wave_sum(r.sum[0]);
-        const double y2 = wave_sum(r.sum[1]);
-        const double c = wave_sum((double)r.n_nonfinite);
-        if (lane == 0) {
-            g.y[l] = y;
-            g.y2[l] = y2;
-            g.c[l] = c;
-        }
-    }
-}
 
 // Zero the spread groups of levels 0..L (every word of their records).
 __device__ __forceinline__ void clear_groups(LevelAcc* spread, int L)

@@ -35,7 +35,7 @@ namespace mlmc {
 struct PlanArgs {
     int L, M, nslots, dim, split_ok, num_cu;
     unsigned resident_blocks, chunk, block;
-    int payoff_kind[kMaxSlots];
+    unsigned cond_slots;              // bit k: slot k holds the conditional digital
     PlanTable* plan;
     unsigned* head;
     unsigned* split;
@@ -53,8 +53,9 @@ __device__ __forceinline__ PlanArgs plan_args(const BatchDesc* d)
     a.resident_blocks = d->resident_blocks;
     a.chunk = d->chunk;
     a.block = d->block;
+    a.cond_slots = 0;
 #pragma unroll
-    for (int k = 0; k < kMaxSlots; ++k) a.payoff_kind[k] = d->payoff_kind[k];
+    for (int k = 0; k < kMaxSlots; ++k) a.cond_slots |= d->payoff_kind[k] == kDigitalCond ? 1u << k : 0u;
     a.plan = d->plan;
     a.head = d->head;
     a.split = d->split;
@@ -102,8 +103,7 @@ __device__ __forceinline__ void plan_body(const PlanArgs& a, const double* dN, c
     uint64_t per_item = 0;
     if (valid) {
         // lanes per path: the per-level launch's rule on the same count
-        const uint32_t G = split_lanes((int)nf, left, a.num_cu,
-                                       a.split_ok && a.payoff_kind[s] != kDigitalCond);
+        const uint32_t G = split_lanes((int)nf, left, a.num_cu, a.split_ok && !((a.cond_slots >> s) & 1u));
         a.split[s * kMaxLevels + l] = G;
         if (left) {
             uint64_t paths = (uint64_t)(target / per);
@@ -195,30 +195,56 @@ __global__ __launch_bounds__(256) void driver_start_kernel(DriverState* st, Leve
 // (update_state), plan the next batch's items from the new state in LDS,
 // then write the state back and clear the groups.  The host reads the
 // update count every iteration and the state once, at the end: the mirror
-// is written whole by the finishing update only.  The group loads go out
-// beside the state's (the level count comes from the stored state) and the
-// stores come last, so the block waits on memory twice: for the loads and
-// for nothing else.  A finished state has no outstanding samples: the plan
-// its finishing update wrote is empty, so a sampler launched after it does
-// nothing, and an update launched after it returns at once.
+// is written whole by the finishing update only.  Every load goes out at
+// the start, none waiting for another: the state (one word per thread), the
+// records of every level's spread group (8 waves, levels w and w + 8; the
+// groups past the sampled levels hold zeros), the descriptor's plan fields
+// and the state's level count and done flag; the stores come last.  A
+// finished state has no outstanding samples: the plan its finishing update
+// wrote is empty, so a sampler launched after it does nothing, and an
+// update launched after it returns once it has summed the groups.
 __global__ __launch_bounds__(512) void driver_update_plan_kernel(DriverState* st, DriverState* mirror,
                                                                  LevelAcc* spread, const BatchDesc* d)
 {
+    constexpr int kWords = sizeof(DriverState) / 8;
+    static_assert(kWords <= 512, "one state word per thread");
+    static_assert(kMaxLevels == 16 && kSpread == 64, "8 waves, two levels' groups each");
     __shared__ DriverState s;
     __shared__ GroupSums g;
-    const PlanArgs pa = plan_args(d);
-    // the levels the batch sampled: 0..L of the stored state (the word the
-    // copy below brings into LDS)
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const unsigned long long word =
+        threadIdx.x < (unsigned)kWords ? ((const unsigned long long*)st)[threadIdx.x] : 0ull;
+    const LevelAcc& r0 = spread[wave * kSpread + lane];
+    const LevelAcc& r1 = spread[(wave + 8) * kSpread + lane];
+    double y0 = r0.sum[0], q0 = r0.sum[1], c0 = (double)r0.n_nonfinite;
+    double y1 = r1.sum[0], q1 = r1.sum[1], c1 = (double)r1.n_nonfinite;
+    // the levels the batch sampled: 0..L of the stored state
     const int L0 = __builtin_amdgcn_readfirstlane(st->L);
-    sum_groups(spread, L0, g);
-    {
-        constexpr int kWords = sizeof(DriverState) / 8;
-        const unsigned long long* src = (const unsigned long long*)st;
-        unsigned long long* w = (unsigned long long*)&s;
-        for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = src[i];
+    const int done = __builtin_amdgcn_readfirstlane(st->done);
+    const PlanArgs pa = plan_args(d);
+    // only the plan reads the descriptor's fields, at the end: taking them
+    // into registers here keeps their loads beside the others
+    asm volatile("" ::"s"(pa.L), "s"(pa.M), "s"(pa.nslots), "s"(pa.dim), "s"(pa.split_ok), "s"(pa.num_cu),
+                 "s"(pa.resident_blocks), "s"(pa.chunk), "s"(pa.block), "s"(pa.cond_slots), "s"(pa.plan),
+                 "s"(pa.head), "s"(pa.split));
+    // the sums of each group, in record order as the per-level form folds them
+    y0 = wave_sum(y0);
+    q0 = wave_sum(q0);
+    c0 = wave_sum(c0);
+    y1 = wave_sum(y1);
+    q1 = wave_sum(q1);
+    c1 = wave_sum(c1);
+    if (done) return;   // block-uniform
+    if (lane == 0) {
+        g.y[wave] = y0;
+        g.y2[wave] = q0;
+        g.c[wave] = c0;
+        g.y[wave + 8] = y1;
+        g.y2[wave + 8] = q1;
+        g.c[wave + 8] = c1;
     }
+    if (threadIdx.x < (unsigned)kWords) ((unsigned long long*)&s)[threadIdx.x] = word;
     __syncthreads();
-    if (s.done) return;   // block-uniform (LDS after a barrier)
     // absorb the groups into the batch records (held at zero between updates)
     if ((int)threadIdx.x <= L0) {
         const int l = (int)threadIdx.x;
