@@ -113,7 +113,7 @@ static mlmc_status ensure_driver(mlmc_ctx* ctx)
 // and the update-and-plan block per iteration)
 mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p,
                            const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st,
-                           const DriverInit& init);
+                           const DriverInit& init, bool clean);
 
 }  // namespace mlmc
 
@@ -205,12 +205,14 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     init.L_max = h->L_max;
     init.max_iterations = h->max_iterations;
     init.pad = 0;
-    // The per-level form lets its first update build the state when the
-    // spread groups are known to hold zeros (one launch fewer on the pilot's
-    // path); otherwise a kernel clears both first (in the device-planned
-    // form, its start kernel).
-    // Until this run ends normally the groups are not known to be clear.
-    const bool fused_init = ctx->drv_clean && !o.persistent;
+    // When the spread groups are known to hold zeros, the per-level form
+    // lets its first update build the state and the device-planned form its
+    // first sampler launch (one launch fewer on the pilot's path); otherwise
+    // a kernel clears both first (in the device-planned form, its start
+    // kernel).  Until this run ends normally the groups are not known to be
+    // clear.
+    const bool clean = ctx->drv_clean;
+    const bool fused_init = clean && !o.persistent;
     ctx->drv_clean = false;
     if (!fused_init && !o.persistent) {
         hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d,
@@ -218,8 +220,7 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
         MLMC_HIP(ctx, hipGetLastError());
     }
     if (o.persistent) {
-        // its start kernel builds the state and clears the groups
-        st = run_persistent(ctx, *model, *payoff, o, d, h, init);
+        st = run_persistent(ctx, *model, *payoff, o, d, h, init, clean);
         if (st) return st;
     } else {
         for (int it = 0;; ++it) {

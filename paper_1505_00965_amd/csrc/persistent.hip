@@ -30,160 +30,23 @@
 
 namespace mlmc {
 
-// What the plan reads of the descriptor besides the request: loaded at a
-// kernel's start, so the loads overlap the kernel's other reads.
-struct PlanArgs {
-    int L, M, nslots, dim, split_ok, num_cu;
-    unsigned resident_blocks, chunk, block;
-    unsigned cond_slots;              // bit k: slot k holds the conditional digital
-    PlanTable* plan;
-    unsigned* head;
-    unsigned* split;
-};
-
-__device__ __forceinline__ PlanArgs plan_args(const BatchDesc* d)
-{
-    PlanArgs a;
-    a.L = d->L;
-    a.M = d->M;
-    a.nslots = d->nslots;
-    a.dim = d->dim;
-    a.split_ok = d->split_ok;
-    a.num_cu = d->num_cu;
-    a.resident_blocks = d->resident_blocks;
-    a.chunk = d->chunk;
-    a.block = d->block;
-    a.cond_slots = 0;
-#pragma unroll
-    for (int k = 0; k < kMaxSlots; ++k) a.cond_slots |= d->payoff_kind[k] == kDigitalCond ? 1u << k : 0u;
-    a.plan = d->plan;
-    a.head = d->head;
-    a.split = d->split;
-    return a;
-}
-
-// ceil(a / b) for a < 2^53, b > 0: the fp64 quotient is within one of it.
-__device__ __forceinline__ uint64_t ceil_div_u53(uint64_t a, uint64_t b)
-{
-    uint64_t q = (uint64_t)ceil((double)a / (double)b);
-    if (q * b < a) ++q;
-    else if (q && (q - 1) * b >= a) --q;
-    return q;
-}
-
-// Plan: the first wave sizes the (slot, level) pairs, one lane each, in
-// processing order (deepest level first, then slot), so the per-pair
-// arithmetic runs side by side; a wave scan gives each pair its first item,
-// and each lane writes its pair's row of the plan table (the sampler decodes
-// the items from it).  dN and off: the outstanding samples and their first
-// index per (slot, level) (device memory, or the driver state in LDS).  Only
-// the first wave works; every thread of the block may call it.  Block sizes
-// and samples per lane are powers of two (the launch shape's rule), and so
-// are the sampler's chunks and split passes: they are cut with masks.
-__device__ __forceinline__ void plan_body(const PlanArgs& a, const double* dN, const double* off)
-{
-    static_assert(kPairs == 64, "one lane of the first wave per (slot, level) pair");
-    if (threadIdx.x >= 64) return;
-    const int L = a.L, M = a.M, nslots = a.nslots;
-    const int p = (int)threadIdx.x;
-    const bool valid = p < (L + 1) * nslots;
-    const int l = valid ? L - p / nslots : 0, s = valid ? p % nslots : 0;
-    double nf = 1.0;
-    for (int i = 0; i < l; ++i) nf *= M;   // M^l, exact
-    const double per = nf + (l ? nf / M : 0.0);
-    const double dn = valid ? dN[s * kMaxLevels + l] : 0.0;
-    // samples x steps over the batch (lane 0's sum: the rotations leave
-    // other lanes with other association orders)
-    const double total = __shfl(wave_sum(valid ? dn * per : 0.0), 0);
-    const double target = total / ((double)a.resident_blocks * kItemsPerBlock);
-    const uint64_t left = (uint64_t)dn;
-    const uint64_t first = valid ? (uint64_t)off[s * kMaxLevels + l] : 0;
-    uint64_t base = first;
-    unsigned items = 0;
-    uint64_t per_item = 0;
-    if (valid) {
-        // lanes per path: the per-level launch's rule on the same count
-        const uint32_t G = split_lanes((int)nf, left, a.num_cu, a.split_ok && !((a.cond_slots >> s) & 1u));
-        a.split[s * kMaxLevels + l] = G;
-        if (left) {
-            uint64_t paths = (uint64_t)(target / per);
-            // samples of one chunk of the sampler: block x ppt samples, or on
-            // one- and two-step levels block x ppt generator blocks of q
-            const uint64_t unit = (uint64_t)a.chunk * (nf < 4 ? (uint64_t)(4 / ((int)nf * a.dim)) : 1ull);
-            if (G > 1) {
-                // split paths: whole block passes of block / G paths
-                const uint64_t pass = a.block / G;
-                paths = paths < pass ? pass : paths & ~(pass - 1);
-            } else if (paths >= unit) {
-                paths &= ~(unit - 1);                    // whole chunks where possible
-            } else {
-                // one sample per lane, or one whole chunk, whichever is nearer
-                paths = 2 * paths >= a.block + unit ? unit : a.block;
-            }
-            if (paths > (1ull << 31)) paths = 1ull << 31;   // item sizes fit 32 bits
-            // at most kItemsPerPair items per pair (one more when cut on the
-            // chunk grid below): item indices stay small
-            const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
-            per_item = paths > min_items ? paths : min_items;
-            if (G == 1 && per_item > a.block) {
-                // whole chunks (the sampler simulates a whole chunk, the
-                // samples past the item's end included), cut on a grid of
-                // whole chunks from the pair's first sample rounded down:
-                // every piece but the pair's first and last then fills all
-                // its chunks (on one- and two-step levels a partial chunk
-                // also takes per-sample range checks)
-                per_item = (per_item + unit - 1) & ~(unit - 1);
-                base = first & ~(unit - 1);
-            }
-            if (per_item > (1ull << 31)) per_item = (1ull << 31) & ~(unit - 1);
-            items = (unsigned)ceil_div_u53(first + left - base, per_item);
-        }
-    }
-    // inclusive scan of the item counts over the lanes (pair order)
-    unsigned incl = items;
-#pragma unroll
-    for (int k = 1; k < 64; k <<= 1) {
-        const unsigned v = __shfl_up(incl, k);
-        if (p >= k) incl += v;
-    }
-    // pairs with samples, packed in order
-    const uint64_t active = __ballot(items > 0);
-    const int rank = __popcll(active & ((1ull << p) - 1ull));
-    PlanTable* t = a.plan;
-    if (items) {
-        t->first[rank] = first;
-        t->left[rank] = left;
-        t->per[rank] = per_item;
-        t->base[rank] = base;
-        t->slot[rank] = (uint8_t)s;
-        t->level[rank] = (uint8_t)l;
-        t->start[rank] = incl - items;
-    }
-    if (p == 63) {
-        const int np = __popcll(active);
-        t->start[np] = incl;
-        t->npairs = np;
-        *a.head = 0;
-    }
-}
-
 __global__ __launch_bounds__(256) void plan_kernel(const BatchDesc* d)
 {
     plan_body(plan_args(d), d->dN, d->offset);
 }
 
-// The adaptive run's first kernel: a fresh state (n_pilot samples
-// outstanding on levels 0..L_min) built in LDS and planned from there, the
-// run's seed into the descriptor, then the state written out and the spread
-// groups cleared (the stores last: nothing waits for them).
+// The adaptive run's first kernel when its spread groups are not known to
+// hold zeros: a fresh state (n_pilot samples outstanding on levels
+// 0..L_min) built in LDS and planned from there (the plan also zeroes the
+// dispenser), then the state written out and the spread groups cleared (the
+// stores last: nothing waits for them).
 __global__ __launch_bounds__(256) void driver_start_kernel(DriverState* st, LevelAcc* spread,
-                                                           DriverInit c, BatchDesc* d, uint64_t seed)
+                                                           DriverInit c, const BatchDesc* d)
 {
     __shared__ DriverState s;
     const PlanArgs pa = plan_args(d);
     init_state(s, c);   // ends with a barrier
     plan_body(pa, s.dN, s.n);
-    if (threadIdx.x == 0) d->seed = seed;
     constexpr int kWords = sizeof(DriverState) / 8;
     const unsigned long long* w = (const unsigned long long*)&s;
     unsigned long long* dst = (unsigned long long*)st;
@@ -308,9 +171,11 @@ struct PersistentBufs {
     hipGraphExec_t graph = nullptr;   // cached batch graph
     int graph_key[6] = {-1, -1, -1, -1, -1, -1};
     BatchDesc last_desc;              // the bytes of the last descriptor upload
-    // 0: unknown; 1: the device descriptor holds last_desc; 2: it does but for
-    // its seed (the adaptive run's start kernel writes the seed)
+    // 0: unknown; 1: the device descriptor holds last_desc
     int desc_state = 0;
+    // the driver runs' dispenser holds zero: set when a driver run ends
+    // normally (its last plan zeroes it), cleared while one runs
+    bool driver_head_zero = true;
 };
 
 static PersistentBufs* bufs_of(mlmc_ctx* ctx);
@@ -338,6 +203,8 @@ static mlmc_status ensure_bufs(mlmc_ctx* ctx)
     if (e == hipSuccess) e = hipHostMalloc(&b->h_desc, sizeof(BatchDesc));
     if (e == hipSuccess) e = hipMalloc(&b->d_plan, sizeof(PlanTable));
     if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(unsigned) * 4);
+    // the dispensers start at zero (a driver run's plans leave its own there)
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_counters, 0, sizeof(unsigned) * 4, ctx->stream);
     if (e == hipSuccess)
         e = hipMalloc(&b->d_acc, sizeof(LevelAcc) * kMaxSlots * kMaxLevels * kSpread);
     if (e == hipSuccess) e = hipMalloc(&b->d_rec, sizeof(LevelAcc) * kMaxSlots * kMaxLevels);
@@ -374,9 +241,12 @@ void free_persistent(mlmc_ctx* ctx)
 }
 
 // Fill the host copy of the descriptor (parameters for every slot and level).
+// A driver run passes its state, the fresh state's configuration and its
+// own dispenser (`head`); a batch passes nullptr for both and the batch
+// dispenser.
 static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const mlmc_payoff* p,
                       int np, int L, int M, uint64_t seed, const double* dN, const double* off,
-                      LevelAcc* acc)
+                      LevelAcc* acc, unsigned* head, DriverState* st, const DriverInit* init)
 {
     auto* b = bufs_of(ctx);
     const PersistentShape s = persistent_shape(ctx);
@@ -394,23 +264,23 @@ static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const ml
     h->offset = off;
     h->acc = acc;
     h->plan = b->d_plan;
-    h->head = b->d_counters;
+    h->head = head;
     h->resident_blocks = (unsigned)(ctx->num_cu * s.blocks_per_cu);
     h->chunk = (unsigned)(s.block * s.ppt);
     h->split = b->d_split;
     h->split_ok = m.kind == MLMC_GBM && !m.antithetic;
     h->num_cu = ctx->num_cu;
     h->block = (unsigned)s.block;
+    h->st = st;
+    if (init) h->init = *init;
 }
 
 // Copy the host descriptor to the device unless the last upload from this
-// context carried the same bytes (repeated runs of one problem skip it).
-// any_seed: the caller sets the seed on the device itself, so a device copy
-// that differs in its seed only is as good.
-static mlmc_status upload_desc(mlmc_ctx* ctx, PersistentBufs* b, bool any_seed)
+// context carried the same bytes (repeated runs of one problem skip it: a
+// driver run passes its seed with each launch, not in the descriptor).
+static mlmc_status upload_desc(mlmc_ctx* ctx, PersistentBufs* b)
 {
-    if (b->desc_state != 0 && (b->desc_state == 1 || any_seed) &&
-        std::memcmp(&b->last_desc, b->h_desc, sizeof(BatchDesc)) == 0)
+    if (b->desc_state == 1 && std::memcmp(&b->last_desc, b->h_desc, sizeof(BatchDesc)) == 0)
         return MLMC_OK;
     b->desc_state = 0;
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
@@ -436,8 +306,9 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, int payoff, hipGraph
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
+        // the seed from the descriptor (uploaded per batch), the plan from plan_kernel
         hipLaunchKernelGGL(pick_persistent(model, M, s.ppt, payoff), dim3(ctx->num_cu * s.blocks_per_cu),
-                           dim3(s.block), 0, cs, (const BatchDesc*)b->d_desc);
+                           dim3(s.block), 0, cs, (const BatchDesc*)b->d_desc, (uint64_t)0, 0u);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -459,7 +330,7 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, int payoff, hipGraph
 // block, as plain launches on the context's stream.
 mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p,
                            const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st,
-                           const DriverInit& init)
+                           const DriverInit& init, bool clean)
 {
     if (o.precision != 32) return fail(ctx, MLMC_EINVAL, "the persistent form runs fp32 paths");
     if (o.cv) {
@@ -476,9 +347,11 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     mlmc_status st = ensure_bufs(ctx);
     if (st) return st;
     auto* b = bufs_of(ctx);
-    // the seed goes in with the start kernel: runs of one problem share the
-    // descriptor's bytes and upload it once
-    fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, 0, d_st->dN, d_st->n, ctx->d_drv_spread);
+    // the seed goes in with each launch: runs of one problem share the
+    // descriptor's bytes and upload it once.  Driver runs have a dispenser
+    // of their own, which their plans leave at zero.
+    fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, 0, d_st->dN, d_st->n, ctx->d_drv_spread,
+              b->d_counters + 1, d_st, &init);
     size_t lds = 0;
     if (o.cv) {
         int max_nf = 1;
@@ -488,7 +361,7 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
         if (e != hipSuccess) return hip_fail(ctx, e, "control-variate table");
         b->h_desc->cv_levels = o.cv_levels;
     }
-    st = upload_desc(ctx, b, true);
+    st = upload_desc(ctx, b);
     if (st) return st;
     const PersistentShape s = persistent_shape(ctx);
     const auto sampler = pick_persistent(sampler_variant(m), o.M, s.ppt, p.kind, o.cv != nullptr);
@@ -496,10 +369,17 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     const dim3 grid(ctx->num_cu * s.blocks_per_cu), block(s.block);
     const BatchDesc* d = b->d_desc;
     DriverState* mirror = (DriverState*)ctx->h_drv_dev;
-    hipLaunchKernelGGL(driver_start_kernel, dim3(1), dim3(256), 0, ctx->stream, d_st,
-                       ctx->d_drv_spread, init, b->d_desc, o.seed);
-    MLMC_HIP(ctx, hipGetLastError());
-    b->desc_state = 2;   // the device copy now carries this run's seed
+    // When the context's last driver run ended normally its updates left the
+    // spread groups and the driver dispenser at zero: the first sampler
+    // launch then plans the pilot batch itself and builds the fresh state
+    // (kPilot), and the start kernel is not needed.
+    const bool fused = clean && b->driver_head_zero;
+    b->driver_head_zero = false;
+    if (!fused) {
+        hipLaunchKernelGGL(driver_start_kernel, dim3(1), dim3(256), 0, ctx->stream, d_st,
+                           ctx->d_drv_spread, init, d);
+        MLMC_HIP(ctx, hipGetLastError());
+    }
     // Iteration k + 1 is enqueued before the host waits for iteration k's
     // update: its sampler reads the items that update planned, so the GPU
     // runs the iterations back to back while the host reads the mirror.  The
@@ -515,8 +395,9 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
             hipEvent_t t0, t1;
             timed_kernel(ctx, 16, 0.0, 0.0, &t0, &t1);
             if (first_tix < 0 && t0) first_tix = (int)ctx->pending.size() - 1;
-            if (t0) hipExtLaunchKernelGGL(sampler, grid, block, lds, ctx->stream, t0, t1, 0, d);
-            else hipLaunchKernelGGL(sampler, grid, block, lds, ctx->stream, d);
+            const unsigned flags = kSeedArg | (it == 0 && k == 0 && fused ? kPilot : 0u);
+            if (t0) hipExtLaunchKernelGGL(sampler, grid, block, lds, ctx->stream, t0, t1, 0, d, o.seed, flags);
+            else hipLaunchKernelGGL(sampler, grid, block, lds, ctx->stream, d, o.seed, flags);
             hipError_t e = hipGetLastError();
             if (e == hipSuccess) {
                 timed_kernel(ctx, 17, 0.0, 0.0, &t0, &t1);
@@ -537,6 +418,7 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
         // seen done is complete; later updates leave it as it is
         if (mirror_done(h_st)) break;
     }
+    b->driver_head_zero = true;   // the finishing update's plan zeroed it
     // the iteration past the last update may still run: the result is read
     // from the mirror; stamped launches are read once finished (harvest_ready
     // now, the rest by a later harvest), the run does not wait for them
@@ -623,10 +505,10 @@ mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc
                 offsets ? (double)offsets[k * (L + 1) + l] : 0.0;
         }
     fill_desc(ctx, b->h_desc, *model, payoffs, npayoffs, L, M, seed, b->d_req,
-              b->d_req + kMaxSlots * kMaxLevels, b->d_acc);
+              b->d_req + kMaxSlots * kMaxLevels, b->d_acc, b->d_counters, nullptr, nullptr);
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_req, b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels,
                                  hipMemcpyHostToDevice, ctx->stream));
-    st = upload_desc(ctx, b, false);
+    st = upload_desc(ctx, b);
     if (st) return st;
     const PersistentShape s = persistent_shape(ctx);
     // one payoff kind in every slot: the kernel holds that payoff's code only

@@ -6,6 +6,7 @@
 
 #include "cv_tab.hpp"
 #include "driver.hpp"
+#include "driver_dev.hpp"
 #include "level.hpp"
 #include "sampler_impl.hpp"
 
@@ -65,6 +66,10 @@ struct BatchDesc {
     TableSpec cv_spec;
     const float* cv_phi0;
     int cv_levels;
+    // a driver run: its state and the configuration of a fresh one (the
+    // pilot launch builds the state when the run has no start kernel)
+    DriverState* st;
+    DriverInit init;
 };
 
 // A batch whose slots may hold different payoff kinds.
@@ -162,12 +167,12 @@ __device__ __forceinline__ T wave_uniform(const T& v)
 // rows, copied into s_tab unless the block's previous item left them there
 // (tab_level, block-uniform; items are separated by barriers).
 template <int MODEL, int PAYOFF, int M, int PPT, bool CV>
-__device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, double (&sums)[kNumSums],
+__device__ __forceinline__ void run_item(const BatchDesc* d, uint64_t seed, const WorkItem& w, double (&sums)[kNumSums],
                                          unsigned& nonfinite, float* s_tab, int& tab_level)
 {
     LevelArgs<float> a;
     a.P = wave_uniform(d->params[w.slot][w.level]);
-    a.seed = wave_uniform(d->seed);
+    a.seed = seed;
     a.l = w.level;
     int nf = 1;
     for (int i = 0; i < a.l; ++i) nf *= M;
@@ -213,6 +218,143 @@ __device__ __forceinline__ void run_item(const BatchDesc* d, const WorkItem& w, 
     }
 }
 
+// What the plan reads of the descriptor besides the request: loaded at a
+// kernel's start, so the loads overlap the kernel's other reads.
+struct PlanArgs {
+    int L, M, nslots, dim, split_ok, num_cu;
+    unsigned resident_blocks, chunk, block;
+    unsigned cond_slots;              // bit k: slot k holds the conditional digital
+    PlanTable* plan;
+    unsigned* head;
+    unsigned* split;
+};
+
+__device__ __forceinline__ PlanArgs plan_args(const BatchDesc* d)
+{
+    PlanArgs a;
+    a.L = d->L;
+    a.M = d->M;
+    a.nslots = d->nslots;
+    a.dim = d->dim;
+    a.split_ok = d->split_ok;
+    a.num_cu = d->num_cu;
+    a.resident_blocks = d->resident_blocks;
+    a.chunk = d->chunk;
+    a.block = d->block;
+    a.cond_slots = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxSlots; ++k) a.cond_slots |= d->payoff_kind[k] == kDigitalCond ? 1u << k : 0u;
+    a.plan = d->plan;
+    a.head = d->head;
+    a.split = d->split;
+    return a;
+}
+
+// ceil(a / b) for a < 2^53, b > 0: the fp64 quotient is within one of it.
+__device__ __forceinline__ uint64_t ceil_div_u53(uint64_t a, uint64_t b)
+{
+    uint64_t q = (uint64_t)ceil((double)a / (double)b);
+    if (q * b < a) ++q;
+    else if (q && (q - 1) * b >= a) --q;
+    return q;
+}
+
+// Plan: the first wave sizes the (slot, level) pairs, one lane each, in
+// processing order (deepest level first, then slot), so the per-pair
+// arithmetic runs side by side; a wave scan gives each pair its first item,
+// and each lane writes its pair's row of the plan table (the sampler decodes
+// the items from it).  dN and off: the outstanding samples and their first
+// index per (slot, level) (device memory, or the driver state in LDS).  Only
+// the first wave works; every thread of the block may call it.  Block sizes
+// and samples per lane are powers of two (the launch shape's rule), and so
+// are the sampler's chunks and split passes: they are cut with masks.
+__device__ __forceinline__ void plan_body(const PlanArgs& a, const double* dN, const double* off)
+{
+    static_assert(kPairs == 64, "one lane of the first wave per (slot, level) pair");
+    if (threadIdx.x >= 64) return;
+    const int L = a.L, M = a.M, nslots = a.nslots;
+    const int p = (int)threadIdx.x;
+    const bool valid = p < (L + 1) * nslots;
+    const int l = valid ? L - p / nslots : 0, s = valid ? p % nslots : 0;
+    double nf = 1.0;
+    for (int i = 0; i < l; ++i) nf *= M;   // M^l, exact
+    const double per = nf + (l ? nf / M : 0.0);
+    const double dn = valid ? dN[s * kMaxLevels + l] : 0.0;
+    // samples x steps over the batch (lane 0's sum: the rotations leave
+    // other lanes with other association orders)
+    const double total = __shfl(wave_sum(valid ? dn * per : 0.0), 0);
+    const double target = total / ((double)a.resident_blocks * kItemsPerBlock);
+    const uint64_t left = (uint64_t)dn;
+    const uint64_t first = valid ? (uint64_t)off[s * kMaxLevels + l] : 0;
+    uint64_t base = first;
+    unsigned items = 0;
+    uint64_t per_item = 0;
+    if (valid) {
+        // lanes per path: the per-level launch's rule on the same count
+        const uint32_t G = split_lanes((int)nf, left, a.num_cu, a.split_ok && !((a.cond_slots >> s) & 1u));
+        a.split[s * kMaxLevels + l] = G;
+        if (left) {
+            uint64_t paths = (uint64_t)(target / per);
+            // samples of one chunk of the sampler: block x ppt samples, or on
+            // one- and two-step levels block x ppt generator blocks of q
+            const uint64_t unit = (uint64_t)a.chunk * (nf < 4 ? (uint64_t)(4 / ((int)nf * a.dim)) : 1ull);
+            if (G > 1) {
+                // split paths: whole block passes of block / G paths
+                const uint64_t pass = a.block / G;
+                paths = paths < pass ? pass : paths & ~(pass - 1);
+            } else if (paths >= unit) {
+                paths &= ~(unit - 1);                    // whole chunks where possible
+            } else {
+                // one sample per lane, or one whole chunk, whichever is nearer
+                paths = 2 * paths >= a.block + unit ? unit : a.block;
+            }
+            if (paths > (1ull << 31)) paths = 1ull << 31;   // item sizes fit 32 bits
+            // at most kItemsPerPair items per pair (one more when cut on the
+            // chunk grid below): item indices stay small
+            const uint64_t min_items = (left + kItemsPerPair - 1) / kItemsPerPair;
+            per_item = paths > min_items ? paths : min_items;
+            if (G == 1 && per_item > a.block) {
+                // whole chunks (the sampler simulates a whole chunk, the
+                // samples past the item's end included), cut on a grid of
+                // whole chunks from the pair's first sample rounded down:
+                // every piece but the pair's first and last then fills all
+                // its chunks (on one- and two-step levels a partial chunk
+                // also takes per-sample range checks)
+                per_item = (per_item + unit - 1) & ~(unit - 1);
+                base = first & ~(unit - 1);
+            }
+            if (per_item > (1ull << 31)) per_item = (1ull << 31) & ~(unit - 1);
+            items = (unsigned)ceil_div_u53(first + left - base, per_item);
+        }
+    }
+    // inclusive scan of the item counts over the lanes (pair order)
+    unsigned incl = items;
+#pragma unroll
+    for (int k = 1; k < 64; k <<= 1) {
+        const unsigned v = __shfl_up(incl, k);
+        if (p >= k) incl += v;
+    }
+    // pairs with samples, packed in order
+    const uint64_t active = __ballot(items > 0);
+    const int rank = __popcll(active & ((1ull << p) - 1ull));
+    PlanTable* t = a.plan;
+    if (items) {
+        t->first[rank] = first;
+        t->left[rank] = left;
+        t->per[rank] = per_item;
+        t->base[rank] = base;
+        t->slot[rank] = (uint8_t)s;
+        t->level[rank] = (uint8_t)l;
+        t->start[rank] = incl - items;
+    }
+    if (p == 63) {
+        const int np = __popcll(active);
+        t->start[np] = incl;
+        t->npairs = np;
+        if (a.head) *a.head = 0;
+    }
+}
+
 // Item `it` of the plan (block-uniform).
 __device__ __forceinline__ WorkItem plan_item(const PlanTable& t, unsigned it)
 {
@@ -229,22 +371,46 @@ __device__ __forceinline__ WorkItem plan_item(const PlanTable& t, unsigned it)
     return w;
 }
 
+// Launch flags of the sampler.
+constexpr unsigned kSeedArg = 1;   // the seed is the launch's argument (else the descriptor's)
+constexpr unsigned kPilot = 2;     // a driver run's first launch, planned by every block itself
+
 // Block b takes item b first; later items come from the dispenser until
 // none are left, so a launch with no more items than blocks (an empty one
 // included) makes no atomics on it.  Each item ends with a block reduction
-// into its (payoff, level) spread group.
+// into its (payoff, level) spread group.  The plan comes from the
+// descriptor's table, or with kPilot from the first wave of every block:
+// the pilot batch of a driver run (n_pilot samples on levels 0..L_min from
+// index 0, the start kernel's plan), while block 0 builds the fresh state;
+// the run then needs no start kernel (its spread groups and the dispenser
+// hold zeros: the caller knows the context's last run ended normally).
 template <int MODEL, int M, int PPT, int PAYOFF, bool CV>
-__device__ __forceinline__ void sample_items(const BatchDesc* d, float* s_tab)
+__device__ __forceinline__ void sample_items(const BatchDesc* d, float* s_tab, uint64_t seed_arg,
+                                             unsigned flags)
 {
     __shared__ unsigned s_item;
     // the plan in LDS: each item is decoded by a short search over its pairs
     __shared__ PlanTable s_plan;
-    {
+    if (flags & kPilot) {   // launch-uniform
+        __shared__ double s_req[2][kMaxLevels];   // outstanding samples, first index
+        if (threadIdx.x < kMaxLevels) {
+            s_req[0][threadIdx.x] = (int)threadIdx.x <= d->init.L_min ? d->init.n_pilot : 0.0;
+            s_req[1][threadIdx.x] = 0.0;
+        }
+        __syncthreads();
+        PlanArgs pa = plan_args(d);
+        pa.plan = &s_plan;
+        pa.head = nullptr;
+        plan_body(pa, s_req[0], s_req[1]);
+        if (blockIdx.x == 0) init_state(*d->st, d->init);   // block-uniform; ends with a barrier
+        __syncthreads();
+    } else {
         const unsigned long long* src = (const unsigned long long*)d->plan;
         unsigned long long* dst = (unsigned long long*)&s_plan;
         for (int i = threadIdx.x; i < (int)(sizeof(PlanTable) / 8); i += blockDim.x) dst[i] = src[i];
         __syncthreads();
     }
+    const uint64_t seed = (flags & kSeedArg) ? seed_arg : d->seed;
     int tab_level = -1;
     const unsigned count = __builtin_amdgcn_readfirstlane(s_plan.start[s_plan.npairs]);
     for (unsigned it = blockIdx.x; it < count;) {   // block-uniform
@@ -253,18 +419,18 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d, float* s_tab)
         unsigned nonfinite = 0;
         if constexpr (PAYOFF == kAnyPayoff) {
             switch (d->payoff_kind[w.slot]) {
-            case kCall: run_item<MODEL, kCall, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level); break;
-            case kAsian: run_item<MODEL, kAsian, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level); break;
+            case kCall: run_item<MODEL, kCall, M, PPT, false>(d, seed, w, sums, nonfinite, s_tab, tab_level); break;
+            case kAsian: run_item<MODEL, kAsian, M, PPT, false>(d, seed, w, sums, nonfinite, s_tab, tab_level); break;
             case kLookback:
-                run_item<MODEL, kLookback, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level);
+                run_item<MODEL, kLookback, M, PPT, false>(d, seed, w, sums, nonfinite, s_tab, tab_level);
                 break;
             case kDigitalCond:
-                run_item<MODEL, kDigitalCond, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level);
+                run_item<MODEL, kDigitalCond, M, PPT, false>(d, seed, w, sums, nonfinite, s_tab, tab_level);
                 break;
-            default: run_item<MODEL, kDigital, M, PPT, false>(d, w, sums, nonfinite, s_tab, tab_level); break;
+            default: run_item<MODEL, kDigital, M, PPT, false>(d, seed, w, sums, nonfinite, s_tab, tab_level); break;
             }
         } else {
-            run_item<MODEL, PAYOFF, M, PPT, CV>(d, w, sums, nonfinite, s_tab, tab_level);
+            run_item<MODEL, PAYOFF, M, PPT, CV>(d, seed, w, sums, nonfinite, s_tab, tab_level);
         }
         if (w.level == 0) copy_y_sums(sums);
         block_reduce_add(sums, nonfinite, &d->acc[(w.slot * kMaxLevels + w.level) * kSpread +
@@ -283,13 +449,13 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d, float* s_tab)
 // payoff, Euler paths; launched with the deepest level's table rows of
 // dynamic LDS).
 template <int MODEL, int M, int PPT, int PAYOFF, bool CV>
-__global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d)
+__global__ __launch_bounds__(1024) void persistent_kernel(const BatchDesc* d, uint64_t seed, unsigned flags)
 {
     extern __shared__ __attribute__((aligned(16))) float s_tab[];
-    sample_items<MODEL, M, PPT, PAYOFF, CV>(d, s_tab);
+    sample_items<MODEL, M, PPT, PAYOFF, CV>(d, s_tab, seed, flags);
 }
 
-using PersistentFn = void (*)(const BatchDesc*);
+using PersistentFn = void (*)(const BatchDesc*, uint64_t, unsigned);
 
 template <int MODEL, int M, int PPT>
 PersistentFn pick_persistent_payoff(int payoff, bool cv)
