@@ -30,6 +30,10 @@ struct mlmc_ctx {
     // the groups are known to hold zeros: the last run ended normally (its
     // updates folded and cleared every group it used)
     bool drv_clean = false;
+    // the driver state and the plan table hold a fresh start for the next
+    // device-planned run of the same descriptor (the last call was one, and
+    // the update queued past its end prepared it)
+    bool drv_pilot_ready = false;
     double* d_tmp = nullptr;                // small fp64 scratch (optimal_n)
     double* h_tmp = nullptr;
     // kernel timing (mlmc_set_timing)

@@ -113,7 +113,7 @@ static mlmc_status ensure_driver(mlmc_ctx* ctx)
 // and the update-and-plan block per iteration)
 mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p,
                            const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st,
-                           const DriverInit& init, bool clean);
+                           const DriverInit& init, bool prepared);
 
 }  // namespace mlmc
 
@@ -206,21 +206,22 @@ mlmc_status mlmc_run(mlmc_ctx* ctx, const mlmc_model* model, const mlmc_payoff* 
     init.max_iterations = h->max_iterations;
     init.pad = 0;
     // When the spread groups are known to hold zeros, the per-level form
-    // lets its first update build the state and the device-planned form its
-    // first sampler launch (one launch fewer on the pilot's path); otherwise
-    // a kernel clears both first (in the device-planned form, its start
-    // kernel).  Until this run ends normally the groups are not known to be
-    // clear.
-    const bool clean = ctx->drv_clean;
-    const bool fused_init = clean && !o.persistent;
+    // lets its first update build the state (one launch fewer on the pilot's
+    // path), and the device-planned form skips its start kernel if the last
+    // call, a device-planned run, left the next run's start prepared;
+    // otherwise a kernel clears both first (in the device-planned form, its
+    // start kernel).  Until this run ends normally neither is known.
+    const bool fused_init = ctx->drv_clean && !o.persistent;
+    const bool prepared = ctx->drv_clean && ctx->drv_pilot_ready;
     ctx->drv_clean = false;
+    ctx->drv_pilot_ready = false;
     if (!fused_init && !o.persistent) {
         hipLaunchKernelGGL(driver_init_kernel, dim3(1), dim3(256), 0, ctx->stream, d,
                            ctx->d_drv_spread, init);
         MLMC_HIP(ctx, hipGetLastError());
     }
     if (o.persistent) {
-        st = run_persistent(ctx, *model, *payoff, o, d, h, init, clean);
+        st = run_persistent(ctx, *model, *payoff, o, d, h, init, prepared);
         if (st) return st;
     } else {
         for (int it = 0;; ++it) {

@@ -64,8 +64,9 @@ __global__ __launch_bounds__(256) void driver_start_kernel(DriverState* st, Leve
 // groups past the sampled levels hold zeros), the descriptor's plan fields
 // and the state's level count and done flag; the stores come last.  A
 // finished state has no outstanding samples: the plan its finishing update
-// wrote is empty, so a sampler launched after it does nothing, and an
-// update launched after it returns once it has summed the groups.
+// wrote is empty, so a sampler launched after it does nothing, and the
+// update launched after it (the host queues exactly one iteration past the
+// last) prepares the next run's start instead.
 __global__ __launch_bounds__(512) void driver_update_plan_kernel(DriverState* st, DriverState* mirror,
                                                                  LevelAcc* spread, const BatchDesc* d)
 {
@@ -97,7 +98,18 @@ __global__ __launch_bounds__(512) void driver_update_plan_kernel(DriverState* st
     y1 = wave_sum(y1);
     q1 = wave_sum(q1);
     c1 = wave_sum(c1);
-    if (done) return;   // block-uniform
+    if (done) {   // block-uniform
+        // The update queued past a run's finishing one: the state becomes
+        // the fresh state of a next run of this descriptor and the plan its
+        // pilot batch (the start kernel's work; the groups already hold
+        // zeros), so that run can start with its sampler.  The mirror, which
+        // holds the finished run's result, is not touched.
+        init_state(s, d->init);   // ends with a barrier
+        plan_body(pa, s.dN, s.n);
+        if (threadIdx.x < (unsigned)kWords)
+            ((unsigned long long*)st)[threadIdx.x] = ((const unsigned long long*)&s)[threadIdx.x];
+        return;
+    }
     if (lane == 0) {
         g.y[wave] = y0;
         g.y2[wave] = q0;
@@ -173,9 +185,6 @@ struct PersistentBufs {
     BatchDesc last_desc;              // the bytes of the last descriptor upload
     // 0: unknown; 1: the device descriptor holds last_desc
     int desc_state = 0;
-    // the driver runs' dispenser holds zero: set when a driver run ends
-    // normally (its last plan zeroes it), cleared while one runs
-    bool driver_head_zero = true;
 };
 
 static PersistentBufs* bufs_of(mlmc_ctx* ctx);
@@ -241,12 +250,11 @@ void free_persistent(mlmc_ctx* ctx)
 }
 
 // Fill the host copy of the descriptor (parameters for every slot and level).
-// A driver run passes its state, the fresh state's configuration and its
-// own dispenser (`head`); a batch passes nullptr for both and the batch
-// dispenser.
+// A driver run passes the fresh state's configuration and its own
+// dispenser (`head`); a batch passes nullptr and the batch dispenser.
 static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const mlmc_payoff* p,
                       int np, int L, int M, uint64_t seed, const double* dN, const double* off,
-                      LevelAcc* acc, unsigned* head, DriverState* st, const DriverInit* init)
+                      LevelAcc* acc, unsigned* head, const DriverInit* init)
 {
     auto* b = bufs_of(ctx);
     const PersistentShape s = persistent_shape(ctx);
@@ -271,17 +279,19 @@ static void fill_desc(mlmc_ctx* ctx, BatchDesc* h, const mlmc_model& m, const ml
     h->split_ok = m.kind == MLMC_GBM && !m.antithetic;
     h->num_cu = ctx->num_cu;
     h->block = (unsigned)s.block;
-    h->st = st;
     if (init) h->init = *init;
 }
 
 // Copy the host descriptor to the device unless the last upload from this
 // context carried the same bytes (repeated runs of one problem skip it: a
 // driver run passes its seed with each launch, not in the descriptor).
-static mlmc_status upload_desc(mlmc_ctx* ctx, PersistentBufs* b)
+// *uploaded (if given) tells which.
+static mlmc_status upload_desc(mlmc_ctx* ctx, PersistentBufs* b, bool* uploaded = nullptr)
 {
+    if (uploaded) *uploaded = false;
     if (b->desc_state == 1 && std::memcmp(&b->last_desc, b->h_desc, sizeof(BatchDesc)) == 0)
         return MLMC_OK;
+    if (uploaded) *uploaded = true;
     b->desc_state = 0;
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
                                  ctx->stream));
@@ -330,7 +340,7 @@ static mlmc_status capture(mlmc_ctx* ctx, int model, int M, int payoff, hipGraph
 // block, as plain launches on the context's stream.
 mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff& p,
                            const mlmc_run_opts& o, DriverState* d_st, DriverState* h_st,
-                           const DriverInit& init, bool clean)
+                           const DriverInit& init, bool prepared)
 {
     if (o.precision != 32) return fail(ctx, MLMC_EINVAL, "the persistent form runs fp32 paths");
     if (o.cv) {
@@ -351,7 +361,7 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     // descriptor's bytes and upload it once.  Driver runs have a dispenser
     // of their own, which their plans leave at zero.
     fill_desc(ctx, b->h_desc, m, &p, 1, o.L_max, o.M, 0, d_st->dN, d_st->n, ctx->d_drv_spread,
-              b->d_counters + 1, d_st, &init);
+              b->d_counters + 1, &init);
     size_t lds = 0;
     if (o.cv) {
         int max_nf = 1;
@@ -361,7 +371,8 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
         if (e != hipSuccess) return hip_fail(ctx, e, "control-variate table");
         b->h_desc->cv_levels = o.cv_levels;
     }
-    st = upload_desc(ctx, b);
+    bool uploaded = false;
+    st = upload_desc(ctx, b, &uploaded);
     if (st) return st;
     const PersistentShape s = persistent_shape(ctx);
     const auto sampler = pick_persistent(sampler_variant(m), o.M, s.ppt, p.kind, o.cv != nullptr);
@@ -369,13 +380,12 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
     const dim3 grid(ctx->num_cu * s.blocks_per_cu), block(s.block);
     const BatchDesc* d = b->d_desc;
     DriverState* mirror = (DriverState*)ctx->h_drv_dev;
-    // When the context's last driver run ended normally its updates left the
-    // spread groups and the driver dispenser at zero: the first sampler
-    // launch then plans the pilot batch itself and builds the fresh state
-    // (kPilot), and the start kernel is not needed.
-    const bool fused = clean && b->driver_head_zero;
-    b->driver_head_zero = false;
-    if (!fused) {
+    // prepared: the context's last call was a device-planned run that ended
+    // normally, so the update queued past its end has built a fresh state
+    // and planned its pilot batch, and its updates left the spread groups at
+    // zero; if the descriptor is that run's, this run starts with its
+    // sampler.  Otherwise the start kernel comes first.
+    if (!(prepared && !uploaded)) {
         hipLaunchKernelGGL(driver_start_kernel, dim3(1), dim3(256), 0, ctx->stream, d_st,
                            ctx->d_drv_spread, init, d);
         MLMC_HIP(ctx, hipGetLastError());
@@ -395,7 +405,7 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
             hipEvent_t t0, t1;
             timed_kernel(ctx, 16, 0.0, 0.0, &t0, &t1);
             if (first_tix < 0 && t0) first_tix = (int)ctx->pending.size() - 1;
-            const unsigned flags = kSeedArg | (it == 0 && k == 0 && fused ? kPilot : 0u);
+            const unsigned flags = kSeedArg;
             if (t0) hipExtLaunchKernelGGL(sampler, grid, block, lds, ctx->stream, t0, t1, 0, d, o.seed, flags);
             else hipLaunchKernelGGL(sampler, grid, block, lds, ctx->stream, d, o.seed, flags);
             hipError_t e = hipGetLastError();
@@ -418,7 +428,8 @@ mlmc_status run_persistent(mlmc_ctx* ctx, const mlmc_model& m, const mlmc_payoff
         // seen done is complete; later updates leave it as it is
         if (mirror_done(h_st)) break;
     }
-    b->driver_head_zero = true;   // the finishing update's plan zeroed it
+    // the update queued past the last one prepares the next run's start
+    ctx->drv_pilot_ready = true;
     // the iteration past the last update may still run: the result is read
     // from the mirror; stamped launches are read once finished (harvest_ready
     // now, the rest by a later harvest), the run does not wait for them
@@ -504,8 +515,10 @@ mlmc_status mlmc_levels_batch(mlmc_ctx* ctx, const mlmc_model* model, const mlmc
             b->h_req[kMaxSlots * kMaxLevels + k * kMaxLevels + l] =
                 offsets ? (double)offsets[k * (L + 1) + l] : 0.0;
         }
+    // a batch rewrites the plan table: a driver run's prepared start is gone
+    ctx->drv_pilot_ready = false;
     fill_desc(ctx, b->h_desc, *model, payoffs, npayoffs, L, M, seed, b->d_req,
-              b->d_req + kMaxSlots * kMaxLevels, b->d_acc, b->d_counters, nullptr, nullptr);
+              b->d_req + kMaxSlots * kMaxLevels, b->d_acc, b->d_counters, nullptr);
     MLMC_HIP(ctx, hipMemcpyAsync(b->d_req, b->h_req, sizeof(double) * 2 * kMaxSlots * kMaxLevels,
                                  hipMemcpyHostToDevice, ctx->stream));
     st = upload_desc(ctx, b);

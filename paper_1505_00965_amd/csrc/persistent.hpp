@@ -6,7 +6,6 @@
 
 #include "cv_tab.hpp"
 #include "driver.hpp"
-#include "driver_dev.hpp"
 #include "level.hpp"
 #include "sampler_impl.hpp"
 
@@ -66,9 +65,8 @@ struct BatchDesc {
     TableSpec cv_spec;
     const float* cv_phi0;
     int cv_levels;
-    // a driver run: its state and the configuration of a fresh one (the
-    // pilot launch builds the state when the run has no start kernel)
-    DriverState* st;
+    // a driver run: the configuration of a fresh state (the update that
+    // finds a run finished builds the next run's from it)
     DriverInit init;
 };
 
@@ -373,17 +371,11 @@ __device__ __forceinline__ WorkItem plan_item(const PlanTable& t, unsigned it)
 
 // Launch flags of the sampler.
 constexpr unsigned kSeedArg = 1;   // the seed is the launch's argument (else the descriptor's)
-constexpr unsigned kPilot = 2;     // a driver run's first launch, planned by every block itself
 
 // Block b takes item b first; later items come from the dispenser until
 // none are left, so a launch with no more items than blocks (an empty one
 // included) makes no atomics on it.  Each item ends with a block reduction
-// into its (payoff, level) spread group.  The plan comes from the
-// descriptor's table, or with kPilot from the first wave of every block:
-// the pilot batch of a driver run (n_pilot samples on levels 0..L_min from
-// index 0, the start kernel's plan), while block 0 builds the fresh state;
-// the run then needs no start kernel (its spread groups and the dispenser
-// hold zeros: the caller knows the context's last run ended normally).
+// into its (payoff, level) spread group.
 template <int MODEL, int M, int PPT, int PAYOFF, bool CV>
 __device__ __forceinline__ void sample_items(const BatchDesc* d, float* s_tab, uint64_t seed_arg,
                                              unsigned flags)
@@ -391,20 +383,7 @@ __device__ __forceinline__ void sample_items(const BatchDesc* d, float* s_tab, u
     __shared__ unsigned s_item;
     // the plan in LDS: each item is decoded by a short search over its pairs
     __shared__ PlanTable s_plan;
-    if (flags & kPilot) {   // launch-uniform
-        __shared__ double s_req[2][kMaxLevels];   // outstanding samples, first index
-        if (threadIdx.x < kMaxLevels) {
-            s_req[0][threadIdx.x] = (int)threadIdx.x <= d->init.L_min ? d->init.n_pilot : 0.0;
-            s_req[1][threadIdx.x] = 0.0;
-        }
-        __syncthreads();
-        PlanArgs pa = plan_args(d);
-        pa.plan = &s_plan;
-        pa.head = nullptr;
-        plan_body(pa, s_req[0], s_req[1]);
-        if (blockIdx.x == 0) init_state(*d->st, d->init);   // block-uniform; ends with a barrier
-        __syncthreads();
-    } else {
+    {
         const unsigned long long* src = (const unsigned long long*)d->plan;
         unsigned long long* dst = (unsigned long long*)&s_plan;
         for (int i = threadIdx.x; i < (int)(sizeof(PlanTable) / 8); i += blockDim.x) dst[i] = src[i];

@@ -183,6 +183,28 @@ def test_graph_runs_between_batches_and_shape_changes(gctx):
             assert close(batch[k][l]["sum_y"], batch2[k][l]["sum_y"], 1e-10)
 
 
+def test_planned_run_after_planned_run_starts_like_a_fresh_start(gctx):
+    """A device-planned run that follows one of the same problem starts with
+    its sampler (the update queued past the last one built the fresh state
+    and planned the pilot); it must give what a run through the start kernel
+    gives: for another seed, after a per-level run (no prepared start), after
+    a run of another problem (another descriptor), and prepared again."""
+    gm, gp = mlmc.model(**W.GBM_MODEL), mlmc.payoff(**W.CALL)
+    kw = dict(M=4, persistent=1)
+    gctx.mlmc_run(gm, gp, 0.02, seed=1, **kw)
+    prepared = gctx.mlmc_run(gm, gp, 0.02, seed=2, **kw)
+    gctx.mlmc_run(gm, gp, 0.02, M=4, seed=1, persistent=0)
+    started = gctx.mlmc_run(gm, gp, 0.02, seed=2, **kw)
+    other = gctx.mlmc_run(gm, gp, 0.05, seed=3, **kw)
+    after_other = gctx.mlmc_run(gm, gp, 0.02, seed=2, **kw)
+    again = gctx.mlmc_run(gm, gp, 0.02, seed=2, **kw)
+    assert other["L"] <= prepared["L"]
+    for r in (started, after_other, again):
+        assert r["N"] == prepared["N"] and r["L"] == prepared["L"]
+        assert r["iterations"] == prepared["iterations"]
+        assert close(r["estimate"], prepared["estimate"], 1e-10)
+
+
 def test_batch_bad_args(gctx):
     gm = mlmc.model(**W.GBM_MODEL)
     with pytest.raises(mlmc.MLMCError):
