@@ -308,7 +308,12 @@ typedef struct {
                             all-levels sampler and one of a block that
                             absorbs the batch and plans the next; the host
                             enqueues each iteration before the previous
-                            update is read (the device plans every batch)  */
+                            update is read (the device plans every batch),
+                            and the one iteration queued past the last
+                            prepares the start of a next run of the same
+                            problem on this context (which then needs no
+                            start kernel); the call returns before that
+                            iteration has run                              */
     double alpha, beta;  /* assumed weak and variance rates (<= 0: 1 and 1) */
     const mlmc_cv* cv;   /* NULL: plain MLMC.  Needs precision 32, Euler
                             paths without the twin and a plain payoff; with
