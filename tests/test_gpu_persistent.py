@@ -203,6 +203,17 @@ def test_planned_run_after_planned_run_starts_like_a_fresh_start(gctx):
         assert r["N"] == prepared["N"] and r["L"] == prepared["L"]
         assert r["iterations"] == prepared["iterations"]
         assert close(r["estimate"], prepared["estimate"], 1e-10)
+    # runs that finish at their first update (the pilot meets the target)
+    # and runs stopped at L_max without convergence prepare the next start too
+    for eps, extra in ((0.8, {}), (0.002, dict(L_max=2, allow_notconv=True))):
+        first = gctx.mlmc_run(gm, gp, eps, seed=5, **kw, **extra)
+        prepared = gctx.mlmc_run(gm, gp, eps, seed=6, **kw, **extra)
+        gctx.mlmc_levels_batch(gm, [gp], 4, 1, [[1000, 100]], seed=1)
+        started = gctx.mlmc_run(gm, gp, eps, seed=6, **kw, **extra)
+        assert prepared["N"] == started["N"] and prepared["iterations"] == started["iterations"]
+        assert close(prepared["estimate"], started["estimate"], 1e-10)
+        if not extra:
+            assert first["iterations"] == 1
 
 
 def test_batch_bad_args(gctx):
